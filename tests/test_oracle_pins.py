@@ -1,0 +1,422 @@
+"""Pins of the CPU oracle against facts fixed outside it (CPU only).
+
+Each test checks the oracle against something other than itself: closed
+forms, invariants, the paper's qualitative claims, an independent numpy
+formulation (vectorised shifts, explicit region enumeration) or the
+real-valued (float64) shadow of Eq. 1 and Eq. 2.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import brute_ref as B
+from paper_2203_02300_amd import synth
+
+Q = 1 << 20
+
+
+def rgb_from_grey(g):
+    return np.repeat(np.asarray(g, np.uint8)[..., None], 3, axis=2)
+
+
+# ----------------------------------------------------------------- grey ---
+
+def test_grey_maps_grey_to_itself():
+    v = np.arange(256, dtype=np.uint8).reshape(16, 16)
+    assert np.array_equal(oracle.grey(rgb_from_grey(v)), v)
+
+
+def test_grey_channel_order():
+    img = np.zeros((1, 3, 3), np.uint8)
+    img[0, 0, 0] = 255
+    img[0, 1, 1] = 255
+    img[0, 2, 2] = 255
+    g = oracle.grey(img)[0]
+    assert g[1] > g[0] > g[2]     # green weighs most, blue least
+
+
+# --------------------------------------------------------------- census ---
+
+def test_census_constant_image_is_zero():
+    Y = np.full((20, 30), 77, np.uint8)
+    assert not oracle.census(Y).any()
+
+
+def test_census_single_bright_pixel():
+    Y = np.zeros((21, 25), np.uint8)
+    Y[10, 12] = 255
+    c = oracle.census(Y)
+    assert int(c[10, 12]) == (1 << 62) - 1
+    c[10, 12] = 0
+    assert not c.any()
+
+
+def test_census_vertical_ramp_sets_the_rows_above():
+    # neighbours in the three rows above are darker: the first 27 bits
+    Y = (np.arange(30)[:, None] * 5 + np.zeros((1, 20))).astype(np.uint8)
+    c = oracle.census(Y)
+    assert int(c[15, 10]) == (1 << 27) - 1
+    assert int(c[0, 10]) == 0                    # clamped rows are equal, not darker
+
+
+def test_census_horizontal_ramp_bit_order():
+    Y = (np.arange(30)[None, :] * 5 + np.zeros((20, 1))).astype(np.uint8)
+    c = oracle.census(Y)
+    want, k = 0, 0
+    for dy in range(-3, 4):
+        for dx in range(-4, 5):
+            if dy == 0 and dx == 0:
+                continue
+            if dx < 0:
+                want |= 1 << k
+            k += 1
+    assert int(c[10, 15]) == want
+    assert int(c[10, 0]) == 0
+    assert int(c[10, 1]) == want                 # clamped columns are still darker
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_census_matches_shifted_copies(seed):
+    rng = np.random.default_rng(seed)
+    Y = rng.integers(0, 256, (17, 23)).astype(np.uint8)
+    Y[3:9, 4:12] = 100                           # ties with the centre
+    assert np.array_equal(oracle.census(Y), B.census_shift(Y))
+    assert np.array_equal(oracle.census(Y, 5, 3), B.census_shift(Y, 5, 3))
+
+
+# ----------------------------------------------------------------- arms ---
+
+def border_arms(H, W, L1):
+    ys, xs = np.mgrid[0:H, 0:W]
+    return np.stack([np.minimum(L1, xs), np.minimum(L1, W - 1 - xs),
+                     np.minimum(L1, ys), np.minimum(L1, H - 1 - ys)], axis=2)
+
+
+def test_arms_constant_image_reach_border_or_L1():
+    img = np.full((45, 50, 3), 90, np.uint8)
+    assert np.array_equal(oracle.arms(img), border_arms(45, 50, 17))
+
+
+def test_arms_vertical_stripes():
+    g = np.zeros((40, 41), np.uint8)
+    g[:, 1::2] = 255
+    a = oracle.arms(rgb_from_grey(g))
+    assert not a[..., :2].any()
+    assert np.array_equal(a[..., 2:], border_arms(40, 41, 17)[..., 2:])
+
+
+def test_arms_measure_distance_to_the_centre_pixel():
+    # a ramp of 5 per column: adjacent pixels always pass (5 < 20), but the
+    # difference to the centre reaches 20 at the fourth step
+    g = (np.arange(40)[None, :] * 5 + np.zeros((30, 1))).astype(np.uint8)
+    a = oracle.arms(rgb_from_grey(g))
+    want = border_arms(30, 40, 3)
+    assert np.array_equal(a[..., :2], want[..., :2])
+    assert np.array_equal(a[..., 2:], border_arms(30, 40, 17)[..., 2:])
+
+
+def test_arms_stop_at_a_step_edge():
+    g = np.full((20, 60), 50, np.uint8)
+    g[:, 30:] = 200
+    a = oracle.arms(rgb_from_grey(g))
+    xs = np.arange(30)
+    assert np.array_equal(a[5, :30, 1], np.minimum(17, 29 - xs))
+    assert np.array_equal(a[5, 30:, 0], np.minimum(17, xs))
+
+
+def test_arms_single_channel_decides():
+    img = np.full((9, 40, 3), 100, np.uint8)
+    img[:, 25:, 2] = 120                         # only blue changes, by exactly tau1
+    a = oracle.arms(img)
+    assert a[4, 10, 1] == 14                     # stops before column 25
+    img[:, 25:, 2] = 119
+    assert oracle.arms(img)[4, 10, 1] == 17
+
+
+@pytest.mark.parametrize("seed,L1,tau", [(0, 17, 20), (1, 17, 20), (2, 5, 7), (3, 30, 40)])
+def test_arms_match_cumulative_product(seed, L1, tau):
+    img = synth.make_patchwork(37, 29, seed, noise=6)
+    assert np.array_equal(oracle.arms(img, L1, tau), B.arms_cumprod(img, L1, tau))
+
+
+# --------------------------------------------------------------- tables ---
+
+def test_alpha_closed_form_values():
+    a, b, ta, tc = oracle.tables()
+    # Eq. 1 with gamma_L = 1 and eps = 0.8 (Sec. 7.2)
+    assert abs(a[0] - 0.713495) < 1e-6
+    assert abs(a[1] - 0.426247) < 1e-6
+    assert abs(a[17] - 0.054631) < 1e-6
+    for L in range(18):
+        assert abs(float(a[L]) - B.alpha_closed(L)) <= 2 ** -24
+        assert abs(float(a[L]) + float(b[L]) - 1.0) <= 2 ** -23
+
+
+def test_alpha_shrinks_as_the_shortest_arm_grows():
+    # Sec. 4.2.1: longer arms (weaker texture) give AD less weight
+    a, b, _, _ = oracle.tables()
+    assert np.all(np.diff(a) < 0) and np.all(np.diff(b) > 0)
+
+
+def test_ad_and_census_tables():
+    _, _, ta, tc = oracle.tables(lam_ad=10.0, lam_c=40.0)
+    assert ta[0] == 0 and tc[0] == 0
+    assert np.all(np.diff(ta.astype(np.float64)) >= 0) and np.all(np.diff(tc) > 0)
+    assert abs(ta[30] - (1 - math.exp(-1.0))) < 1e-7      # s/3 = lambda_ad
+    assert abs(tc[40] - (1 - math.exp(-1.0))) < 1e-7      # h = lambda_census
+
+
+# ----------------------------------------------------------------- cost ---
+
+def small_pair(seed=5, W=40, H=24, d0=3):
+    p = synth.make_shift_pair(W, H, d0, seed, texture="patches")
+    L, R = p["left"], p["right"]
+    return L, R, oracle.census(oracle.grey(L)), oracle.census(oracle.grey(R)), \
+        oracle.arms(L), oracle.arms(R)
+
+
+def test_cost_identical_views_is_zero_at_d0():
+    L, _, cL, _, aL, _ = small_pair()
+    q = oracle.cost_q(0, L, L, cL, cL, aL, 4)
+    assert not q[0].any()
+
+
+def test_cost_partner_outside_is_one():
+    L, R, cL, cR, aL, aR = small_pair()
+    D = 9
+    qL = oracle.cost_q(0, L, R, cL, cR, aL, D)
+    qR = oracle.cost_q(1, L, R, cL, cR, aR, D)
+    W = L.shape[1]
+    for d in range(D):
+        assert np.all(qL[d, :, :d] == Q)
+        assert np.all(qL[d, :, d:] < Q)
+        assert np.all(qR[d, :, W - d:] == Q)
+        assert np.all(qR[d, :, :W - d] < Q)
+
+
+def test_cost_within_fixed_point_bound_of_real_eq1():
+    L, R, cL, cR, aL, aR = small_pair(seed=9)
+    D = 7
+    for ref, arm in ((0, aL), (1, aR)):
+        q = oracle.cost_q(ref, L, R, cL, cR, arm, D)
+        c = B.cost_real(ref, L, R, cL, cR, arm, D)
+        err = np.abs(q * 2.0 ** -20 - c)
+        assert err.max() <= 1.375 * 2 ** -20
+        valid = c < 1.0
+        assert (q[valid] * 2.0 ** -20).max() <= 0.9392
+
+
+def test_cost_uses_reference_shortest_arm():
+    L, R, cL, cR, aL, aR = small_pair(seed=11)
+    q1 = oracle.cost_q(0, L, R, cL, cR, aL, 5)
+    a2 = aL.copy()
+    a2[..., 3] = 0                               # shortest arm becomes 0 everywhere
+    q2 = oracle.cost_q(0, L, R, cL, cR, a2, 5)
+    c2 = B.cost_real(0, L, R, cL, cR, a2, 5)
+    assert np.abs(q2 * 2.0 ** -20 - c2).max() <= 1.375 * 2 ** -20
+    assert not np.array_equal(q1, q2)
+
+
+# ---------------------------------------------------------- aggregation ---
+
+@pytest.mark.parametrize("iters", [1, 2])
+def test_aggregate_matches_region_enumeration(iters):
+    img = synth.make_patchwork(26, 19, 4, noise=4)
+    a = oracle.arms(img)
+    assert a.max() >= 10                         # long arms are exercised
+    rng = np.random.default_rng(7)
+    q = rng.integers(0, Q + 1, (3, 19, 26)).astype(np.int32)
+    assert np.array_equal(oracle.aggregate(q, a, iters), B.aggregate_sets(q, a, iters))
+
+
+def test_aggregate_c1_matches_region_enumeration():
+    p = synth.config_c1()
+    st = oracle.stages(p["left"], p["right"], 16)
+    sel = [0, 5, 15]
+    got = st["aggL"][sel]
+    want = B.aggregate_sets(st["qL"][sel], st["armsL"], 2)
+    assert np.array_equal(got, want)
+
+
+def test_aggregate_constant_volume():
+    img = synth.make_patchwork(40, 30, 2, noise=3)
+    a = oracle.arms(img)
+    q = np.full((2, 30, 40), 12345, np.int32)
+    out = oracle.aggregate(q, a)
+    assert np.all(out == np.float32(12345 * 2.0 ** -20))
+    q[:] = Q - 1                                 # large values: float S2 may round
+    out = oracle.aggregate(q, a).astype(np.float64)
+    assert np.abs(out - (Q - 1) * 2.0 ** -20).max() <= 2.0 ** -23
+
+
+def test_aggregate_zero_arms_is_identity():
+    rng = np.random.default_rng(3)
+    q = rng.integers(0, Q + 1, (3, 12, 15)).astype(np.int32)
+    a = np.zeros((12, 15, 4), np.uint8)
+    out = oracle.aggregate(q, a)
+    assert np.array_equal(out, (q * 2.0 ** -20).astype(np.float32))
+
+
+def test_aggregate_full_arms_is_a_box_mean():
+    H, W = 90, 100
+    img = np.full((H, W, 3), 128, np.uint8)
+    a = oracle.arms(img)
+    rng = np.random.default_rng(1)
+    q = rng.integers(0, Q + 1, (1, H, W)).astype(np.int32)
+    out = oracle.aggregate(q, a)[0]
+    a1 = B.box_mean_int(q[0], 17)                # valid on rows/cols 17..H-18
+    S = np.zeros((a1.shape[0] + 1, a1.shape[1] + 1), np.int64)
+    S[1:, 1:] = a1.cumsum(0).cumsum(1)
+    s2 = S[35:, 35:] - S[:-35, 35:] - S[35:, :-35] + S[:-35, :-35]
+    want = (s2.astype(np.float32) / np.float32(1225)) * np.float32(2.0 ** -20)
+    assert np.array_equal(out[34:H - 34, 34:W - 34], want)
+
+
+def test_aggregate_within_bound_of_real_eq2():
+    L, R, cL, cR, aL, aR = small_pair(seed=13, W=36, H=20)
+    D = 5
+    q = oracle.cost_q(0, L, R, cL, cR, aL, D)
+    agg = oracle.aggregate(q, aL).astype(np.float64)
+    real = B.aggregate_real(B.cost_real(0, L, R, cL, cR, aL, D), aL)
+    bound = 2.0 * 2 ** -20 + 2.0 ** -23 * real
+    assert np.all(np.abs(agg - real) <= bound)
+
+
+# ---------------------------------------------------------- WTA, LR ---
+
+def test_wta_recovers_parabola_vertex():
+    D = 24
+    d0 = np.array([[3.3, 10.5, 17.77], [1.01, 21.49, 12.0]])
+    d = np.arange(D)[:, None, None]
+    vol = (0.01 * (d - d0[None]) ** 2 + 0.1).astype(np.float32)
+    di, delta = oracle.wta(vol)
+    assert np.array_equal(di, np.rint(d0).astype(np.int16))
+    assert np.abs(di + delta.astype(np.float64) - d0).max() < 1e-5
+
+
+def test_wta_ties_pick_smallest_and_edges_have_no_subpixel():
+    vol = np.full((6, 2, 2), 0.5, np.float32)
+    vol[4:, 1, 1] = 0.25
+    vol[5, 1, 0] = 0.1
+    di, delta = oracle.wta(vol)
+    assert di.tolist() == [[0, 0], [5, 4]]
+    assert delta[0, 0] == 0 and delta[1, 0] == 0
+    assert delta[1, 1] == 0.5                    # flat right neighbour: vertex at +0.5
+
+
+@pytest.mark.parametrize("d0", [0, 5, 13])
+def test_pure_shift_recovers_d0_and_passes_lr(d0):
+    W, H, D = 160, 24, 16
+    p = synth.make_shift_pair(W, H, d0, 21 + d0, texture="uniform")
+    st = oracle.stages(p["left"], p["right"], D)
+    lo, hi = d0 + 2 * 17 + 4, W - 1 - 2 * 17 - 4
+    assert np.all(st["dL"][:, lo:hi + 1] == d0)
+    assert np.all(st["aggL"][d0][:, lo:hi + 1] == 0)
+    assert np.all(st["valid"][:, lo:hi + 1] == 1)
+    assert np.all(st["dR"][:, lo - d0:hi + 1 - d0] == d0)
+
+
+def lr_invariant(st, maxdiff=0):
+    dL, dR, valid = st["dL"].astype(int), st["dR"].astype(int), st["valid"]
+    H, W = dL.shape
+    xs = np.arange(W)[None, :].repeat(H, 0)
+    ys = np.arange(H)[:, None].repeat(W, 1)
+    xr = xs - dL
+    ok = xr >= 0
+    want = np.zeros_like(valid)
+    want[ok] = np.abs(dL[ok] - dR[ys[ok], xr[ok]]) <= maxdiff
+    return np.array_equal(valid, want)
+
+
+def test_lr_check_invariant_and_zero_fill_c1():
+    p = synth.config_c1()
+    st = oracle.stages(p["left"], p["right"], 16)
+    assert lr_invariant(st)
+    v = st["valid"].astype(bool)
+    assert np.all(st["disp"][~v] == 0)
+    assert np.array_equal(st["disp"][v], (st["dL"][v] + st["deltaL"][v]).astype(np.float32))
+    d2, v2, dl2, dr2 = oracle.match(p["left"], p["right"], 16)
+    assert np.array_equal(d2, st["disp"]) and np.array_equal(v2, st["valid"])
+
+
+def guaranteed_set(p, arms, cw=9, ch=7):
+    """Pixels whose whole influence region is one non-occluded plane."""
+    gt, occ = p["disp"], p["occluded"]
+    H, W = gt.shape
+    good = np.zeros((H, W), bool)
+    for y in range(H):
+        for x in range(W):
+            pts = set()
+            for (xx, yy) in B.region2(arms, x, y):
+                pts.update(B.region1(arms, xx, yy))
+            ok = True
+            for (xx, yy) in pts:
+                y0, y1 = max(0, yy - ch // 2), min(H, yy + ch // 2 + 1)
+                x0, x1 = max(0, xx - cw // 2), min(W, xx + cw // 2 + 1)
+                if (xx - cw // 2 < 0 or yy - ch // 2 < 0 or yy + ch // 2 >= H
+                        or xx + cw // 2 >= W):
+                    ok = False
+                    break
+                blk_gt, blk_occ = gt[y0:y1, x0:x1], occ[y0:y1, x0:x1]
+                if blk_occ.any() or np.any(blk_gt != gt[y, x]):
+                    ok = False
+                    break
+            good[y, x] = ok
+    return good
+
+
+def test_c1_recovers_ground_truth_on_guaranteed_set():
+    p = synth.config_c1()
+    st = oracle.stages(p["left"], p["right"], 16)
+    g = guaranteed_set(p, st["armsL"])
+    assert g.sum() > 500
+    assert np.all(st["dL"][g] == p["disp"][g].astype(np.int16))
+
+
+# ------------------------------------------------------------ soft path ---
+
+def soft_inputs(seed=31, W=30, H=14, D=8):
+    p = synth.make_slanted_pair(W, H, D, seed, n_planes=2, dmin=1.0, dmax=D - 2.0)
+    L, R = p["left"], p["right"]
+    return L, R, oracle.census(oracle.grey(L)), oracle.census(oracle.grey(R)), oracle.arms(L), D
+
+
+def test_soft_forward_matches_brute_real_valued():
+    L, R, cL, cR, aL, D = soft_inputs()
+    dhat, vol = oracle.soft_forward(L, R, cL, cR, aL, D, lam_c=30.0, T=0.05, want_volume=True)
+    c = B.cost_real(0, L, R, cL, cR, aL, D, lam_c=30.0)
+    real = B.aggregate_real(c, aL)
+    assert np.abs(vol - real).max() < 1e-12
+    assert np.abs(dhat - B.soft_argmin(real, 0.05)).max() < 1e-9
+
+
+def test_soft_small_temperature_is_the_argmin():
+    L, R, cL, cR, aL, D = soft_inputs(seed=32)
+    dhat, vol = oracle.soft_forward(L, R, cL, cR, aL, D, T=1e-4, want_volume=True)
+    srt = np.sort(vol, axis=0)
+    clear = (srt[1] - srt[0]) > 0.01
+    assert clear.sum() > 50
+    assert np.abs(dhat[clear] - vol.argmin(axis=0)[clear]).max() < 1e-9
+
+
+@pytest.mark.parametrize("T", [1.0, 0.02])
+def test_soft_gradient_matches_central_differences(T):
+    L, R, cL, cR, aL, D = soft_inputs(seed=33)
+    rng = np.random.default_rng(0)
+    gd = rng.normal(size=L.shape[:2])
+    theta = np.array([10.0, 30.0, T])
+    g = oracle.soft_grad(L, R, cL, cR, aL, D, gd, lam_ad=theta[0], lam_c=theta[1], T=theta[2])
+
+    def f(th):
+        dh = oracle.soft_forward(L, R, cL, cR, aL, D, lam_ad=th[0], lam_c=th[1], T=th[2])
+        return float((gd * dh).sum())
+
+    for k in range(3):
+        h = 1e-4 * theta[k]
+        tp, tm = theta.copy(), theta.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (f(tp) - f(tm)) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])), (k, fd, g[k])
