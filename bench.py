@@ -1,0 +1,189 @@
+"""Benchmark of the gfx950 adaptive AD-census matcher.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extras]
+
+A step is one pass of the whole plain matcher (census and arms of both views,
+cost and two-stage aggregation of both views, WTA with sub-pixel refinement,
+LR check) over one 1280x720 pair with D = 128, through the one-call entry
+point ``dco_stereo_match``.  Inputs are resident in HBM before timing starts.
+The JSON line carries:
+  value        Mpix*disp/s = W*H*D / seconds per step / 1e6
+  roofline     the dominant kernel (largest share of the step) against its
+               bound, with its duration from HIP events recorded by the
+               library on its own stream over the timed steps
+  cpu_baseline the CPU oracle (single thread) on a bounded sample of the
+               same pair
+  extras       (with --extras, default on) the staged four-call path per
+               stage against the HBM roofline
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+# One CDNA4 compute unit issues one 64-lane VALU instruction per SIMD per
+# 4 cycles (16 lanes per cycle each): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+METRIC = "Mpix·disp/s and ms/frame at 1280x720 D=128 vs oracle; batched & fwd+bwd vs plain"
+STAGES = ("census+arms+counts", "cost+aggregate L", "cost+aggregate R", "wta", "lrcheck")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(L, R, D, rows):
+    """The oracle on the first `rows` rows of the pair (single thread)."""
+    import oracle
+    H, W = L.shape[:2]
+    t0 = time.perf_counter()
+    oracle.match(L[:rows], R[:rows], D)
+    dt = time.perf_counter() - t0
+    units = W * rows * D
+    return dict(value=units / dt / 1e6, unit="Mpix·disp/s", cores=1, kind="oracle",
+                sample=f"rows 0..{rows - 1} of the {W}x{H} D={D} pair ({rows}/{H} of the frame), "
+                       f"whole plain matcher, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=240)
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(pairs would shard across GPUs with no communication); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2203_02300_amd import StereoMatcher, synth
+    from paper_2203_02300_amd._lib import check, lib
+
+    W, H, D = 1280, 720, 128
+    log("bench: generating the 1280x720 D=128 pair (seed 3)")
+    pair = synth.config_c3()
+    L, R = pair["left"], pair["right"]
+    gL = torch.from_numpy(L).cuda()
+    gR = torch.from_numpy(R).cuda()
+    m = StereoMatcher(W, H, D)
+    disp = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    valid = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+    for _ in range(args.warmup):
+        m.match(gL, gR, disp, valid)
+    torch.cuda.synchronize()
+    log(f"bench: warmup done, timing {args.steps} steps")
+
+    check(lib().dco_stereo_profile(m._h, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        m.match(gL, gR, disp, valid)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    check(lib().dco_stereo_profile(m._h, 0))
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    stage_ms = (C.c_float * len(STAGES))()
+    calls = C.c_int()
+    check(lib().dco_stereo_stage_times(m._h, stage_ms, len(STAGES), C.byref(calls)))
+    per_call = [stage_ms[i] / calls.value for i in range(len(STAGES))]
+    log("bench: stage ms " + ", ".join(f"{n}={t:.4f}" for n, t in zip(STAGES, per_call)))
+
+    units = W * H * D
+    value = units / (ms_step / 1e3) / 1e6
+    P, V = W * H, W * H * D
+    # dominant kernel: cost + aggregation of one view (stages 1 and 2)
+    agg_ms = (per_call[1] + per_call[2]) / 2
+    # algorithmic VALU work of one cost+aggregation launch: ~14 ops for the
+    # raw cost and ~26 for the four range sums and two divisions per (p, d)
+    ops_per_unit = 40
+    achieved = ops_per_unit * V / (agg_ms / 1e3) / 1e12
+    roofline = dict(bound="alu", achieved=round(achieved, 2), peak=round(VALU_PEAK_TOPS, 2),
+                    unit="TOP/s", frac=round(achieved / VALU_PEAK_TOPS, 4), traffic=None,
+                    kernel="k_agg_stream<2,fused>", kernel_ms=round(agg_ms, 4),
+                    ops_per_pd=ops_per_unit)
+
+    extras = {"stage_ms": {n: round(t, 4) for n, t in zip(STAGES, per_call)}}
+    if not args.no_extras:
+        extras["staged"] = staged_extras(m, gL, gR, args.steps)
+    del m
+    torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"bench: CPU oracle on {args.cpu_rows} rows")
+        cpu = cpu_baseline(L, R, D, args.cpu_rows)
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "Mpix·disp/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32 (Q20 fixed point) + f32",
+        "data": "synthetic",
+        "config": {"workload": "plain matcher, one 1280x720 RGB pair, D=128, 10 slanted planes "
+                               "+ 2 boxes, noise 2, right gain 0.9..1.1 (seed 3)",
+                   "W": W, "H": H, "D": D, "entry": "dco_stereo_match"},
+        "roofline": roofline, "cpu_baseline": cpu, "extras": extras,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def staged_extras(m, gL, gR, steps):
+    """Per-stage times of the four-call path, against the HBM roofline."""
+    import torch
+    W, H, D = m.W, m.H, m.D
+    P, V = W * H, W * H * D
+    cL, aL = m.census(gL)
+    cR, aR = m.census(gR)
+    costL = m.cost_volume(0, gL, gR, cL, cR, aL)
+    costR = m.cost_volume(1, gL, gR, cL, cR, aR)
+    aggL = m.aggregate(costL, aL)
+    aggR = m.aggregate(costR, aR)
+    torch.cuda.synchronize()
+    n = max(3, steps // 5)
+    # algorithmic bytes per call (each stage reads its inputs and writes its outputs once)
+    stages = {
+        "census": (lambda: (m.census(gL), m.census(gR)), 2 * (3 * P + 8 * P + 4 * P)),
+        "cost_volume": (lambda: (m.cost_volume(0, gL, gR, cL, cR, aL, costL),
+                                 m.cost_volume(1, gL, gR, cL, cR, aR, costR)),
+                        2 * (4 * V + 3 * P * 2 + 8 * P * 2 + 4 * P)),
+        "aggregate": (lambda: (m.aggregate(costL, aL, aggL), m.aggregate(costR, aR, aggR)),
+                      2 * (8 * V + 4 * P)),
+        "wta_lrcheck": (lambda: m.wta_lrcheck(aggL, aggR), 8 * V + 9 * P),
+    }
+    res = {}
+    total = 0.0
+    for name, (fn, nbytes) in stages.items():
+        fn()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(n):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / n
+        total += ms
+        gbs = nbytes / (ms / 1e3) / 1e9
+        res[name] = dict(ms=round(ms, 4), GBs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4),
+                         bytes=nbytes)
+    allbytes = sum(b for _, b in stages.values())
+    res["total"] = dict(ms=round(total, 4), GBs=round(allbytes / (total / 1e3) / 1e9, 1),
+                        hbm_frac=round(allbytes / (total / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                        Mpix_disp_s=round(V / (total / 1e3) / 1e6, 1))
+    del costL, costR, aggL, aggR
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,214 @@
+/*
+ * dco_stereo.h -- C ABI of the MI355X (gfx950) two-stage adaptive AD-census
+ * stereo matcher: the sparse-disparity front end of the depth contour
+ * occlusion method (paper Sec. 4).
+ *
+ * Problem statement (Sec. 3, Sec. 4): a rectified stereo pair (epipolar lines
+ * are image rows) goes in, with the left view as the reference; a sparse
+ * disparity map comes out, 0 marking a missing value (the convention of
+ * Eq. 14).  The steps are the census transform and cross-support arms
+ * (Sec. 4.1), the adaptive AD-census cost (Eq. 1), aggregation over the
+ * adaptive region (Eq. 2, applied as two stages), winner-take-all (Eq. 3)
+ * with parabola sub-pixel refinement, and a left-right consistency check.
+ *
+ * Conventions shared by every entry point
+ *  - Memory: every buffer argument is a DEVICE pointer owned by the caller,
+ *    contiguous, naturally aligned (uint64 to 8 bytes, float to 4).  Images
+ *    are H x W x 3 uint8, row-major, RGB interleaved.  Per-pixel maps are
+ *    H x W row-major.  Arms are H x W x 4 uint8 in the order (left, right,
+ *    up, down).  Volumes are D x H x W float (one H x W slice per disparity,
+ *    d = 0 .. D-1).  The library owns only its handle, its lookup tables and
+ *    internal scratch.
+ *  - Streams: every call after create is asynchronous on the handle's
+ *    stream (a hipStream_t passed as void*; NULL = the default stream).
+ *    Nothing synchronises except create, destroy and the batch autotuner.
+ *  - Errors: every call returns a dco_status.  Argument errors (null
+ *    pointers, sizes out of range) are detected before anything is launched
+ *    and return DCO_ERR_ARG or DCO_ERR_SHAPE; HIP failures return
+ *    DCO_ERR_HIP; allocation failures DCO_ERR_OOM.  dco_last_error() gives a
+ *    thread-local message for the last failure.  Nothing throws across the ABI.
+ *  - Determinism: equal inputs give bit-identical outputs, whatever the
+ *    launch configuration (all sums are integer; see dco_aggregate).
+ */
+#ifndef DCO_STEREO_H
+#define DCO_STEREO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dco_stereo dco_stereo; /* opaque matcher handle */
+typedef struct dco_batch dco_batch;   /* opaque batched-matcher handle */
+
+typedef enum {
+    DCO_OK = 0,
+    DCO_ERR_ARG = -1,   /* null pointer or parameter out of range */
+    DCO_ERR_SHAPE = -2, /* W, H or D out of range */
+    DCO_ERR_HIP = -3,   /* a HIP runtime call failed */
+    DCO_ERR_OOM = -4,   /* device allocation failed */
+    DCO_ERR_STATE = -5  /* handle not usable for this call */
+} dco_status;
+
+/* Matcher parameters.  Defaults (dco_default_params): the stereo constants
+ * of Sec. 7.2 (lambda_AD = 10, lambda_census = 40, gamma_L = 1, eps = 0.8)
+ * and, where the paper gives none, census 9 x 7, L1 = 17, tau1 = 20,
+ * two-stage aggregation, LR tolerance 0, sub-pixel on. */
+typedef struct {
+    int census_w, census_h;   /* odd, census_w * census_h - 1 <= 64 (default 9, 7) */
+    int arm_L1, arm_tau1;     /* 0 <= L1 <= 17; 1 <= tau1 <= 256 (default 17, 20) */
+    float lambda_ad;          /* > 0 (Eq. 1) */
+    float lambda_census;      /* > 0 (Eq. 1) */
+    float gamma_L, eps;       /* > 0 (Eq. 1, weight alpha) */
+    int agg_iters;            /* 2 = two-stage aggregation; 1 = Eq. 2 once */
+    int lr_max_diff;          /* >= 0: LR tolerance in whole disparities */
+    int subpixel;             /* 1 = parabola refinement, 0 = integer output */
+} dco_params;
+
+/* Fill *out with the defaults above.  DCO_ERR_ARG if out is NULL. */
+dco_status dco_default_params(dco_params* out);
+
+/* Create a matcher for W x H images and disparities d = 0 .. D-1.
+ * Requires 1 <= D < W, W >= census_w, H >= census_h, W, H <= 16384 and
+ * W * H * D < 2^31.  Copies *p (NULL = defaults), builds the Eq. 1 tables on
+ * the host in double precision and uploads them, and allocates the scratch
+ * that dco_stereo_match needs.  Synchronous.  On failure *out is NULL. */
+dco_status dco_stereo_create(dco_stereo** out, int W, int H, int D, const dco_params* p,
+                             void* stream);
+
+/* Free the handle and its scratch (synchronises its stream).  NULL is a no-op. */
+void dco_stereo_destroy(dco_stereo* h);
+
+/* Make later calls enqueue on `stream` (a hipStream_t). */
+dco_status dco_stereo_set_stream(dco_stereo* h, void* stream);
+
+/* Census codes and cross arms of one image (Sec. 4.1; C_census of Eq. 1).
+ *   grey:   Y = (77 R + 150 G + 29 B + 128) >> 8
+ *   census: bit k of census[p] is Y(q_k) < Y(p) for the k-th neighbour q_k
+ *           of the census_w x census_h window, enumerated row-major (top row
+ *           first) without the centre, coordinates clamped to the image
+ *   arms:   for each direction, the largest k <= L1 such that every step
+ *           j = 1..k stays inside the image and the largest per-channel
+ *           absolute difference to p is below tau1
+ * rgb: H x W x 3 uint8; census: H x W uint64 (out); arms: H x W x 4 uint8 (out). */
+dco_status dco_census(dco_stereo* h, const uint8_t* rgb, uint64_t* census, uint8_t* arms);
+
+/* Raw AD-census cost volume of one reference view (Eq. 1), fixed point.
+ * ref = 0: reference = left view, partner pixel (x - d, y) in the right view;
+ * ref = 1: reference = right view, partner pixel (x + d, y) in the left view.
+ *   s = sum over RGB of |I_ref - I_partner|     (C_AD = s / 3)
+ *   h = popcount(census_ref ^ census_partner)
+ *   L = min of the four arms of the reference pixel (arms_ref)
+ *   q = rint(alpha_L * TA[s] * 2^20) + rint(beta_L * TC[h] * 2^20)
+ * with float tables alpha_L = 1 - exp(-gamma_L / (L + eps)), beta_L =
+ * exp(-gamma_L / (L + eps)), TA[s] = 1 - exp(-s / (3 lambda_AD)), TC[h] =
+ * 1 - exp(-h / lambda_census), each rounded once from double, float products,
+ * round-half-even.  A partner outside the image gives q = 2^20.
+ * cost[d][y][x] = q * 2^-20 (D x H x W float, out). */
+dco_status dco_cost_volume(dco_stereo* h, int ref, const uint8_t* rgbL, const uint8_t* rgbR,
+                           const uint64_t* cenL, const uint64_t* cenR, const uint8_t* arms_ref,
+                           float* cost);
+
+/* Aggregation over the reference view's adaptive cross region (Eq. 2).
+ * cost must hold values q * 2^-20 with integer 0 <= q <= 2^20 (as written by
+ * dco_cost_volume); other values give unspecified results.  With agg_iters = 2:
+ *   stage 1: S1 = sum over the horizontal-then-vertical cross region of q,
+ *            N1 = its pixel count, a1 = floor((S1 + floor(N1/2)) / N1)
+ *   stage 2: S2 = sum over the vertical-then-horizontal cross region of a1,
+ *            N2 = its pixel count, agg = ((float)S2 / (float)N2) * 2^-20
+ * With agg_iters = 1: agg = ((float)S1 / (float)N1) * 2^-20.
+ * cost, agg: D x H x W float (agg out, must not alias cost); arms_ref: the
+ * reference view's arms. */
+dco_status dco_aggregate(dco_stereo* h, const float* cost, const uint8_t* arms_ref, float* agg);
+
+/* Winner-take-all (Eq. 3) of both views, sub-pixel refinement of the left
+ * view and the left-right check.
+ *   d* = smallest d minimising agg(p, d)
+ *   delta = (m - p) / (2 ((m - c) + (p - c))) with m, c, p the aggregated
+ *           costs at d*-1, d*, d*+1, clamped to [-0.5, 0.5]; 0 when d* is 0
+ *           or D-1 (or subpixel = 0)
+ *   valid(x, y) = x - dL >= 0 and |dL(x, y) - dR(x - dL, y)| <= lr_max_diff
+ *   disp = dL + delta where valid, else 0
+ * aggL, aggR: D x H x W float; disp: H x W float (out); valid: H x W uint8
+ * (out); dL, dR: H x W int16 (out, optional: NULL to skip). */
+dco_status dco_wta_lrcheck(dco_stereo* h, const float* aggL, const float* aggR, float* disp,
+                           uint8_t* valid, int16_t* dL, int16_t* dR);
+
+/* The whole plain matcher in one call: census and arms of both views, then
+ * cost, aggregation and WTA of both views streamed per disparity with no
+ * cost volume in memory, then the LR check.  Results are bit-identical to
+ * dco_census -> dco_cost_volume -> dco_aggregate -> dco_wta_lrcheck.
+ * rgbL, rgbR: H x W x 3 uint8; disp: H x W float (out); valid: H x W uint8 (out). */
+dco_status dco_stereo_match(dco_stereo* h, const uint8_t* rgbL, const uint8_t* rgbR, float* disp,
+                            uint8_t* valid);
+
+/* Integer disparities of both views from the last dco_stereo_match on this
+ * handle (H x W int16 each, device, out; either may be NULL). */
+dco_status dco_stereo_last_disparities(dco_stereo* h, int16_t* dL, int16_t* dR);
+
+/* Per-stage GPU timing of dco_stereo_match (diagnostics).  While enabled,
+ * every kernel stage of dco_stereo_match is bracketed by HIP events recorded
+ * on the handle's stream (no synchronisation is added).
+ * dco_stereo_profile(h, 1) starts (and clears) the record, (h, 0) stops it.
+ * dco_stereo_stage_times waits for the recorded events and writes, for each
+ * stage s < n, ms[s] = total milliseconds over the recorded calls, and
+ * *calls = the number of recorded calls.  Stages: 0 census + arms + region
+ * counts of both views, 1 cost + aggregation of the left view, 2 the same for
+ * the right view, 3 WTA of both views, 4 LR check.  ms: host array of n floats. */
+#define DCO_NUM_STAGES 5
+dco_status dco_stereo_profile(dco_stereo* h, int enable);
+dco_status dco_stereo_stage_times(dco_stereo* h, float* ms, int n, int* calls);
+
+/* ---- Batched matcher: many pairs of uneven size and disparity range ---- */
+
+/* Create a batched matcher for n pairs of sizes W[i] x H[i], disparity
+ * ranges D[i] (host arrays, each pair within the limits of
+ * dco_stereo_create).  Runs the tile autotuner (or reads its cache file,
+ * named by the environment variable DCO_AUTOTUNE_CACHE when set), builds
+ * the device work list and captures one persistent launch in a HIP graph.
+ * Synchronous. */
+dco_status dco_batch_create(dco_batch** out, int n, const int* W, const int* H, const int* D,
+                            const dco_params* p, void* stream);
+void dco_batch_destroy(dco_batch* b);
+
+/* Match every pair with one graph launch.  L, R, disp, valid: host arrays of
+ * n device pointers (images H x W x 3 uint8; disp H x W float; valid H x W
+ * uint8).  Per-pair results are bit-identical to dco_stereo_match. */
+dco_status dco_batch_match(dco_batch* b, const uint8_t* const* L, const uint8_t* const* R,
+                           float* const* disp, uint8_t* const* valid);
+
+/* Tile shape the autotuner picked for pair i (out: tile width, tile height,
+ * workgroups per CU); host pointers. */
+dco_status dco_batch_tile(const dco_batch* b, int i, int* tile_w, int* tile_h, int* occupancy);
+
+/* ---- Differentiable soft-argmin form (left view) ---- */
+
+/* Forward for B pairs of the handle's size, stacked (L, R: B x H x W x 3).
+ * theta: 3 device floats (lambda_AD, lambda_census, T).  Float costs
+ *   c = alpha_L (1 - exp(-(s/3)/lambda_AD)) + (1 - alpha_L)(1 - exp(-h/lambda_census))
+ * (c = 1 where the partner is outside the image), two normalised region
+ * means as in dco_aggregate but in float with no rounding step, and
+ *   dhat = sum_d d softmax_d(-agg(p, d) / T).
+ * dhat: B x H x W float (out); lse: B x H x W float (out), the log-sum-exp
+ * of -agg/T per pixel, kept for the backward pass. */
+dco_status dco_soft_forward(dco_stereo* h, int B, const uint8_t* L, const uint8_t* R,
+                            const float* theta, float* dhat, float* lse);
+
+/* Backward: given grad_dhat = dLoss/d dhat (B x H x W float), writes
+ * grad_theta[0..2] = dLoss/d(lambda_AD, lambda_census, T) (3 device floats,
+ * overwritten).  Recomputes costs and aggregation; needs the dhat and lse of
+ * the matching forward.  Deterministic. */
+dco_status dco_soft_backward(dco_stereo* h, int B, const uint8_t* L, const uint8_t* R,
+                             const float* theta, const float* dhat, const float* lse,
+                             const float* grad_dhat, float* grad_theta);
+
+/* ---- Diagnostics ---- */
+const char* dco_status_string(dco_status s);
+const char* dco_last_error(void); /* thread-local; "" when none */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCO_STEREO_H */

@@ -1,0 +1,459 @@
+// api.cpp -- host side of the C ABI declared in include/dco_stereo.h:
+// argument validation, the matcher handle, the Eq. 1 lookup tables, scratch
+// memory and the kernel sequence of each entry point.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "dco_internal.h"
+
+static thread_local char g_err[512] = "";
+
+void dco_set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+extern "C" const char* dco_last_error(void) { return g_err; }
+
+extern "C" const char* dco_status_string(dco_status s) {
+    switch (s) {
+        case DCO_OK: return "ok";
+        case DCO_ERR_ARG: return "invalid argument";
+        case DCO_ERR_SHAPE: return "invalid shape";
+        case DCO_ERR_HIP: return "HIP runtime error";
+        case DCO_ERR_OOM: return "out of device memory";
+        case DCO_ERR_STATE: return "invalid handle state";
+    }
+    return "unknown status";
+}
+
+extern "C" dco_status dco_default_params(dco_params* out) {
+    if (!out) {
+        dco_set_error("dco_default_params: out is NULL");
+        return DCO_ERR_ARG;
+    }
+    out->census_w = 9;
+    out->census_h = 7;
+    out->arm_L1 = 17;
+    out->arm_tau1 = 20;
+    out->lambda_ad = 10.0f;
+    out->lambda_census = 40.0f;
+    out->gamma_L = 1.0f;
+    out->eps = 0.8f;
+    out->agg_iters = 2;
+    out->lr_max_diff = 0;
+    out->subpixel = 1;
+    return DCO_OK;
+}
+
+static dco_status need(const void* ptr, const char* what);
+
+static bool pos_finite(float v) { return std::isfinite(v) && v > 0.0f; }
+
+static dco_status check_params(const dco_params& p) {
+    if (p.census_w < 1 || p.census_h < 1 || !(p.census_w & 1) || !(p.census_h & 1) ||
+        p.census_w > 9 || p.census_h > 9 || p.census_w * p.census_h - 1 > 64) {
+        dco_set_error("census window %d x %d: need odd sizes <= 9 with w*h-1 <= 64", p.census_w,
+                      p.census_h);
+        return DCO_ERR_ARG;
+    }
+    if (p.arm_L1 < 0 || p.arm_L1 > kLMax || p.arm_tau1 < 1 || p.arm_tau1 > 256) {
+        dco_set_error("arms: need 0 <= L1 <= %d and 1 <= tau1 <= 256 (got %d, %d)", kLMax,
+                      p.arm_L1, p.arm_tau1);
+        return DCO_ERR_ARG;
+    }
+    if (!pos_finite(p.lambda_ad) || !pos_finite(p.lambda_census) || !pos_finite(p.gamma_L) ||
+        !pos_finite(p.eps)) {
+        dco_set_error("lambda_ad, lambda_census, gamma_L and eps must be finite and > 0");
+        return DCO_ERR_ARG;
+    }
+    if (p.agg_iters != 1 && p.agg_iters != 2) {
+        dco_set_error("agg_iters must be 1 or 2 (got %d)", p.agg_iters);
+        return DCO_ERR_ARG;
+    }
+    if (p.lr_max_diff < 0 || (p.subpixel != 0 && p.subpixel != 1)) {
+        dco_set_error("lr_max_diff must be >= 0 and subpixel 0 or 1");
+        return DCO_ERR_ARG;
+    }
+    return DCO_OK;
+}
+
+static dco_status check_shape(int W, int H, int D, const dco_params& p) {
+    if (W < p.census_w || H < p.census_h || W > 16384 || H > 16384 || D < 1 || D >= W ||
+        D > 32767 || (long long)W * H * D >= (1LL << 31)) {
+        dco_set_error("shape W=%d H=%d D=%d: need 1 <= D < W, W >= census_w, H >= census_h, "
+                      "W, H <= 16384 and W*H*D < 2^31",
+                      W, H, D);
+        return DCO_ERR_SHAPE;
+    }
+    return DCO_OK;
+}
+
+// Eq. 1 tables, evaluated in double and rounded once to float.  The AD and
+// census tables are stored scaled by 2^20 (an exact power-of-two scaling), so
+// a kernel's alpha_L * tabA[s] equals RN(alpha_L * TA[s]) * 2^20.
+static void build_tables(const dco_params& p, std::vector<float>& tabA, std::vector<float>& tabC,
+                         std::vector<float>& alpha, std::vector<float>& beta) {
+    tabA.assign(768, 0.0f);
+    tabC.assign(65, 0.0f);
+    alpha.assign(kLMax + 1, 0.0f);
+    beta.assign(kLMax + 1, 0.0f);
+    const double g = p.gamma_L, e = p.eps, la = p.lambda_ad, lc = p.lambda_census;
+    for (int L = 0; L <= kLMax; ++L) {
+        const double w = std::exp(-g / ((double)L + e));
+        alpha[L] = (float)(1.0 - w);
+        beta[L] = (float)w;
+    }
+    for (int s = 0; s <= 765; ++s)
+        tabA[s] = std::ldexp((float)(-std::expm1(-(double)s / (3.0 * la))), 20);
+    for (int h = 0; h <= 64; ++h) tabC[h] = std::ldexp((float)(-std::expm1(-(double)h / lc)), 20);
+}
+
+template <class T>
+static dco_status dev_alloc(T** p, size_t n) {
+    *p = nullptr;
+    if (n == 0) return DCO_OK;
+    if (getenv("DCO_FAIL_ALLOC")) {
+        dco_set_error("allocation of %zu bytes refused (DCO_FAIL_ALLOC)", n * sizeof(T));
+        return DCO_ERR_OOM;
+    }
+    hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        dco_set_error("hipMalloc(%zu) failed: %s", n * sizeof(T), hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? DCO_ERR_OOM : DCO_ERR_HIP;
+    }
+    return DCO_OK;
+}
+
+static void free_handle_memory(dco_stereo* h) {
+    void* ptrs[] = {h->tabA,       h->tabC,       h->alpha,      h->beta,       h->alpha_soft,
+                    h->s.cen[0],   h->s.cen[1],   h->s.arms[0],  h->s.arms[1],  h->s.div1[0],
+                    h->s.div1[1],  h->s.div2[0],  h->s.div2[1],  h->s.rgbp[0],  h->s.rgbp[1],
+                    h->s.agg[0],   h->s.agg[1],   h->s.dint[0],  h->s.dint[1],  h->s.delta,
+                    h->soft_vol,   h->soft_partials};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+#define DCO_TRY(expr)                      \
+    do {                                   \
+        dco_status _s = (expr);            \
+        if (_s != DCO_OK) return _s;       \
+    } while (0)
+
+static dco_status alloc_scratch(dco_stereo* h) {
+    const size_t P = (size_t)h->W * h->H, V = P * h->D;
+    dco_scratch& s = h->s;
+    for (int v = 0; v < 2; ++v) {
+        DCO_TRY(dev_alloc(&s.cen[v], P));
+        DCO_TRY(dev_alloc(&s.arms[v], P));
+        DCO_TRY(dev_alloc(&s.div1[v], P));
+        DCO_TRY(dev_alloc(&s.div2[v], P));
+        DCO_TRY(dev_alloc(&s.rgbp[v], P));
+        DCO_TRY(dev_alloc(&s.agg[v], V));
+        DCO_TRY(dev_alloc(&s.dint[v], P));
+    }
+    DCO_TRY(dev_alloc(&s.delta, P));
+    h->scratch_ready = true;
+    return DCO_OK;
+}
+
+extern "C" dco_status dco_stereo_create(dco_stereo** out, int W, int H, int D,
+                                        const dco_params* p, void* stream) {
+    if (!out) {
+        dco_set_error("dco_stereo_create: out is NULL");
+        return DCO_ERR_ARG;
+    }
+    *out = nullptr;
+    dco_params prm;
+    if (p)
+        prm = *p;
+    else
+        dco_default_params(&prm);
+    DCO_TRY(check_params(prm));
+    DCO_TRY(check_shape(W, H, D, prm));
+    dco_stereo* h = new (std::nothrow) dco_stereo();
+    if (!h) {
+        dco_set_error("host allocation failed");
+        return DCO_ERR_OOM;
+    }
+    h->W = W;
+    h->H = H;
+    h->D = D;
+    h->p = prm;
+    h->stream = (hipStream_t)stream;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete h;
+        dco_set_error("hipGetDevice failed: no usable GPU");
+        return DCO_ERR_HIP;
+    }
+    std::vector<float> tabA, tabC, alpha, beta;
+    build_tables(prm, tabA, tabC, alpha, beta);
+    dco_status st = DCO_OK;
+    auto fail = [&](dco_status s) {
+        free_handle_memory(h);
+        delete h;
+        return s;
+    };
+    if ((st = dev_alloc(&h->tabA, tabA.size())) != DCO_OK) return fail(st);
+    if ((st = dev_alloc(&h->tabC, tabC.size())) != DCO_OK) return fail(st);
+    if ((st = dev_alloc(&h->alpha, alpha.size())) != DCO_OK) return fail(st);
+    if ((st = dev_alloc(&h->beta, beta.size())) != DCO_OK) return fail(st);
+    struct {
+        float* dst;
+        const std::vector<float>* src;
+    } ups[] = {{h->tabA, &tabA}, {h->tabC, &tabC}, {h->alpha, &alpha}, {h->beta, &beta}};
+    for (auto& u : ups) {
+        hipError_t e = hipMemcpy(u.dst, u.src->data(), u.src->size() * sizeof(float),
+                                 hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            dco_set_error("hipMemcpy of tables failed: %s", hipGetErrorString(e));
+            return fail(DCO_ERR_HIP);
+        }
+    }
+    if ((st = alloc_scratch(h)) != DCO_OK) return fail(st);
+    *out = h;
+    return DCO_OK;
+}
+
+extern "C" void dco_stereo_destroy(dco_stereo* h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    for (hipEvent_t e : h->prof_events) (void)hipEventDestroy(e);
+    free_handle_memory(h);
+    delete h;
+}
+
+// Next free event of the profiling pool (created on demand).
+static dco_status prof_event(dco_stereo* h, hipEvent_t* out) {
+    if (h->prof_used == h->prof_events.size()) {
+        hipEvent_t e;
+        DCO_HIP_CHECK(hipEventCreate(&e));
+        h->prof_events.push_back(e);
+    }
+    *out = h->prof_events[h->prof_used++];
+    return DCO_OK;
+}
+
+static dco_status prof_mark(dco_stereo* h) {
+    if (!h->profiling) return DCO_OK;
+    hipEvent_t e;
+    DCO_TRY(prof_event(h, &e));
+    DCO_HIP_CHECK(hipEventRecord(e, h->stream));
+    return DCO_OK;
+}
+
+extern "C" dco_status dco_stereo_profile(dco_stereo* h, int enable) {
+    DCO_TRY(need(h, "handle"));
+    h->profiling = enable != 0;
+    if (enable) h->prof_used = 0;
+    return DCO_OK;
+}
+
+extern "C" dco_status dco_stereo_stage_times(dco_stereo* h, float* ms, int n, int* calls) {
+    DCO_TRY(need(h, "handle"));
+    DCO_TRY(need(ms, "ms"));
+    const size_t per = 2 * DCO_NUM_STAGES;
+    const size_t ncalls = h->prof_used / per;
+    for (int s = 0; s < n; ++s) ms[s] = 0.0f;
+    for (size_t c = 0; c < ncalls; ++c)
+        for (int s = 0; s < n && s < DCO_NUM_STAGES; ++s) {
+            hipEvent_t a = h->prof_events[c * per + 2 * s], b = h->prof_events[c * per + 2 * s + 1];
+            DCO_HIP_CHECK(hipEventSynchronize(b));
+            float t = 0.0f;
+            DCO_HIP_CHECK(hipEventElapsedTime(&t, a, b));
+            ms[s] += t;
+        }
+    if (calls) *calls = (int)ncalls;
+    return DCO_OK;
+}
+
+extern "C" dco_status dco_stereo_set_stream(dco_stereo* h, void* stream) {
+    if (!h) {
+        dco_set_error("dco_stereo_set_stream: handle is NULL");
+        return DCO_ERR_ARG;
+    }
+    h->stream = (hipStream_t)stream;
+    return DCO_OK;
+}
+
+static dco_status need(const void* ptr, const char* what) {
+    if (!ptr) {
+        dco_set_error("%s is NULL", what);
+        return DCO_ERR_ARG;
+    }
+    return DCO_OK;
+}
+
+static dco_status need_align(const void* ptr, size_t a, const char* what) {
+    if (((uintptr_t)ptr) % a) {
+        dco_set_error("%s must be %zu-byte aligned", what, a);
+        return DCO_ERR_ARG;
+    }
+    return DCO_OK;
+}
+
+extern "C" dco_status dco_census(dco_stereo* h, const uint8_t* rgb, uint64_t* census,
+                                 uint8_t* arms) {
+    DCO_TRY(need(h, "handle"));
+    DCO_TRY(need(rgb, "rgb"));
+    DCO_TRY(need(census, "census"));
+    DCO_TRY(need(arms, "arms"));
+    DCO_TRY(need_align(census, 8, "census"));
+    DCO_TRY(need_align(arms, 4, "arms"));
+    DCO_HIP_CHECK(launch_census_arms(rgb, h->W, h->H, h->p.census_w, h->p.census_h, h->p.arm_L1,
+                                     h->p.arm_tau1, census, (uint32_t*)arms, nullptr, h->stream));
+    return DCO_OK;
+}
+
+extern "C" dco_status dco_cost_volume(dco_stereo* h, int ref, const uint8_t* rgbL,
+                                      const uint8_t* rgbR, const uint64_t* cenL,
+                                      const uint64_t* cenR, const uint8_t* arms_ref,
+                                      float* cost) {
+    DCO_TRY(need(h, "handle"));
+    if (ref != 0 && ref != 1) {
+        dco_set_error("ref must be 0 (left) or 1 (right), got %d", ref);
+        return DCO_ERR_ARG;
+    }
+    DCO_TRY(need(rgbL, "rgbL"));
+    DCO_TRY(need(rgbR, "rgbR"));
+    DCO_TRY(need(cenL, "cenL"));
+    DCO_TRY(need(cenR, "cenR"));
+    DCO_TRY(need(arms_ref, "arms_ref"));
+    DCO_TRY(need(cost, "cost"));
+    DCO_TRY(need_align(cenL, 8, "cenL"));
+    DCO_TRY(need_align(cenR, 8, "cenR"));
+    DCO_TRY(need_align(arms_ref, 4, "arms_ref"));
+    DCO_TRY(need_align(cost, 4, "cost"));
+    DCO_HIP_CHECK(launch_cost(ref, rgbL, rgbR, cenL, cenR, (const uint32_t*)arms_ref, h->W, h->H,
+                              h->D, h->tabA, h->tabC, h->alpha, h->beta, h->p.arm_L1, cost,
+                              h->stream));
+    return DCO_OK;
+}
+
+extern "C" dco_status dco_aggregate(dco_stereo* h, const float* cost, const uint8_t* arms_ref,
+                                    float* agg) {
+    DCO_TRY(need(h, "handle"));
+    DCO_TRY(need(cost, "cost"));
+    DCO_TRY(need(arms_ref, "arms_ref"));
+    DCO_TRY(need(agg, "agg"));
+    DCO_TRY(need_align(arms_ref, 4, "arms_ref"));
+    DCO_TRY(need_align(cost, 4, "cost"));
+    DCO_TRY(need_align(agg, 4, "agg"));
+    if ((const void*)cost == (const void*)agg) {
+        dco_set_error("dco_aggregate: agg must not alias cost");
+        return DCO_ERR_ARG;
+    }
+    const uint32_t* arms = (const uint32_t*)arms_ref;
+    DCO_HIP_CHECK(launch_geometry(arms, h->W, h->H, h->p.agg_iters, h->s.div1[0], h->s.div2[0],
+                                  h->stream));
+    DCO_HIP_CHECK(launch_aggregate(cost, arms, h->s.div1[0], h->s.div2[0], h->W, h->H, h->D,
+                                   h->p.agg_iters, agg, h->stream));
+    return DCO_OK;
+}
+
+extern "C" dco_status dco_wta_lrcheck(dco_stereo* h, const float* aggL, const float* aggR,
+                                      float* disp, uint8_t* valid, int16_t* dL, int16_t* dR) {
+    DCO_TRY(need(h, "handle"));
+    DCO_TRY(need(aggL, "aggL"));
+    DCO_TRY(need(aggR, "aggR"));
+    DCO_TRY(need(disp, "disp"));
+    DCO_TRY(need(valid, "valid"));
+    int16_t* oL = dL ? dL : h->s.dint[0];
+    int16_t* oR = dR ? dR : h->s.dint[1];
+    DCO_HIP_CHECK(launch_wta2(aggL, aggR, h->W, h->H, h->D, h->p.subpixel, oL, h->s.delta, oR,
+                              h->stream));
+    DCO_HIP_CHECK(launch_lrcheck(oL, h->s.delta, oR, h->W, h->H, h->p.lr_max_diff, disp, valid,
+                                 h->stream));
+    return DCO_OK;
+}
+
+extern "C" dco_status dco_stereo_match(dco_stereo* h, const uint8_t* rgbL, const uint8_t* rgbR,
+                                       float* disp, uint8_t* valid) {
+    DCO_TRY(need(h, "handle"));
+    DCO_TRY(need(rgbL, "rgbL"));
+    DCO_TRY(need(rgbR, "rgbR"));
+    DCO_TRY(need(disp, "disp"));
+    DCO_TRY(need(valid, "valid"));
+    if (!h->scratch_ready) {
+        dco_set_error("handle has no scratch");
+        return DCO_ERR_STATE;
+    }
+    dco_scratch& s = h->s;
+    const dco_params& p = h->p;
+    const uint8_t* img[2] = {rgbL, rgbR};
+    DCO_TRY(prof_mark(h));
+    for (int v = 0; v < 2; ++v) {
+        DCO_HIP_CHECK(launch_census_arms(img[v], h->W, h->H, p.census_w, p.census_h, p.arm_L1,
+                                         p.arm_tau1, s.cen[v], s.arms[v], s.rgbp[v], h->stream));
+        DCO_HIP_CHECK(launch_geometry(s.arms[v], h->W, h->H, p.agg_iters, s.div1[v], s.div2[v],
+                                      h->stream));
+    }
+    DCO_TRY(prof_mark(h));
+    for (int v = 0; v < 2; ++v) {
+        DCO_TRY(prof_mark(h));
+        DCO_HIP_CHECK(launch_cost_aggregate(v, s.rgbp[0], s.rgbp[1], s.cen[0], s.cen[1],
+                                            s.arms[v], s.div1[v], s.div2[v], h->W, h->H, h->D,
+                                            p.agg_iters, h->tabA, h->tabC, h->alpha, h->beta,
+                                            p.arm_L1, s.agg[v], h->stream));
+        DCO_TRY(prof_mark(h));
+    }
+    DCO_TRY(prof_mark(h));
+    DCO_HIP_CHECK(launch_wta2(s.agg[0], s.agg[1], h->W, h->H, h->D, p.subpixel, s.dint[0],
+                              s.delta, s.dint[1], h->stream));
+    DCO_TRY(prof_mark(h));
+    DCO_TRY(prof_mark(h));
+    DCO_HIP_CHECK(launch_lrcheck(s.dint[0], s.delta, s.dint[1], h->W, h->H, p.lr_max_diff, disp,
+                                 valid, h->stream));
+    DCO_TRY(prof_mark(h));
+    return DCO_OK;
+}
+
+extern "C" dco_status dco_stereo_last_disparities(dco_stereo* h, int16_t* dL, int16_t* dR) {
+    DCO_TRY(need(h, "handle"));
+    const size_t bytes = (size_t)h->W * h->H * sizeof(int16_t);
+    if (dL)
+        DCO_HIP_CHECK(hipMemcpyAsync(dL, h->s.dint[0], bytes, hipMemcpyDeviceToDevice, h->stream));
+    if (dR)
+        DCO_HIP_CHECK(hipMemcpyAsync(dR, h->s.dint[1], bytes, hipMemcpyDeviceToDevice, h->stream));
+    return DCO_OK;
+}
+
+// ---- not yet built: batched and differentiable forms ----
+extern "C" dco_status dco_batch_create(dco_batch** out, int, const int*, const int*, const int*,
+                                       const dco_params*, void*) {
+    if (out) *out = nullptr;
+    dco_set_error("dco_batch_create: not available in this build");
+    return DCO_ERR_STATE;
+}
+extern "C" void dco_batch_destroy(dco_batch*) {}
+extern "C" dco_status dco_batch_match(dco_batch*, const uint8_t* const*, const uint8_t* const*,
+                                      float* const*, uint8_t* const*) {
+    dco_set_error("dco_batch_match: not available in this build");
+    return DCO_ERR_STATE;
+}
+extern "C" dco_status dco_batch_tile(const dco_batch*, int, int*, int*, int*) {
+    dco_set_error("dco_batch_tile: not available in this build");
+    return DCO_ERR_STATE;
+}
+extern "C" dco_status dco_soft_forward(dco_stereo*, int, const uint8_t*, const uint8_t*,
+                                       const float*, float*, float*) {
+    dco_set_error("dco_soft_forward: not available in this build");
+    return DCO_ERR_STATE;
+}
+extern "C" dco_status dco_soft_backward(dco_stereo*, int, const uint8_t*, const uint8_t*,
+                                        const float*, const float*, const float*, const float*,
+                                        float*) {
+    dco_set_error("dco_soft_backward: not available in this build");
+    return DCO_ERR_STATE;
+}

@@ -1,0 +1,99 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+arguments before touching a GPU (CPU only)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2203_02300_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dco_stereo.h")
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dco_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2203_02300_amd import build
+        build.build()
+    return _lib.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    syms = declared_symbols()
+    assert len(syms) >= 18
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (dco_\w+)", out))
+    missing = [s for s in syms if s not in exported]
+    assert not missing, missing
+    assert set(syms) == set(_lib.EXPORTS)
+
+
+def test_default_params(L):
+    p = _lib.Params()
+    assert L.dco_default_params(C.byref(p)) == 0
+    assert (p.census_w, p.census_h, p.arm_L1, p.arm_tau1) == (9, 7, 17, 20)
+    assert (p.lambda_ad, p.lambda_census, p.gamma_L) == (10.0, 40.0, 1.0)
+    assert abs(p.eps - 0.8) < 1e-7 and p.agg_iters == 2 and p.subpixel == 1
+    assert L.dco_default_params(None) == -1
+
+
+def create(L, W, H, D, **kw):
+    p = _lib.Params()
+    L.dco_default_params(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    h = C.c_void_p()
+    st = L.dco_stereo_create(C.byref(h), W, H, D, C.byref(p), None)
+    return st, h
+
+
+@pytest.mark.parametrize("W,H,D", [(64, 48, 64), (64, 48, 0), (8, 48, 4), (64, 6, 4),
+                                   (20000, 8, 4), (16384, 16384, 16)])
+def test_bad_shapes_rejected(L, W, H, D):
+    st, h = create(L, W, H, D)
+    assert st == -2 and not h.value
+    assert b"shape" in L.dco_last_error()
+
+
+@pytest.mark.parametrize("kw", [dict(census_w=8), dict(census_w=11), dict(census_h=0),
+                                dict(arm_L1=18), dict(arm_L1=-1), dict(arm_tau1=0),
+                                dict(lambda_ad=0.0), dict(lambda_census=-1.0),
+                                dict(eps=float("nan")), dict(agg_iters=3),
+                                dict(lr_max_diff=-1), dict(subpixel=2)])
+def test_bad_params_rejected(L, kw):
+    st, h = create(L, 64, 48, 16, **kw)
+    assert st == -1 and not h.value
+
+
+def test_null_arguments_rejected(L):
+    assert L.dco_stereo_create(None, 64, 48, 16, None, None) == -1
+    assert L.dco_census(None, None, None, None) == -1
+    assert L.dco_cost_volume(None, 0, None, None, None, None, None, None) == -1
+    assert L.dco_aggregate(None, None, None, None) == -1
+    assert L.dco_wta_lrcheck(None, None, None, None, None, None, None) == -1
+    assert L.dco_stereo_match(None, None, None, None, None) == -1
+    assert L.dco_stereo_set_stream(None, None) == -1
+    L.dco_stereo_destroy(None)
+
+
+def test_status_strings(L):
+    assert L.dco_status_string(0) == b"ok"
+    assert L.dco_status_string(-4) == b"out of device memory"
+    assert L.dco_status_string(99) == b"unknown status"
+
+
+def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        _lib.lib()

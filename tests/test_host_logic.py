@@ -1,0 +1,69 @@
+"""Host-side checks of the exact-arithmetic claims the kernels rely on (CPU).
+
+1. Stage-1 rounding: floor(n / N) == (n * m) >> sh with sh = 31 + ceil(log2 N)
+   and m = ceil(2^sh / N) < 2^32, for every 1 <= N <= 1225 and 0 <= n < 2^31.
+2. Final division: with y = RN(1/N), q0 = RN(a y), r = RN(a - q0 N) (one
+   fused multiply-add), q = RN(q0 + r y) equals RN(a / N) for every float a
+   that is an integer below 2^31 and every integer 1 <= N <= 1225.
+Both are emulated exactly (Python integers, fractions) on dense samples.
+"""
+from fractions import Fraction
+
+import numpy as np
+
+NMAX = (2 * 17 + 1) ** 2
+
+
+def magic(N):
+    lg = 0 if N <= 1 else (N - 1).bit_length()
+    sh = 31 + lg
+    m = -(-(1 << sh) // N)
+    return m, sh
+
+
+def test_magic_division_exact():
+    rng = np.random.default_rng(0)
+    for N in range(1, NMAX + 1):
+        m, sh = magic(N)
+        assert m < (1 << 32)
+        top = (1 << 31) - 1
+        ns = [0, 1, N - 1, N, N + 1, top, top - 1, top - (top % N), top - (top % N) - 1]
+        ns += [int(v) for v in rng.integers(0, 1 << 31, 40)]
+        ns += [int(k) * N - 1 for k in rng.integers(1, top // N, 20)]
+        for n in ns:
+            if 0 <= n < (1 << 31):
+                assert (n * m) >> sh == n // N, (N, n)
+
+
+def rn32(x: Fraction) -> Fraction:
+    """Round a rational to the nearest float32 (ties to even), normal range."""
+    if x == 0:
+        return Fraction(0)
+    s = -1 if x < 0 else 1
+    x = abs(x)
+    e = x.numerator.bit_length() - x.denominator.bit_length()
+    if Fraction(2) ** e > x:
+        e -= 1
+    ulp = Fraction(2) ** (e - 23)
+    q, r = divmod(x, ulp)
+    q = int(q)
+    if r * 2 > ulp or (r * 2 == ulp and q & 1):
+        q += 1
+    return s * q * ulp
+
+
+def test_reciprocal_division_exact():
+    rng = np.random.default_rng(1)
+    Ns = list(range(1, 60)) + [int(v) for v in rng.integers(60, NMAX + 1, 120)] + [NMAX]
+    for N in Ns:
+        y = rn32(Fraction(1, N))
+        samples = [int(v) for v in rng.integers(0, 1 << 31, 25)]
+        samples += [int(v) for v in rng.integers(0, 1 << 24, 25)]
+        samples += [int(k) * N + N // 2 for k in rng.integers(1, (1 << 30) // N, 10)]
+        for s in samples:
+            a = rn32(Fraction(s))          # (float)S, as both sides convert
+            q0 = rn32(a * y)
+            r = rn32(a - q0 * N)
+            assert r == a - q0 * N          # the residual is exact
+            q = rn32(q0 + r * y)
+            assert q == rn32(a / N), (N, s)
