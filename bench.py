@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=240)
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MiB",
+                    help="only run a plain device copy of MiB mebibytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -70,6 +72,18 @@ def main():
     import torch
     from paper_2203_02300_amd import StereoMatcher, synth
     from paper_2203_02300_amd._lib import check, lib
+
+    if args.copy_calib:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings
+        # scale the same counters of the matcher's kernels
+        n = args.copy_calib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 4, "calls": 3}), flush=True)
+        return
 
     W, H, D = 1280, 720, 128
     log("bench: generating the 1280x720 D=128 pair (seed 3)")

@@ -135,11 +135,15 @@ static dco_status dev_alloc(T** p, size_t n) {
 }
 
 static void free_handle_memory(dco_stereo* h) {
-    void* ptrs[] = {h->tabA,       h->tabC,       h->alpha,      h->beta,       h->alpha_soft,
-                    h->s.cen[0],   h->s.cen[1],   h->s.arms[0],  h->s.arms[1],  h->s.div1[0],
-                    h->s.div1[1],  h->s.div2[0],  h->s.div2[1],  h->s.rgbp[0],  h->s.rgbp[1],
-                    h->s.agg[0],   h->s.agg[1],   h->s.dint[0],  h->s.dint[1],  h->s.delta,
-                    h->soft_vol,   h->soft_partials};
+    void* ptrs[] = {h->tabA,         h->tabC,         h->alpha,        h->beta,
+                    h->alpha_soft,   h->s.cen[0],     h->s.cen[1],     h->s.arms[0],
+                    h->s.arms[1],    h->s.rec[0].a,   h->s.rec[0].b,   h->s.rec[0].c,
+                    h->s.rec[1].a,   h->s.rec[1].b,   h->s.rec[1].c,   h->s.rgbp[0],
+                    h->s.rgbp[1],    h->s.agg[0],     h->s.agg[1],     h->s.dint[0],
+                    h->s.dint[1],    h->s.delta,      h->soft.cen[0],  h->soft.cen[1],
+                    h->soft.arms,    h->soft.rgbp[0], h->soft.rgbp[1], h->soft.arms_r,
+                    h->soft.n1,      h->soft.n2,      h->soft.tab,     h->soft.vol[0],
+                    h->soft.vol[1],  h->soft.vol[2],  h->soft.partAC,  h->soft.partT};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -150,14 +154,28 @@ static void free_handle_memory(dco_stereo* h) {
         if (_s != DCO_OK) return _s;       \
     } while (0)
 
+// Aggregation records with a zero apron and a zero extra row (zeroed once:
+// the geometry kernel writes only the interior).
+static dco_status alloc_records(AggRecords* r, int W, int H) {
+    r->apron = kRecApronL;
+    r->Wp = W + kRecApronL + kRecApronR;
+    const size_t n = (size_t)r->Wp * (H + 1);
+    DCO_TRY(dev_alloc(&r->a, n));
+    DCO_TRY(dev_alloc(&r->b, n));
+    DCO_TRY(dev_alloc(&r->c, n));
+    DCO_HIP_CHECK(hipMemset(r->a, 0, n * sizeof(uint32_t)));
+    DCO_HIP_CHECK(hipMemset(r->b, 0, n * sizeof(uint2)));
+    DCO_HIP_CHECK(hipMemset(r->c, 0, n * sizeof(uint2)));
+    return DCO_OK;
+}
+
 static dco_status alloc_scratch(dco_stereo* h) {
     const size_t P = (size_t)h->W * h->H, V = P * h->D;
     dco_scratch& s = h->s;
     for (int v = 0; v < 2; ++v) {
         DCO_TRY(dev_alloc(&s.cen[v], P));
         DCO_TRY(dev_alloc(&s.arms[v], P));
-        DCO_TRY(dev_alloc(&s.div1[v], P));
-        DCO_TRY(dev_alloc(&s.div2[v], P));
+        DCO_TRY(alloc_records(&s.rec[v], h->W, h->H));
         DCO_TRY(dev_alloc(&s.rgbp[v], P));
         DCO_TRY(dev_alloc(&s.agg[v], V));
         DCO_TRY(dev_alloc(&s.dint[v], P));
@@ -355,10 +373,9 @@ extern "C" dco_status dco_aggregate(dco_stereo* h, const float* cost, const uint
         return DCO_ERR_ARG;
     }
     const uint32_t* arms = (const uint32_t*)arms_ref;
-    DCO_HIP_CHECK(launch_geometry(arms, h->W, h->H, h->p.agg_iters, h->s.div1[0], h->s.div2[0],
-                                  h->stream));
-    DCO_HIP_CHECK(launch_aggregate(cost, arms, h->s.div1[0], h->s.div2[0], h->W, h->H, h->D,
-                                   h->p.agg_iters, agg, h->stream));
+    DCO_HIP_CHECK(launch_geometry(arms, h->W, h->H, h->p.agg_iters, h->s.rec[0], h->stream));
+    DCO_HIP_CHECK(launch_aggregate(cost, h->s.rec[0], h->W, h->H, h->D, h->p.agg_iters, agg,
+                                   h->stream));
     return DCO_OK;
 }
 
@@ -396,16 +413,14 @@ extern "C" dco_status dco_stereo_match(dco_stereo* h, const uint8_t* rgbL, const
     for (int v = 0; v < 2; ++v) {
         DCO_HIP_CHECK(launch_census_arms(img[v], h->W, h->H, p.census_w, p.census_h, p.arm_L1,
                                          p.arm_tau1, s.cen[v], s.arms[v], s.rgbp[v], h->stream));
-        DCO_HIP_CHECK(launch_geometry(s.arms[v], h->W, h->H, p.agg_iters, s.div1[v], s.div2[v],
-                                      h->stream));
+        DCO_HIP_CHECK(launch_geometry(s.arms[v], h->W, h->H, p.agg_iters, s.rec[v], h->stream));
     }
     DCO_TRY(prof_mark(h));
     for (int v = 0; v < 2; ++v) {
         DCO_TRY(prof_mark(h));
-        DCO_HIP_CHECK(launch_cost_aggregate(v, s.rgbp[0], s.rgbp[1], s.cen[0], s.cen[1],
-                                            s.arms[v], s.div1[v], s.div2[v], h->W, h->H, h->D,
-                                            p.agg_iters, h->tabA, h->tabC, h->alpha, h->beta,
-                                            p.arm_L1, s.agg[v], h->stream));
+        DCO_HIP_CHECK(launch_cost_aggregate(v, s.rgbp[0], s.rgbp[1], s.cen[0], s.cen[1], s.rec[v],
+                                            h->W, h->H, h->D, p.agg_iters, h->tabA, h->tabC,
+                                            h->alpha, h->beta, p.arm_L1, s.agg[v], h->stream));
         DCO_TRY(prof_mark(h));
     }
     DCO_TRY(prof_mark(h));
@@ -446,14 +461,107 @@ extern "C" dco_status dco_batch_tile(const dco_batch*, int, int*, int*, int*) {
     dco_set_error("dco_batch_tile: not available in this build");
     return DCO_ERR_STATE;
 }
-extern "C" dco_status dco_soft_forward(dco_stereo*, int, const uint8_t*, const uint8_t*,
-                                       const float*, float*, float*) {
-    dco_set_error("dco_soft_forward: not available in this build");
-    return DCO_ERR_STATE;
+
+
+// ---- differentiable soft-argmin form ----
+
+static void free_soft(SoftScratch& f) {
+    void* ptrs[] = {f.cen[0], f.cen[1], f.arms, f.rgbp[0], f.rgbp[1], f.arms_r, f.n1, f.n2,
+                    f.tab,    f.vol[0], f.vol[1], f.vol[2], f.partAC, f.partT};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    f = SoftScratch{};
 }
-extern "C" dco_status dco_soft_backward(dco_stereo*, int, const uint8_t*, const uint8_t*,
-                                        const float*, const float*, const float*, const float*,
-                                        float*) {
-    dco_set_error("dco_soft_backward: not available in this build");
-    return DCO_ERR_STATE;
+
+static dco_status soft_reserve(dco_stereo* h, int B) {
+    SoftScratch& f = h->soft;
+    if (f.cap >= B) return DCO_OK;
+    (void)hipStreamSynchronize(h->stream);
+    free_soft(f);
+    const size_t P = (size_t)h->W * h->H, V = P * h->D * B;
+    const size_t nb = (P + 255) / 256;
+    DCO_TRY(dev_alloc(&f.cen[0], P * B));
+    DCO_TRY(dev_alloc(&f.cen[1], P * B));
+    DCO_TRY(dev_alloc(&f.arms, P * B));
+    DCO_TRY(dev_alloc(&f.arms_r, P * B));
+    DCO_TRY(dev_alloc(&f.rgbp[0], P * B));
+    DCO_TRY(dev_alloc(&f.rgbp[1], P * B));
+    DCO_TRY(dev_alloc(&f.n1, P * B));
+    DCO_TRY(dev_alloc(&f.n2, P * B));
+    DCO_TRY(dev_alloc(&f.tab, 1792));
+    for (int k = 0; k < 3; ++k) DCO_TRY(dev_alloc(&f.vol[k], V));
+    DCO_TRY(dev_alloc(&f.partAC, 2 * (size_t)B * h->D * h->H));
+    DCO_TRY(dev_alloc(&f.partT, (size_t)B * nb));
+    f.cap = B;
+    return DCO_OK;
+}
+
+// Census, arms and packed RGB of every pair, the Eq. 1 tables for theta,
+// region counts, and the aggregated volume A2 (vol[0]).
+static dco_status soft_front(dco_stereo* h, int B, const uint8_t* L, const uint8_t* R,
+                             const float* theta, SoftBuffers* sb) {
+    SoftScratch& f = h->soft;
+    const dco_params& p = h->p;
+    const size_t P = (size_t)h->W * h->H;
+    for (int b = 0; b < B; ++b) {
+        DCO_HIP_CHECK(launch_census_arms(L + 3 * P * b, h->W, h->H, p.census_w, p.census_h,
+                                         p.arm_L1, p.arm_tau1, f.cen[0] + P * b, f.arms + P * b,
+                                         f.rgbp[0] + P * b, h->stream));
+        DCO_HIP_CHECK(launch_census_arms(R + 3 * P * b, h->W, h->H, p.census_w, p.census_h,
+                                         p.arm_L1, p.arm_tau1, f.cen[1] + P * b,
+                                         f.arms_r + P * b, f.rgbp[1] + P * b, h->stream));
+    }
+    DCO_HIP_CHECK(soft_prepare(theta, f.tab, f.arms, B, h->W, h->H, h->D, f.n1, f.n2, h->stream));
+    *sb = SoftBuffers{f.arms, f.n1, f.n2, f.rgbp[0], f.rgbp[1], f.cen[0], f.cen[1], h->alpha, f.tab};
+    DCO_HIP_CHECK(soft_aggregate(*sb, B, h->W, h->H, h->D, f.vol[0], f.vol[1], f.vol[2], h->stream));
+    return DCO_OK;
+}
+
+static dco_status soft_check(dco_stereo* h, int B) {
+    DCO_TRY(need(h, "handle"));
+    if (B < 1) {
+        dco_set_error("B must be >= 1 (got %d)", B);
+        return DCO_ERR_ARG;
+    }
+    if (h->W > 2048 || h->p.agg_iters != 2) {
+        dco_set_error("the soft path needs W <= 2048 and two-stage aggregation");
+        return DCO_ERR_SHAPE;
+    }
+    return DCO_OK;
+}
+
+extern "C" dco_status dco_soft_forward(dco_stereo* h, int B, const uint8_t* L, const uint8_t* R,
+                                       const float* theta, float* dhat, float* lse) {
+    DCO_TRY(soft_check(h, B));
+    DCO_TRY(need(L, "L"));
+    DCO_TRY(need(R, "R"));
+    DCO_TRY(need(theta, "theta"));
+    DCO_TRY(need(dhat, "dhat"));
+    DCO_TRY(need(lse, "lse"));
+    DCO_TRY(soft_reserve(h, B));
+    SoftBuffers sb;
+    DCO_TRY(soft_front(h, B, L, R, theta, &sb));
+    DCO_HIP_CHECK(soft_argmin(sb, B, h->W, h->H, h->D, h->soft.vol[0], theta, dhat, lse,
+                              h->stream));
+    return DCO_OK;
+}
+
+extern "C" dco_status dco_soft_backward(dco_stereo* h, int B, const uint8_t* L, const uint8_t* R,
+                                        const float* theta, const float* dhat, const float* lse,
+                                        const float* grad_dhat, float* grad_theta) {
+    DCO_TRY(soft_check(h, B));
+    DCO_TRY(need(L, "L"));
+    DCO_TRY(need(R, "R"));
+    DCO_TRY(need(theta, "theta"));
+    DCO_TRY(need(dhat, "dhat"));
+    DCO_TRY(need(lse, "lse"));
+    DCO_TRY(need(grad_dhat, "grad_dhat"));
+    DCO_TRY(need(grad_theta, "grad_theta"));
+    DCO_TRY(soft_reserve(h, B));
+    SoftBuffers sb;
+    DCO_TRY(soft_front(h, B, L, R, theta, &sb));  // recompute the aggregation
+    SoftScratch& f = h->soft;
+    DCO_HIP_CHECK(soft_backward(sb, B, h->W, h->H, h->D, f.vol[0], theta, dhat, lse, grad_dhat,
+                                f.vol[1], f.vol[2], f.partAC, f.partT, grad_theta, h->stream));
+    return DCO_OK;
 }

@@ -23,31 +23,61 @@ constexpr int kStripOut = kStripThreads - 4 * kLMax;
 // Rows processed per block-scan round in the streaming kernels.
 constexpr int kRowChunk = 8;
 
-// Per-pixel division data for the aggregation (computed once per view).
-//   div1: stage-1 rounding a1 = ((S1 + half) * m) >> sh, exact for
-//         0 <= S1 + half < 2^31 and 1 <= N1 <= 2^11.
-//   div2: (N as float, RN(1/N)) of the final float division.
-struct DivInt {
-    uint32_t m;
-    uint32_t half_sh;  // half | (sh << 16)
+// Packed per-pixel records of one view for the aggregation kernels, written
+// by k_geometry.  Each array has H + 1 rows of Wp entries; pixel (x, y) sits
+// at y * Wp + x + apron, and the apron columns and row H are zero.
+//   a[p] = l | r << 8 | u << 16 | dn << 24                        (arms)
+//   b[p] = (m, half | sh << 10 | u << 16 | dn << 21)   stage-1 rounding
+//          floor((S1 + half) / N1) = ((S1 + half) * m) >> sh, half = N1 / 2
+//   c[p] = (bits of RN(1/N), l | r << 5 | u << 10 | dn << 15 | N << 20)
+//          with N = N2 for two stages and N1 for one
+struct AggRecords {
+    uint32_t* a;
+    uint2* b;
+    uint2* c;
+    int Wp, apron;
 };
-
-struct dco_geometry {
-    uint32_t* arms;   // packed arms: l | r << 8 | u << 16 | dn << 24  (H x W)
-    DivInt* div1;     // stage-1 integer division data                (H x W)
-    float2* div2;     // final float division data                    (H x W)
-};
+constexpr int kRecApronL = 2 * kLMax;        // left apron of the records
+constexpr int kRecApronR = kStripThreads;    // right apron (covers a strip's overhang)
 
 // Scratch owned by a matcher handle for the one-call path.
 struct dco_scratch {
     uint64_t* cen[2];
     uint32_t* arms[2];
-    DivInt* div1[2];
-    float2* div2[2];
+    AggRecords rec[2];
     uint32_t* rgbp[2];  // packed RGB of both views
     float* agg[2];      // aggregated volumes of both views (D x H x W)
     int16_t* dint[2];
     float* delta;
+};
+
+// Soft-path scratch of a handle: per-pair maps of B pairs and three
+// B x D x H x W float volumes (grown on demand).
+struct SoftScratch {
+    int cap;               // pairs the buffers hold
+    uint64_t* cen[2];      // census codes of left / right views
+    uint32_t* arms;        // arms of the left views
+    uint32_t* rgbp[2];     // packed RGB
+    uint32_t* arms_r;      // arms of the right views (computed, unused)
+    float* n1;             // region counts
+    float* n2;
+    float* tab;            // Eq. 1 tables and derivatives for the current theta
+    float* vol[3];
+    double* partAC;        // per-row partial sums of the lambda gradients
+    double* partT;         // per-block partial sums of the temperature gradient
+};
+
+// Read-only view of the soft-path inputs handed to the kernels.
+struct SoftBuffers {
+    const uint32_t* arms;
+    const float* n1;
+    const float* n2;
+    const uint32_t* rgbL;
+    const uint32_t* rgbR;
+    const uint64_t* cenL;
+    const uint64_t* cenR;
+    const float* alpha;
+    const float* tab;
 };
 
 struct dco_stereo {
@@ -71,10 +101,7 @@ struct dco_stereo {
     std::vector<hipEvent_t> prof_events;  // 2 * DCO_NUM_STAGES per recorded call
     size_t prof_used;
     // soft-path scratch (allocated on first use)
-    float* soft_vol;
-    size_t soft_vol_elems;
-    double* soft_partials;
-    size_t soft_partials_n;
+    SoftScratch soft;
 };
 
 // ---- error helpers (api.cpp) ----
@@ -93,22 +120,32 @@ void dco_set_error(const char* fmt, ...);
 hipError_t launch_census_arms(const uint8_t* rgb, int W, int H, int cw, int ch, int L1, int tau1,
                               uint64_t* census, uint32_t* arms, uint32_t* rgb_packed,
                               hipStream_t st);
-hipError_t launch_geometry(const uint32_t* arms, int W, int H, int iters, DivInt* div1,
-                           float2* div2, hipStream_t st);
+hipError_t launch_geometry(const uint32_t* arms, int W, int H, int iters, const AggRecords& rec,
+                           hipStream_t st);
 hipError_t launch_cost(int ref, const uint8_t* rgbL, const uint8_t* rgbR, const uint64_t* cenL,
                        const uint64_t* cenR, const uint32_t* arms_ref, int W, int H, int D,
                        const float* tabA, const float* tabC, const float* alpha,
                        const float* beta, int L1, float* cost, hipStream_t st);
-hipError_t launch_aggregate(const float* cost, const uint32_t* arms, const DivInt* div1,
-                            const float2* div2, int W, int H, int D, int iters, float* out,
-                            hipStream_t st);
+hipError_t launch_aggregate(const float* cost, const AggRecords& rec, int W, int H, int D,
+                            int iters, float* out, hipStream_t st);
 hipError_t launch_cost_aggregate(int ref, const uint32_t* rgbL, const uint32_t* rgbR,
                                  const uint64_t* cenL, const uint64_t* cenR,
-                                 const uint32_t* arms, const DivInt* div1, const float2* div2,
-                                 int W, int H, int D, int iters, const float* tabA,
-                                 const float* tabC, const float* alpha, const float* beta,
-                                 int L1, float* out, hipStream_t st);
+                                 const AggRecords& rec, int W, int H, int D, int iters,
+                                 const float* tabA, const float* tabC, const float* alpha,
+                                 const float* beta, int L1, float* out, hipStream_t st);
 hipError_t launch_wta2(const float* aggL, const float* aggR, int W, int H, int D, int subpixel,
                        int16_t* dL, float* deltaL, int16_t* dR, hipStream_t st);
 hipError_t launch_lrcheck(const int16_t* dL, const float* deltaL, const int16_t* dR, int W,
                           int H, int maxdiff, float* disp, uint8_t* valid, hipStream_t st);
+
+// k_soft.hip
+hipError_t soft_prepare(const float* theta, float* tab, const uint32_t* arms, int B, int W, int H,
+                        int D, float* n1, float* n2, hipStream_t st);
+hipError_t soft_aggregate(const SoftBuffers& s, int B, int W, int H, int D, float* A2, float* t1,
+                          float* t2, hipStream_t st);
+hipError_t soft_argmin(const SoftBuffers& s, int B, int W, int H, int D, const float* A2,
+                       const float* theta, float* dhat, float* lse, hipStream_t st);
+hipError_t soft_backward(const SoftBuffers& s, int B, int W, int H, int D, const float* A2,
+                         const float* theta, const float* dhat, const float* lse,
+                         const float* gdhat, float* t1, float* t2, double* partAC,
+                         double* partT, float* grad, hipStream_t st);

@@ -91,29 +91,28 @@ __global__ __launch_bounds__(256) void k_census_arms(const uint8_t* __restrict__
     }
 }
 
-// Region pixel counts and division data of every pixel:
+// Region pixel counts and the packed aggregation records of every pixel:
 //   N1 = sum over y' in [y-u, y+dn] of (l(x,y') + r(x,y') + 1)
 //   N2 = sum over x' in [x-l, x+r] of (u(x',y) + dn(x',y) + 1)
-// div1 holds (m, half | sh << 16) with sh = 31 + ceil(log2 N1) and
-// m = ceil(2^sh / N1) < 2^32, so floor(n / N1) = (n * m) >> sh for every
-// 0 <= n < 2^31.  div2 holds (N, RN(1/N)) of the final float division
-// (N = N2 for two stages, N1 for one).
+// Stage-1 rounding uses sh = 31 + ceil(log2 N1) and m = ceil(2^sh / N1) <
+// 2^32, so floor(n / N1) = (n * m) >> sh for every 0 <= n < 2^31 (N1 <= 2^11).
+// The final division uses (N, RN(1/N)) with N = N2 (two stages) or N1 (one).
+// Record layout: see AggRecords.
 __global__ __launch_bounds__(256) void k_geometry(const uint32_t* __restrict__ arms, int W, int H,
-                                                  int iters, DivInt* __restrict__ div1,
-                                                  float2* __restrict__ div2) {
+                                                  int iters, AggRecords rec) {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= W || y >= H) return;
     const uint32_t a = arms[(size_t)y * W + x];
-    const int l = a & 0xff, r = (a >> 8) & 0xff, u = (a >> 16) & 0xff, dn = a >> 24;
+    const uint32_t l = a & 0xff, r = (a >> 8) & 0xff, u = (a >> 16) & 0xff, dn = a >> 24;
     uint32_t n1 = 0, n2 = 0;
     // arms come from k_census_arms and stay inside the image; the clamps only
     // keep a corrupted arms buffer from reading outside it
-    for (int yy = max(0, y - u); yy <= min(H - 1, y + dn); ++yy) {
+    for (int yy = max(0, y - (int)u); yy <= min(H - 1, y + (int)dn); ++yy) {
         uint32_t b = arms[(size_t)yy * W + x];
         n1 += (b & 0xff) + ((b >> 8) & 0xff) + 1;
     }
-    for (int xx = max(0, x - l); xx <= min(W - 1, x + r); ++xx) {
+    for (int xx = max(0, x - (int)l); xx <= min(W - 1, x + (int)r); ++xx) {
         uint32_t b = arms[(size_t)y * W + xx];
         n2 += ((b >> 16) & 0xff) + (b >> 24) + 1;
     }
@@ -121,9 +120,13 @@ __global__ __launch_bounds__(256) void k_geometry(const uint32_t* __restrict__ a
     const uint32_t sh = 31u + lg;
     const uint64_t num = (uint64_t)1 << sh;
     const uint32_t m = (uint32_t)((num + n1 - 1) / n1);
-    div1[(size_t)y * W + x] = DivInt{m, (n1 >> 1) | (sh << 16)};
-    const float nf = (float)(iters == 1 ? n1 : n2);
-    div2[(size_t)y * W + x] = make_float2(nf, 1.0f / nf);
+    const uint32_t n = iters == 1 ? n1 : n2;
+    const float rcp = 1.0f / (float)n;
+    const size_t i = (size_t)y * rec.Wp + x + rec.apron;
+    rec.a[i] = a;
+    rec.b[i] = make_uint2(m, (n1 >> 1) | (sh << 10) | (u << 16) | (dn << 21));
+    rec.c[i] = make_uint2(__float_as_uint(rcp),
+                          l | (r << 5) | (u << 10) | (dn << 15) | (n << 20));
 }
 
 }  // namespace
@@ -137,9 +140,9 @@ hipError_t launch_census_arms(const uint8_t* rgb, int W, int H, int cw, int ch, 
     return hipGetLastError();
 }
 
-hipError_t launch_geometry(const uint32_t* arms, int W, int H, int iters, DivInt* div1,
-                           float2* div2, hipStream_t st) {
+hipError_t launch_geometry(const uint32_t* arms, int W, int H, int iters, const AggRecords& rec,
+                           hipStream_t st) {
     dim3 grid((W + 63) / 64, (H + 3) / 4);
-    hipLaunchKernelGGL(k_geometry, grid, dim3(256), 0, st, arms, W, H, iters, div1, div2);
+    hipLaunchKernelGGL(k_geometry, grid, dim3(256), 0, st, arms, W, H, iters, rec);
     return hipGetLastError();
 }

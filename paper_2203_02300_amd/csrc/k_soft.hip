@@ -1,0 +1,440 @@
+// k_soft.hip -- differentiable soft-argmin form of the matcher (left view).
+//
+// Forward, per pair b, disparity d, pixel p (all float):
+//   c(p,d)  = alpha_p (1 - exp(-(s/3)/lambda_AD)) + (1 - alpha_p)(1 - exp(-h/lambda_census))
+//             (Eq. 1; c = 1 where the partner pixel x - d is outside the image)
+//   E1 = row range sum of c       a1 = (column range sum of E1) / N1     (Eq. 2, stage 1)
+//   E2 = column range sum of a1   A2 = (row range sum of E2) / N2         (Eq. 2, stage 2)
+//   dhat = sum_d d softmax_d(-A2 / T),  lse = log sum_d exp(-A2 / T)
+// Every range sum adds at most 2 kLMax + 1 terms directly, in a fixed order,
+// so there is no cancellation between long prefix sums and the result is
+// bit-reproducible.
+//
+// Backward, given g = dLoss/d dhat:
+//   G_A2  = g w (dhat - d) / T,   dLoss/dT = sum g w (d - dhat) A2 / T^2
+// then the adjoint of each range sum: an output that summed a range hands its
+// adjoint back to every pixel of that range.  Each adjoint is written as a
+// gather over the (at most 2 kLMax + 1) candidate pixels whose range can
+// cover a pixel, so there are no atomics and no float reductions of
+// unspecified order.  Finally
+//   dLoss/dlambda_AD     = sum G_c alpha   d(1 - exp(-(s/3)/lambda_AD))/dlambda_AD
+//   dLoss/dlambda_census = sum G_c (1 - alpha) d(1 - exp(-h/lambda_census))/dlambda_census
+// with fixed-order two-level reductions.
+//
+// Layout: volumes are B x D x H x W float in handle scratch; arms, census
+// and packed RGB are per pair B x H x W.  Row passes run one workgroup per
+// image row with the row in LDS; column passes one workgroup per 64-column x
+// 64-row tile with a kLMax-row apron in LDS.
+#include "dco_internal.h"
+
+namespace {
+
+constexpr int kTileX = 64, kTileY = 64;
+
+struct SoftGeom {
+    const uint32_t* arms;  // B x H x W packed arms of the left view
+    const float* n1;       // B x H x W stage-1 region counts
+    const float* n2;       // B x H x W stage-2 region counts
+    int B, W, H, D;
+};
+
+__device__ inline int arm(uint32_t a, int k) { return (a >> (8 * k)) & 0xff; }
+
+// Tables of Eq. 1 for the current theta, and their lambda derivatives:
+// tab[0..765] = 1 - exp(-(s/3)/lambda_AD),   tab[768..1533] = d/dlambda_AD
+// tab[1536..1600] = 1 - exp(-h/lambda_c),    tab[1664..1728] = d/dlambda_c
+__global__ void k_soft_tables(const float* __restrict__ theta, float* __restrict__ tab) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const float la = theta[0], lc = theta[1];
+    if (i < 766) {
+        const float x = (float)i / 3.0f;
+        const float e = expf(-x / la);
+        tab[i] = -expm1f(-x / la);
+        tab[768 + i] = -e * x / (la * la);
+    } else if (i >= 768 && i < 768 + 65) {
+        const int h = i - 768;
+        const float e = expf(-(float)h / lc);
+        tab[1536 + h] = -expm1f(-(float)h / lc);
+        tab[1664 + h] = -e * (float)h / (lc * lc);
+    }
+}
+
+// Region pixel counts of the left view (as floats) for every pair.
+__global__ void k_soft_counts(SoftGeom g, float* __restrict__ n1, float* __restrict__ n2) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int b = blockIdx.z;
+    if (x >= g.W || y >= g.H) return;
+    const uint32_t* A = g.arms + (size_t)b * g.W * g.H;
+    const uint32_t a = A[(size_t)y * g.W + x];
+    int s1 = 0, s2 = 0;
+    for (int yy = max(0, y - arm(a, 2)); yy <= min(g.H - 1, y + arm(a, 3)); ++yy) {
+        const uint32_t q = A[(size_t)yy * g.W + x];
+        s1 += arm(q, 0) + arm(q, 1) + 1;
+    }
+    for (int xx = max(0, x - arm(a, 0)); xx <= min(g.W - 1, x + arm(a, 1)); ++xx) {
+        const uint32_t q = A[(size_t)y * g.W + xx];
+        s2 += arm(q, 2) + arm(q, 3) + 1;
+    }
+    const size_t i = (size_t)b * g.W * g.H + (size_t)y * g.W + x;
+    n1[i] = (float)s1;
+    n2[i] = (float)s2;
+}
+
+// Raw costs c (and, with kDeriv, the two lambda-derivative factors packed as
+// dc/dlambda_AD and dc/dlambda_c) of one image row for one (pair, d).
+template <bool kDeriv>
+__device__ inline void cost_row(const uint32_t* rgbL, const uint32_t* rgbR, const uint64_t* cenL,
+                                const uint64_t* cenR, const uint32_t* arms, const float* alpha,
+                                const float* tab, int W, int y, int d, int x, float* c,
+                                float* dca, float* dcc) {
+    const size_t i = (size_t)y * W + x;
+    if (x - d < 0) {
+        *c = 1.0f;
+        if (kDeriv) *dca = 0.0f, *dcc = 0.0f;
+        return;
+    }
+    const uint32_t s = __builtin_amdgcn_sad_u8(rgbL[i], rgbR[i - d], 0u);
+    const int h = __popcll(cenL[i] ^ cenR[i - d]);
+    const uint32_t a = arms[i];
+    const int lmin = min(min(arm(a, 0), arm(a, 1)), min(arm(a, 2), arm(a, 3)));
+    const float al = alpha[lmin];
+    *c = al * tab[s] + (1.0f - al) * tab[1536 + h];
+    if (kDeriv) {
+        *dca = al * tab[768 + s];
+        *dcc = (1.0f - al) * tab[1664 + h];
+    }
+}
+
+struct SoftImg {
+    const uint32_t* rgbL;  // B x H x W packed RGB
+    const uint32_t* rgbR;
+    const uint64_t* cenL;  // B x H x W census
+    const uint64_t* cenR;
+    const float* alpha;    // alpha_L, L = 0..kLMax
+    const float* tab;      // k_soft_tables output
+};
+
+// Forward row pass 1: E1(x) = sum of c over [x - l, x + r], one row per block.
+__global__ __launch_bounds__(256) void k_soft_h1(SoftGeom g, SoftImg im, float* __restrict__ E1) {
+    __shared__ float row[2048];
+    const int y = blockIdx.x, d = blockIdx.y, b = blockIdx.z, W = g.W;
+    const size_t P = (size_t)W * g.H;
+    const uint32_t* arms = g.arms + b * P;
+    for (int x = threadIdx.x; x < W; x += blockDim.x) {
+        float c;
+        cost_row<false>(im.rgbL + b * P, im.rgbR + b * P, im.cenL + b * P, im.cenR + b * P, arms,
+                        im.alpha, im.tab, W, y, d, x, &c, nullptr, nullptr);
+        row[x] = c;
+    }
+    __syncthreads();
+    float* out = E1 + ((size_t)b * g.D + d) * P + (size_t)y * W;
+    for (int x = threadIdx.x; x < W; x += blockDim.x) {
+        const uint32_t a = arms[(size_t)y * W + x];
+        float s = 0.0f;
+        for (int xx = x - arm(a, 0); xx <= x + arm(a, 1); ++xx) s += row[xx];
+        out[x] = s;
+    }
+}
+
+// Column pass: out(x, y) = scale(x, y) * sum of in(x, y') over y' in [y - u, y + dn]
+// of pixel (x, y).  One 64 x 64 tile per block with the kLMax-row aprons in LDS.
+__global__ __launch_bounds__(256) void k_soft_v(SoftGeom g, const float* __restrict__ in,
+                                                const float* __restrict__ scale,
+                                                float* __restrict__ out) {
+    __shared__ float tile[kTileY + 2 * kLMax][kTileX];
+    const int x0 = blockIdx.x * kTileX, y0 = (blockIdx.y % ((g.H + kTileY - 1) / kTileY)) * kTileY;
+    const int bd = blockIdx.y / ((g.H + kTileY - 1) / kTileY);  // b * D + d
+    const int b = bd / g.D;
+    const size_t P = (size_t)g.W * g.H;
+    const float* src = in + (size_t)bd * P;
+    for (int i = threadIdx.x; i < (kTileY + 2 * kLMax) * kTileX; i += 256) {
+        const int ty = i / kTileX, tx = i - ty * kTileX;
+        const int y = y0 - kLMax + ty, x = x0 + tx;
+        tile[ty][tx] = (y >= 0 && y < g.H && x < g.W) ? src[(size_t)y * g.W + x] : 0.0f;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x & 63;
+    const int x = x0 + tx;
+    if (x >= g.W) return;
+    for (int ty = threadIdx.x >> 6; ty < kTileY; ty += 4) {
+        const int y = y0 + ty;
+        if (y >= g.H) break;
+        const size_t i = (size_t)y * g.W + x;
+        const uint32_t a = g.arms[b * P + i];
+        float s = 0.0f;
+        for (int k = ty + kLMax - arm(a, 2); k <= ty + kLMax + arm(a, 3); ++k) s += tile[k][tx];
+        out[(size_t)bd * P + i] = scale ? s / scale[b * P + i] : s;
+    }
+}
+
+// Forward row pass 2: A2(x) = sum of E2 over [x - l, x + r] / N2.
+__global__ __launch_bounds__(256) void k_soft_h2(SoftGeom g, const float* __restrict__ E2,
+                                                 float* __restrict__ A2) {
+    __shared__ float row[2048];
+    const int y = blockIdx.x, d = blockIdx.y, b = blockIdx.z, W = g.W;
+    const size_t P = (size_t)W * g.H;
+    const size_t base = ((size_t)b * g.D + d) * P + (size_t)y * W;
+    for (int x = threadIdx.x; x < W; x += blockDim.x) row[x] = E2[base + x];
+    __syncthreads();
+    for (int x = threadIdx.x; x < W; x += blockDim.x) {
+        const size_t i = (size_t)y * W + x;
+        const uint32_t a = g.arms[b * P + i];
+        float s = 0.0f;
+        for (int xx = x - arm(a, 0); xx <= x + arm(a, 1); ++xx) s += row[xx];
+        A2[base + x] = s / g.n2[b * P + i];
+    }
+}
+
+// Soft-argmin over d per pixel: dhat and lse (log-sum-exp of -A2/T).
+__global__ __launch_bounds__(256) void k_soft_argmin(SoftGeom g, const float* __restrict__ A2,
+                                                     const float* __restrict__ theta,
+                                                     float* __restrict__ dhat,
+                                                     float* __restrict__ lse) {
+    const size_t P = (size_t)g.W * g.H;
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const int b = blockIdx.y;
+    if (i >= P) return;
+    const float invT = 1.0f / theta[2];
+    const float* a = A2 + (size_t)b * g.D * P + i;
+    float m = -a[0] * invT;
+    for (int d = 1; d < g.D; ++d) m = fmaxf(m, -a[(size_t)d * P] * invT);
+    float z = 0.0f, zd = 0.0f;
+    for (int d = 0; d < g.D; ++d) {
+        const float e = expf(-a[(size_t)d * P] * invT - m);
+        z += e;
+        zd += (float)d * e;
+    }
+    dhat[(size_t)b * P + i] = zd / z;
+    lse[(size_t)b * P + i] = m + logf(z);
+}
+
+// Backward seed: G(p,d) = g w (dhat - d) / (T N2), per-block partial sums of
+// the T-gradient terms g w (d - dhat) A2 / T^2 (one partial per block).
+__global__ __launch_bounds__(256) void k_soft_seed(SoftGeom g, const float* __restrict__ A2,
+                                                   const float* __restrict__ theta,
+                                                   const float* __restrict__ dhat,
+                                                   const float* __restrict__ lse,
+                                                   const float* __restrict__ gdhat,
+                                                   float* __restrict__ G,
+                                                   double* __restrict__ partT) {
+    __shared__ double red[256];
+    const size_t P = (size_t)g.W * g.H;
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const int b = blockIdx.y;
+    const float T = theta[2], invT = 1.0f / T;
+    double acc = 0.0;
+    if (i < P) {
+        const size_t pi = (size_t)b * P + i;
+        const float gp = gdhat[pi], dh = dhat[pi], l = lse[pi], n2 = g.n2[pi];
+        for (int d = 0; d < g.D; ++d) {
+            const size_t vi = ((size_t)b * g.D + d) * P + i;
+            const float a2 = A2[vi];
+            const float w = expf(-a2 * invT - l);
+            G[vi] = gp * w * (dh - (float)d) * invT / n2;
+            acc += (double)(gp * w * ((float)d - dh) * a2) * (double)(invT * invT);
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partT[(size_t)b * gridDim.x + blockIdx.x] = red[0];
+}
+
+// Adjoint of a row range sum: out(x') = sum over x with x' in [x - l(x), x + r(x)]
+// of in(x).  The candidates are x in [x' - kLMax, x' + kLMax].
+__global__ __launch_bounds__(256) void k_soft_h_adj(SoftGeom g, const float* __restrict__ in,
+                                                    float* __restrict__ out) {
+    __shared__ float row[2048];
+    __shared__ uint32_t arow[2048];
+    const int y = blockIdx.x, d = blockIdx.y, b = blockIdx.z, W = g.W;
+    const size_t P = (size_t)W * g.H;
+    const size_t base = ((size_t)b * g.D + d) * P + (size_t)y * W;
+    for (int x = threadIdx.x; x < W; x += blockDim.x) {
+        row[x] = in[base + x];
+        arow[x] = g.arms[b * P + (size_t)y * W + x];
+    }
+    __syncthreads();
+    for (int xp = threadIdx.x; xp < W; xp += blockDim.x) {
+        float s = 0.0f;
+        for (int x = max(0, xp - kLMax); x <= min(W - 1, xp + kLMax); ++x) {
+            const uint32_t a = arow[x];
+            if (xp >= x - arm(a, 0) && xp <= x + arm(a, 1)) s += row[x];
+        }
+        out[base + xp] = s;
+    }
+}
+
+// Adjoint of a column range sum, then an optional per-pixel scale:
+// out(x, y') = scale(x, y') * sum over y with y' in [y - u(y), y + dn(y)] of in(x, y).
+__global__ __launch_bounds__(256) void k_soft_v_adj(SoftGeom g, const float* __restrict__ in,
+                                                    const float* __restrict__ scale,
+                                                    float* __restrict__ out) {
+    __shared__ float tile[kTileY + 2 * kLMax][kTileX];
+    __shared__ uint32_t atile[kTileY + 2 * kLMax][kTileX];
+    const int nty = (g.H + kTileY - 1) / kTileY;
+    const int x0 = blockIdx.x * kTileX, y0 = (blockIdx.y % nty) * kTileY;
+    const int bd = blockIdx.y / nty;
+    const int b = bd / g.D;
+    const size_t P = (size_t)g.W * g.H;
+    for (int i = threadIdx.x; i < (kTileY + 2 * kLMax) * kTileX; i += 256) {
+        const int ty = i / kTileX, tx = i - ty * kTileX;
+        const int y = y0 - kLMax + ty, x = x0 + tx;
+        const bool ok = y >= 0 && y < g.H && x < g.W;
+        tile[ty][tx] = ok ? in[(size_t)bd * P + (size_t)y * g.W + x] : 0.0f;
+        atile[ty][tx] = ok ? g.arms[b * P + (size_t)y * g.W + x] : 0u;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x & 63;
+    const int x = x0 + tx;
+    if (x >= g.W) return;
+    for (int ty = threadIdx.x >> 6; ty < kTileY; ty += 4) {
+        const int yp = y0 + ty;
+        if (yp >= g.H) break;
+        float s = 0.0f;
+        for (int k = ty; k <= ty + 2 * kLMax; ++k) {  // candidate rows yp - kLMax .. yp + kLMax
+            const int y = y0 - kLMax + k;
+            const uint32_t a = atile[k][tx];
+            if (yp >= y - arm(a, 2) && yp <= y + arm(a, 3)) s += tile[k][tx];
+        }
+        const size_t i = (size_t)yp * g.W + x;
+        out[(size_t)bd * P + i] = scale ? s / scale[b * P + i] : s;
+    }
+}
+
+// Last adjoint (row direction, onto the raw costs) fused with the lambda
+// derivatives: per-block partial sums of G_c dc/dlambda_AD and G_c dc/dlambda_c.
+__global__ __launch_bounds__(256) void k_soft_h1_adj_grad(SoftGeom g, SoftImg im,
+                                                          const float* __restrict__ GE1,
+                                                          double* __restrict__ part) {
+    __shared__ float row[2048];
+    __shared__ uint32_t arow[2048];
+    __shared__ double red[2][256];
+    const int y = blockIdx.x, d = blockIdx.y, b = blockIdx.z, W = g.W;
+    const size_t P = (size_t)W * g.H;
+    const size_t base = ((size_t)b * g.D + d) * P + (size_t)y * W;
+    const uint32_t* arms = g.arms + b * P;
+    for (int x = threadIdx.x; x < W; x += blockDim.x) {
+        row[x] = GE1[base + x];
+        arow[x] = arms[(size_t)y * W + x];
+    }
+    __syncthreads();
+    double sa = 0.0, sc = 0.0;
+    for (int xp = threadIdx.x; xp < W; xp += blockDim.x) {
+        float s = 0.0f;
+        for (int x = max(0, xp - kLMax); x <= min(W - 1, xp + kLMax); ++x) {
+            const uint32_t a = arow[x];
+            if (xp >= x - arm(a, 0) && xp <= x + arm(a, 1)) s += row[x];
+        }
+        float c, dca, dcc;
+        cost_row<true>(im.rgbL + b * P, im.rgbR + b * P, im.cenL + b * P, im.cenR + b * P, arms,
+                       im.alpha, im.tab, W, y, d, xp, &c, &dca, &dcc);
+        sa += (double)(s * dca);
+        sc += (double)(s * dcc);
+    }
+    red[0][threadIdx.x] = sa;
+    red[1][threadIdx.x] = sc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const size_t blk = ((size_t)b * g.D + d) * g.H + y;
+        part[2 * blk] = red[0][0];
+        part[2 * blk + 1] = red[1][0];
+    }
+}
+
+// Final fixed-order reduction of the partial sums into grad_theta (float).
+__global__ void k_soft_reduce(const double* __restrict__ partAC, size_t nAC,
+                              const double* __restrict__ partT, size_t nT,
+                              float* __restrict__ grad) {
+    __shared__ double red[3][256];
+    double a = 0.0, c = 0.0, t = 0.0;
+    for (size_t i = threadIdx.x; i < nAC; i += 256) {
+        a += partAC[2 * i];
+        c += partAC[2 * i + 1];
+    }
+    for (size_t i = threadIdx.x; i < nT; i += 256) t += partT[i];
+    red[0][threadIdx.x] = a;
+    red[1][threadIdx.x] = c;
+    red[2][threadIdx.x] = t;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        grad[0] = (float)red[0][0];
+        grad[1] = (float)red[1][0];
+        grad[2] = (float)red[2][0];
+    }
+}
+
+}  // namespace
+
+// ---- launchers -------------------------------------------------------------
+
+hipError_t soft_prepare(const float* theta, float* tab, const uint32_t* arms, int B, int W, int H,
+                        int D, float* n1, float* n2, hipStream_t st) {
+    hipLaunchKernelGGL(k_soft_tables, dim3(4), dim3(256), 0, st, theta, tab);
+    SoftGeom g{arms, nullptr, nullptr, B, W, H, D};
+    hipLaunchKernelGGL(k_soft_counts, dim3((W + 63) / 64, (H + 3) / 4, B), dim3(256), 0, st, g, n1,
+                       n2);
+    return hipGetLastError();
+}
+
+// Forward aggregation into A2 (B x D x H x W); t1, t2 are volume-sized scratch.
+hipError_t soft_aggregate(const SoftBuffers& s, int B, int W, int H, int D, float* A2, float* t1,
+                          float* t2, hipStream_t st) {
+    SoftGeom g{s.arms, s.n1, s.n2, B, W, H, D};
+    SoftImg im{s.rgbL, s.rgbR, s.cenL, s.cenR, s.alpha, s.tab};
+    const int nty = (H + kTileY - 1) / kTileY;
+    hipLaunchKernelGGL(k_soft_h1, dim3(H, D, B), dim3(256), 0, st, g, im, t1);             // E1
+    hipLaunchKernelGGL(k_soft_v, dim3((W + kTileX - 1) / kTileX, nty * B * D), dim3(256), 0, st,
+                       g, t1, s.n1, t2);                                                     // a1
+    hipLaunchKernelGGL(k_soft_v, dim3((W + kTileX - 1) / kTileX, nty * B * D), dim3(256), 0, st,
+                       g, t2, (const float*)nullptr, t1);                                    // E2
+    hipLaunchKernelGGL(k_soft_h2, dim3(H, D, B), dim3(256), 0, st, g, t1, A2);             // A2
+    return hipGetLastError();
+}
+
+hipError_t soft_argmin(const SoftBuffers& s, int B, int W, int H, int D, const float* A2,
+                       const float* theta, float* dhat, float* lse, hipStream_t st) {
+    SoftGeom g{s.arms, s.n1, s.n2, B, W, H, D};
+    const size_t P = (size_t)W * H;
+    hipLaunchKernelGGL(k_soft_argmin, dim3((unsigned)((P + 255) / 256), B), dim3(256), 0, st, g,
+                       A2, theta, dhat, lse);
+    return hipGetLastError();
+}
+
+// Backward: A2 recomputed by the caller into `A2`; t1, t2 volume scratch.
+hipError_t soft_backward(const SoftBuffers& s, int B, int W, int H, int D, const float* A2,
+                         const float* theta, const float* dhat, const float* lse,
+                         const float* gdhat, float* t1, float* t2, double* partAC,
+                         double* partT, float* grad, hipStream_t st) {
+    SoftGeom g{s.arms, s.n1, s.n2, B, W, H, D};
+    SoftImg im{s.rgbL, s.rgbR, s.cenL, s.cenR, s.alpha, s.tab};
+    const size_t P = (size_t)W * H;
+    const unsigned nb = (unsigned)((P + 255) / 256);
+    const int nty = (H + kTileY - 1) / kTileY;
+    hipLaunchKernelGGL(k_soft_seed, dim3(nb, B), dim3(256), 0, st, g, A2, theta, dhat, lse, gdhat,
+                       t1, partT);                                              // G_A2 / N2
+    hipLaunchKernelGGL(k_soft_h_adj, dim3(H, D, B), dim3(256), 0, st, g, t1, t2);   // G_E2
+    hipLaunchKernelGGL(k_soft_v_adj, dim3((W + kTileX - 1) / kTileX, nty * B * D), dim3(256), 0,
+                       st, g, t2, s.n1, t1);                                    // G_a1 / N1
+    hipLaunchKernelGGL(k_soft_v_adj, dim3((W + kTileX - 1) / kTileX, nty * B * D), dim3(256), 0,
+                       st, g, t1, (const float*)nullptr, t2);                   // G_E1
+    hipLaunchKernelGGL(k_soft_h1_adj_grad, dim3(H, D, B), dim3(256), 0, st, g, im, t2, partAC);
+    hipLaunchKernelGGL(k_soft_reduce, dim3(1), dim3(256), 0, st, partAC, (size_t)B * D * H,
+                       partT, (size_t)B * nb, grad);
+    return hipGetLastError();
+}
