@@ -164,23 +164,31 @@ dco_status dco_stereo_stage_times(dco_stereo* h, float* ms, int n, int* calls);
 
 /* Create a batched matcher for n pairs of sizes W[i] x H[i], disparity
  * ranges D[i] (host arrays, each pair within the limits of
- * dco_stereo_create).  Runs the tile autotuner (or reads its cache file,
- * named by the environment variable DCO_AUTOTUNE_CACHE when set), builds
- * the device work list and captures one persistent launch in a HIP graph.
- * Synchronous. */
+ * dco_stereo_create).  For every distinct (W, H, D) the tile
+ * autotuner times the candidate aggregation tiles (rows per work item,
+ * disparities per work item) on a synthetic pair of that size, or reads the
+ * choice from its cache file (the environment variable DCO_AUTOTUNE_CACHE,
+ * default $HOME/.cache/dco_stereo_autotune.txt; DCO_AUTOTUNE=0 skips tuning
+ * and takes full-height bands of one disparity).  It then allocates each
+ * pair's scratch, builds the device work list (stages in order, longest
+ * aggregation items first) and captures its five stage launches (each a
+ * persistent work-list kernel over all pairs) in one HIP graph.  Synchronous. */
 dco_status dco_batch_create(dco_batch** out, int n, const int* W, const int* H, const int* D,
                             const dco_params* p, void* stream);
 void dco_batch_destroy(dco_batch* b);
 
-/* Match every pair with one graph launch.  L, R, disp, valid: host arrays of
- * n device pointers (images H x W x 3 uint8; disp H x W float; valid H x W
- * uint8).  Per-pair results are bit-identical to dco_stereo_match. */
+/* Match every pair with one graph launch on the stream given at create.
+ * L, R, disp, valid: host arrays of n device pointers (images H x W x 3
+ * uint8; disp H x W float; valid H x W uint8).  The pointers are copied to
+ * the device before the launch; the arrays may be reused on return.
+ * Per-pair results are bit-identical to dco_stereo_match. */
 dco_status dco_batch_match(dco_batch* b, const uint8_t* const* L, const uint8_t* const* R,
                            float* const* disp, uint8_t* const* valid);
 
-/* Tile shape the autotuner picked for pair i (out: tile width, tile height,
- * workgroups per CU); host pointers. */
-dco_status dco_batch_tile(const dco_batch* b, int i, int* tile_w, int* tile_h, int* occupancy);
+/* Tiles the autotuner picked for pair i (host pointers, out): output columns
+ * of an aggregation strip, rows of an aggregation band, disparities per
+ * aggregation work item. */
+dco_status dco_batch_tile(const dco_batch* b, int i, int* strip_w, int* band_h, int* d_chunk);
 
 /* ---- Differentiable soft-argmin form (left view) ---- */
 

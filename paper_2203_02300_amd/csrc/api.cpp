@@ -53,11 +53,10 @@ extern "C" dco_status dco_default_params(dco_params* out) {
     return DCO_OK;
 }
 
-static dco_status need(const void* ptr, const char* what);
 
 static bool pos_finite(float v) { return std::isfinite(v) && v > 0.0f; }
 
-static dco_status check_params(const dco_params& p) {
+dco_status check_params(const dco_params& p) {
     if (p.census_w < 1 || p.census_h < 1 || !(p.census_w & 1) || !(p.census_h & 1) ||
         p.census_w > 9 || p.census_h > 9 || p.census_w * p.census_h - 1 > 64) {
         dco_set_error("census window %d x %d: need odd sizes <= 9 with w*h-1 <= 64", p.census_w,
@@ -85,7 +84,7 @@ static dco_status check_params(const dco_params& p) {
     return DCO_OK;
 }
 
-static dco_status check_shape(int W, int H, int D, const dco_params& p) {
+dco_status check_shape(int W, int H, int D, const dco_params& p) {
     if (W < p.census_w || H < p.census_h || W > 16384 || H > 16384 || D < 1 || D >= W ||
         D > 32767 || (long long)W * H * D >= (1LL << 31)) {
         dco_set_error("shape W=%d H=%d D=%d: need 1 <= D < W, W >= census_w, H >= census_h, "
@@ -99,7 +98,7 @@ static dco_status check_shape(int W, int H, int D, const dco_params& p) {
 // Eq. 1 tables, evaluated in double and rounded once to float.  The AD and
 // census tables are stored scaled by 2^20 (an exact power-of-two scaling), so
 // a kernel's alpha_L * tabA[s] equals RN(alpha_L * TA[s]) * 2^20.
-static void build_tables(const dco_params& p, std::vector<float>& tabA, std::vector<float>& tabC,
+void build_tables(const dco_params& p, std::vector<float>& tabA, std::vector<float>& tabC,
                          std::vector<float>& alpha, std::vector<float>& beta) {
     tabA.assign(768, 0.0f);
     tabC.assign(65, 0.0f);
@@ -116,24 +115,6 @@ static void build_tables(const dco_params& p, std::vector<float>& tabA, std::vec
     for (int h = 0; h <= 64; ++h) tabC[h] = std::ldexp((float)(-std::expm1(-(double)h / lc)), 20);
 }
 
-template <class T>
-static dco_status dev_alloc(T** p, size_t n) {
-    *p = nullptr;
-    if (n == 0) return DCO_OK;
-    if (getenv("DCO_FAIL_ALLOC")) {
-        dco_set_error("allocation of %zu bytes refused (DCO_FAIL_ALLOC)", n * sizeof(T));
-        return DCO_ERR_OOM;
-    }
-    hipError_t e = hipMalloc((void**)p, n * sizeof(T));
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        dco_set_error("hipMalloc(%zu) failed: %s", n * sizeof(T), hipGetErrorString(e));
-        return e == hipErrorOutOfMemory ? DCO_ERR_OOM : DCO_ERR_HIP;
-    }
-    return DCO_OK;
-}
-
 static void free_handle_memory(dco_stereo* h) {
     void* ptrs[] = {h->tabA,         h->tabC,         h->alpha,        h->beta,
                     h->alpha_soft,   h->s.cen[0],     h->s.cen[1],     h->s.arms[0],
@@ -148,15 +129,9 @@ static void free_handle_memory(dco_stereo* h) {
         if (p) (void)hipFree(p);
 }
 
-#define DCO_TRY(expr)                      \
-    do {                                   \
-        dco_status _s = (expr);            \
-        if (_s != DCO_OK) return _s;       \
-    } while (0)
-
 // Aggregation records with a zero apron and a zero extra row (zeroed once:
 // the geometry kernel writes only the interior).
-static dco_status alloc_records(AggRecords* r, int W, int H) {
+dco_status alloc_records(AggRecords* r, int W, int H) {
     r->apron = kRecApronL;
     r->Wp = W + kRecApronL + kRecApronR;
     const size_t n = (size_t)r->Wp * (H + 1);
@@ -305,7 +280,7 @@ extern "C" dco_status dco_stereo_set_stream(dco_stereo* h, void* stream) {
     return DCO_OK;
 }
 
-static dco_status need(const void* ptr, const char* what) {
+dco_status need(const void* ptr, const char* what) {
     if (!ptr) {
         dco_set_error("%s is NULL", what);
         return DCO_ERR_ARG;
@@ -443,25 +418,6 @@ extern "C" dco_status dco_stereo_last_disparities(dco_stereo* h, int16_t* dL, in
         DCO_HIP_CHECK(hipMemcpyAsync(dR, h->s.dint[1], bytes, hipMemcpyDeviceToDevice, h->stream));
     return DCO_OK;
 }
-
-// ---- not yet built: batched and differentiable forms ----
-extern "C" dco_status dco_batch_create(dco_batch** out, int, const int*, const int*, const int*,
-                                       const dco_params*, void*) {
-    if (out) *out = nullptr;
-    dco_set_error("dco_batch_create: not available in this build");
-    return DCO_ERR_STATE;
-}
-extern "C" void dco_batch_destroy(dco_batch*) {}
-extern "C" dco_status dco_batch_match(dco_batch*, const uint8_t* const*, const uint8_t* const*,
-                                      float* const*, uint8_t* const*) {
-    dco_set_error("dco_batch_match: not available in this build");
-    return DCO_ERR_STATE;
-}
-extern "C" dco_status dco_batch_tile(const dco_batch*, int, int*, int*, int*) {
-    dco_set_error("dco_batch_tile: not available in this build");
-    return DCO_ERR_STATE;
-}
-
 
 // ---- differentiable soft-argmin form ----
 

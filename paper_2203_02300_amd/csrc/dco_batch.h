@@ -1,0 +1,54 @@
+// dco_batch.h -- data shared by the batched matcher's host code (batch.cpp)
+// and its persistent kernel (k_batch.hip).
+#pragma once
+
+#include "dco_internal.h"
+
+constexpr int kBatchStages = 5;  // census, records, cost + aggregation, WTA, LR
+constexpr int kWtaPx = 4096;     // pixels per WTA item
+constexpr int kLrRows = 16;      // rows per LR item
+
+// Static description and scratch of one pair.
+struct BatchPair {
+    int W, H, D, nstrips;
+    int band;     // output rows per aggregation item (tuned)
+    int dchunk;   // disparities per aggregation item (tuned)
+    int nitems[kBatchStages];
+    uint64_t* cen[2];
+    uint32_t* arms[2];
+    uint32_t* rgbp[2];
+    AggRecords rec[2];
+    float* agg[2];
+    int16_t* dint[2];
+    float* delta;
+};
+
+// Inputs and outputs of one pair for the current call.
+struct BatchIO {
+    const uint8_t* L;
+    const uint8_t* R;
+    float* disp;
+    uint8_t* valid;
+};
+
+struct BatchItem {
+    int pair, stage, view, a, b, c;
+};
+
+struct BatchArgs {
+    const BatchPair* pairs;
+    const BatchIO* io;
+    const BatchItem* items;   // stage-ordered work list
+    const float* tabA;
+    const float* tabC;
+    const float* alpha;
+    const float* beta;
+    int cw, ch, L1, tau1, subpixel, maxdiff;
+};
+
+// Launches the five stage kernels on `st`: stage s handles items
+// [first[s], first[s + 1]) with grid[s] workgroups.
+hipError_t launch_batch(const BatchArgs& a, int iters, const int* first, const int* grid,
+                        hipStream_t st);
+// Resident workgroups per CU of each stage kernel.
+void batch_blocks_per_cu(int iters, int* per_stage);

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 #include <vector>
 
@@ -115,6 +116,40 @@ void dco_set_error(const char* fmt, ...);
             return DCO_ERR_HIP;                                                    \
         }                                                                          \
     } while (0)
+
+#define DCO_TRY(expr)                \
+    do {                             \
+        dco_status _s = (expr);      \
+        if (_s != DCO_OK) return _s; \
+    } while (0)
+
+// hipMalloc of n elements with the library's error reporting (DCO_FAIL_ALLOC
+// in the environment makes it fail, to exercise the error paths).
+template <class T>
+inline dco_status dev_alloc(T** p, size_t n) {
+    *p = nullptr;
+    if (n == 0) return DCO_OK;
+    if (getenv("DCO_FAIL_ALLOC")) {
+        dco_set_error("allocation of %zu bytes refused (DCO_FAIL_ALLOC)", n * sizeof(T));
+        return DCO_ERR_OOM;
+    }
+    hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        dco_set_error("hipMalloc(%zu) failed: %s", n * sizeof(T), hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? DCO_ERR_OOM : DCO_ERR_HIP;
+    }
+    return DCO_OK;
+}
+
+// ---- host helpers shared by api.cpp and batch.cpp ----
+dco_status need(const void* ptr, const char* what);
+dco_status check_params(const dco_params& p);
+dco_status check_shape(int W, int H, int D, const dco_params& p);
+void build_tables(const dco_params& p, std::vector<float>& tabA, std::vector<float>& tabC,
+                  std::vector<float>& alpha, std::vector<float>& beta);
+dco_status alloc_records(AggRecords* r, int W, int H);
 
 // ---- kernel launchers (one per .hip file) ----
 hipError_t launch_census_arms(const uint8_t* rgb, int W, int H, int cw, int ch, int L1, int tau1,

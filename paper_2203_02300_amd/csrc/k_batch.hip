@@ -1,0 +1,149 @@
+// k_batch.hip -- the batched matcher's kernels: one persistent work-list
+// kernel per stage, all five captured in one HIP graph.
+//
+// The host builds a work list ordered by stage (0 census + arms of a 64 x 64
+// block, 1 region counts and records of a 64 x 64 block, 2 cost +
+// aggregation of d-chunk x column strip x row band, longest first, 3 WTA of
+// a pixel block, 4 LR check of a row block) over every pair of the batch.
+// The kernel of stage s runs a grid sized to the GPU's resident capacity; its
+// workgroup w takes the stage's items w, w + G, w + 2G, ...  The kernel
+// boundary is the barrier between stages, so workgroups never wait on each
+// other and need no atomics.
+//
+// Each stage runs the same device function as the one-call matcher
+// (dco_device.h), so per-pair results are bit-identical to dco_stereo_match.
+#include <type_traits>
+
+#include "dco_batch.h"
+#include "dco_device.h"
+
+namespace {
+
+// Rows per block-scan round of the batched aggregation: fewer than the
+// one-call kernel's, so that the stage kernel's item loop fits in registers
+// without spilling (the sums are exact, so every chunk size gives the same
+// result).
+constexpr int kBatchChunk = 4;
+
+struct NoLds {
+    int unused;
+};
+
+// LDS of each stage kernel: census tiles, aggregation rings, or none.
+template <int ITERS, int STAGE>
+using StageLds = typename std::conditional<
+    STAGE == 0, dco::CensusLds,
+    typename std::conditional<STAGE == 2, dco::AggLds<ITERS, true, kBatchChunk>, NoLds>::type>::type;
+
+template <int ITERS, int STAGE>
+__global__ __launch_bounds__(256, 2) void k_batch_stage(BatchArgs B, int first, int count) {
+    __shared__ StageLds<ITERS, STAGE> S;
+    const int t = threadIdx.x;
+    for (int k = blockIdx.x; k < count; k += gridDim.x) {
+        const BatchItem I = B.items[first + k];
+        const BatchPair& pr = B.pairs[I.pair];
+        const BatchIO& io = B.io[I.pair];
+        const int W = pr.W, H = pr.H;
+        if constexpr (STAGE == 0) {  // census + arms + packed RGB of a 64 x 64 block of one view
+            const uint8_t* img = I.view == 0 ? io.L : io.R;
+            for (int r = 0; r < 4; ++r) {
+                const int y0 = I.b * 64 + r * dco::kCenTH;
+                if (y0 >= H) break;
+                dco::census_tile(img, W, H, B.cw, B.ch, B.L1, B.tau1, pr.cen[I.view],
+                                 pr.arms[I.view], pr.rgbp[I.view], I.a * dco::kCenTW, y0, S);
+                __syncthreads();
+            }
+        } else if constexpr (STAGE == 1) {  // region counts and records of a 64 x 64 block
+            const int x = I.a * 64 + (t & 63);
+            for (int r = t >> 6; r < 64; r += 4) {
+                const int y = I.b * 64 + r;
+                if (x < W && y < H)
+                    dco::geometry_pixel(pr.arms[I.view], W, H, ITERS, pr.rec[I.view], x, y);
+            }
+        } else if constexpr (STAGE == 2) {  // slices a .. a+dchunk-1, strip b, row band c
+            dco::AggArgs A{};
+            A.rgbL = pr.rgbp[0];
+            A.rgbR = pr.rgbp[1];
+            A.cenL = pr.cen[0];
+            A.cenR = pr.cen[1];
+            A.tabA = B.tabA;
+            A.tabC = B.tabC;
+            A.alpha = B.alpha;
+            A.beta = B.beta;
+            A.rec = pr.rec[I.view];
+            A.out = pr.agg[I.view];
+            A.W = W;
+            A.H = H;
+            A.D = pr.D;
+            A.nstrips = pr.nstrips;
+            A.ref = I.view;
+            A.L1 = B.L1;
+            const int y0 = I.c * pr.band, y1 = min(H, y0 + pr.band);
+            const int dend = min(pr.D, I.a + pr.dchunk);
+            for (int d = I.a; d < dend; ++d) {
+                dco::agg_stream<ITERS, true, kBatchChunk>(A, d, I.b, y0, y1, S);
+                __syncthreads();
+            }
+        } else if constexpr (STAGE == 3) {  // WTA of both views for pixels [a, a + kWtaPx)
+            const int P = W * H;
+            for (int r = 0; r < kWtaPx / 256; ++r) {
+                const int i = I.a + r * 256 + t;
+                if (i >= P) break;
+                dco::wta_pixel(pr.agg[0], P, pr.D, i, B.subpixel, pr.dint[0] + i, pr.delta + i);
+                dco::wta_pixel(pr.agg[1], P, pr.D, i, B.subpixel, pr.dint[1] + i, nullptr);
+            }
+        } else {  // LR check of rows [a, a + kLrRows)
+            for (int y = I.a; y < min(H, I.a + kLrRows); ++y)
+                for (int x = t; x < W; x += 256)
+                    dco::lr_pixel(pr.dint[0], pr.delta, pr.dint[1], W, x, y, B.maxdiff,
+                                  io.disp, io.valid);
+        }
+        __syncthreads();
+    }
+}
+
+template <int ITERS, int STAGE>
+int stage_blocks_per_cu() {
+    int nb = 0;
+    hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_stage<ITERS, STAGE>, 256, 0);
+    return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+template <int ITERS>
+hipError_t launch_all(const BatchArgs& a, const int* first, const int* grid, hipStream_t st) {
+    hipLaunchKernelGGL((k_batch_stage<ITERS, 0>), dim3(grid[0]), dim3(256), 0, st, a, first[0],
+                       first[1] - first[0]);
+    hipLaunchKernelGGL((k_batch_stage<ITERS, 1>), dim3(grid[1]), dim3(256), 0, st, a, first[1],
+                       first[2] - first[1]);
+    hipLaunchKernelGGL((k_batch_stage<ITERS, 2>), dim3(grid[2]), dim3(256), 0, st, a, first[2],
+                       first[3] - first[2]);
+    hipLaunchKernelGGL((k_batch_stage<ITERS, 3>), dim3(grid[3]), dim3(256), 0, st, a, first[3],
+                       first[4] - first[3]);
+    hipLaunchKernelGGL((k_batch_stage<ITERS, 4>), dim3(grid[4]), dim3(256), 0, st, a, first[4],
+                       first[5] - first[4]);
+    return hipGetLastError();
+}
+
+template <int ITERS>
+void blocks_per_cu(int* per_stage) {
+    per_stage[0] = stage_blocks_per_cu<ITERS, 0>();
+    per_stage[1] = stage_blocks_per_cu<ITERS, 1>();
+    per_stage[2] = stage_blocks_per_cu<ITERS, 2>();
+    per_stage[3] = stage_blocks_per_cu<ITERS, 3>();
+    per_stage[4] = stage_blocks_per_cu<ITERS, 4>();
+}
+
+}  // namespace
+
+hipError_t launch_batch(const BatchArgs& a, int iters, const int* first, const int* grid,
+                        hipStream_t st) {
+    return iters == 1 ? launch_all<1>(a, first, grid, st) : launch_all<2>(a, first, grid, st);
+}
+
+void batch_blocks_per_cu(int iters, int* per_stage) {
+    if (iters == 1)
+        blocks_per_cu<1>(per_stage);
+    else
+        blocks_per_cu<2>(per_stage);
+}
