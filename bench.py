@@ -133,6 +133,13 @@ def main():
         extras["staged"] = staged_extras(m, gL, gR, args.steps)
     del m
     torch.cuda.empty_cache()
+    if not args.no_extras:
+        log("bench: batched matcher (32 mixed pairs)")
+        extras["batched"] = batched_extras(max(3, args.steps // 10))
+        torch.cuda.empty_cache()
+        log("bench: differentiable soft-argmin (8 x 640x480, D=64)")
+        extras["soft"] = soft_extras(max(3, args.steps // 10))
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu:
@@ -151,6 +158,88 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu, "extras": extras,
     }
     print(json.dumps(out), flush=True)
+
+
+def _time(fn, n):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(n):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def batched_extras(n):
+    """32 pairs of mixed size and disparity range: one graph launch per batch,
+    against the same pairs matched one by one with dco_stereo_match."""
+    import torch
+    from paper_2203_02300_amd import BatchMatcher, StereoMatcher, synth
+    pairs = synth.config_c4()
+    shapes = [(p["W"], p["H"], p["D"]) for p in pairs]
+    Ls = [torch.from_numpy(p["left"]).cuda() for p in pairs]
+    Rs = [torch.from_numpy(p["right"]).cuda() for p in pairs]
+    units = sum(W * H * D for W, H, D in shapes)
+    t0 = time.perf_counter()
+    bm = BatchMatcher(shapes)
+    create_s = time.perf_counter() - t0
+    disps = [torch.empty((H, W), device="cuda") for W, H, D in shapes]
+    valids = [torch.empty((H, W), dtype=torch.uint8, device="cuda") for W, H, D in shapes]
+    ms_batch = _time(lambda: bm.match(Ls, Rs, disps, valids), n)
+    tiles = [bm.tile(i) for i in range(len(shapes))]
+    bm.close()
+    ms_plain = 0.0
+    same = True
+    for i, (W, H, D) in enumerate(shapes):
+        with StereoMatcher(W, H, D) as m:
+            d, v = m.match(Ls[i], Rs[i])
+            ms_plain += _time(lambda: m.match(Ls[i], Rs[i], d, v), 2)
+            same &= bool(torch.equal(d, disps[i]) and torch.equal(v, valids[i]))
+    return dict(pairs=len(shapes), sum_WHD=units, ms_per_batch=round(ms_batch, 3),
+                ms_per_pair=round(ms_batch / len(shapes), 4),
+                Mpix_disp_s=round(units / (ms_batch / 1e3) / 1e6, 1),
+                plain_ms_sum=round(ms_plain, 3),
+                plain_Mpix_disp_s=round(units / (ms_plain / 1e3) / 1e6, 1),
+                speedup_vs_plain=round(ms_plain / ms_batch, 3), bit_identical_to_plain=same,
+                create_s=round(create_s, 2),
+                tiles_band_dchunk=sorted(set((t[1], t[2]) for t in tiles)))
+
+
+def soft_extras(n):
+    """Forward + backward of the soft-argmin head (8 pairs, 640x480, D=64)
+    against the plain matcher on the same 8 pairs."""
+    import torch
+    from paper_2203_02300_amd import StereoMatcher, synth
+    from paper_2203_02300_amd.soft import soft_argmin_disparity
+    pairs = synth.config_c5()
+    W, H, D = 640, 480, 64
+    L = torch.from_numpy(np.stack([p["left"] for p in pairs])).cuda()
+    R = torch.from_numpy(np.stack([p["right"] for p in pairs])).cuda()
+    gt = torch.from_numpy(np.stack([p["disp"] for p in pairs])).cuda()
+    mask = ~torch.from_numpy(np.stack([p["occluded"] for p in pairs])).cuda()
+    theta = torch.tensor([10.0, 40.0, 1.0], device="cuda", requires_grad=True)
+    m = StereoMatcher(W, H, D)
+
+    def step():
+        theta.grad = None
+        dhat = soft_argmin_disparity(m, L, R, theta)
+        loss = ((dhat - gt).abs() * mask).sum() / mask.sum()
+        loss.backward()
+        return loss
+
+    ms_fb = _time(step, n)
+    loss = float(step())
+    grad = theta.grad.detach().cpu().tolist()
+    ms_plain = _time(lambda: [m.match(L[b], R[b]) for b in range(L.shape[0])], n)
+    m.close()
+    units = L.shape[0] * W * H * D
+    return dict(pairs=int(L.shape[0]), ms_fwd_bwd=round(ms_fb, 3),
+                Mpix_disp_s=round(units / (ms_fb / 1e3) / 1e6, 1),
+                plain_ms=round(ms_plain, 3), ratio_to_plain=round(ms_fb / ms_plain, 3),
+                loss=round(loss, 4), grad_theta=[round(g, 6) for g in grad])
 
 
 def staged_extras(m, gL, gR, steps):
