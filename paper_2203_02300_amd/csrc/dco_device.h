@@ -106,8 +106,31 @@ __device__ inline void census_tile(const uint8_t* __restrict__ rgb, int W, int H
 //   N2 = sum over x' in [x-l, x+r] of (u(x',y) + dn(x',y) + 1)
 // Stage-1 rounding uses sh = 31 + ceil(log2 N1) and m = ceil(2^sh / N1) <
 // 2^32, so floor(n / N1) = (n * m) >> sh for every 0 <= n < 2^31 (N1 <= 2^11).
-// The final division uses (N, RN(1/N)) with N = N2 (two stages) or N1 (one).
-// Record layout: see AggRecords.
+// A final division by N uses N' = N * 2^20 and y' = RN(1/N) * 2^-20 (both
+// exact scalings), so that it also removes the Q20 scale (div_q20 below).
+//
+// The streaming kernel keeps row r of a column-prefix ring in slot r mod R,
+// so the byte offsets of the two prefix rows of a vertical range are fixed
+// per pixel and are stored here (16 bits each).
+
+constexpr int kAggK = kStripThreads / 64;             // rows per chunk = wavefronts (4)
+constexpr int kSeg = kStripThreads / 64;              // 64-column segments of a strip row
+constexpr int kRing1 = 2 * kLMax + 1 + kAggK;         // stage-1 prefix rows per column
+constexpr int kRing2 = 2 * kLMax + 2 + kAggK;         // stage 2 is read one chunk later
+constexpr int kRingCols = kStripThreads - 2 * kLMax;  // columns with a ring: 222
+constexpr int kRingStride = 224;                      // a multiple of the 32 LDS banks
+constexpr uint32_t kSlotBytes = kRingStride * 4;
+constexpr int kPStride = 280;                         // prefix row: P(-1) at 0, P(i) at i + 1
+constexpr uint32_t kOOB = 0x7fffffffu;                // buffer offset that reads as 0
+static_assert(kRing2 * kSlotBytes < 65536, "ring offsets are stored in 16 bits");
+static_assert(kStripThreads == 256 && kAggK == 4, "one row per wavefront per chunk");
+
+__device__ inline uint32_t ring_slot_bytes(int row, int ring) {
+    int s = row % ring;
+    if (s < 0) s += ring;
+    return (uint32_t)s * kSlotBytes;
+}
+
 __device__ inline void geometry_pixel(const uint32_t* __restrict__ arms, int W, int H, int iters,
                                       const AggRecords& rec, int x, int y) {
     const uint32_t a = arms[(size_t)y * W + x];
@@ -123,63 +146,71 @@ __device__ inline void geometry_pixel(const uint32_t* __restrict__ arms, int W, 
         uint32_t b = arms[(size_t)y * W + xx];
         n2 += ((b >> 16) & 0xff) + (b >> 24) + 1;
     }
-    const uint32_t lg = n1 <= 1 ? 0u : 32u - (uint32_t)__clz((int)(n1 - 1));
-    const uint32_t sh = 31u + lg;
-    const uint64_t num = (uint64_t)1 << sh;
-    const uint32_t m = (uint32_t)((num + n1 - 1) / n1);
-    const uint32_t n = iters == 1 ? n1 : n2;
-    const float rcp = 1.0f / (float)n;
+    const uint32_t lmin = min(min(l, r), min(u, dn));
+    const uint32_t lr = 4 * (r + 1) | (4 * l) << 8;
+    const uint32_t hi = (uint32_t)y + dn, lo = (uint32_t)y - u - 1;
     const size_t i = (size_t)y * rec.Wp + x + rec.apron;
-    rec.a[i] = a;
-    rec.b[i] = make_uint2(m, (n1 >> 1) | (sh << 10) | (u << 16) | (dn << 21));
-    rec.c[i] = make_uint2(__float_as_uint(rcp),
-                          l | (r << 5) | (u << 10) | (dn << 15) | (n << 20));
+    rec.a[i] = lr | (8 * lmin) << 16;
+    uint32_t* b = rec.b + 3 * i;
+    b[2] = ring_slot_bytes((int)hi, kRing1) | ring_slot_bytes((int)lo, kRing1) << 16;
+    if (iters == 2) {
+        const uint32_t lg = n1 <= 1 ? 0u : 32u - (uint32_t)__clz((int)(n1 - 1));
+        const uint32_t sh = 31u + lg;
+        const uint64_t num = (uint64_t)1 << sh;
+        b[0] = (uint32_t)((num + n1 - 1) / n1);
+        b[1] = (n1 >> 1) | (sh << 10);
+        rec.c[i] = make_uint4(ring_slot_bytes((int)hi, kRing2) |
+                                  ring_slot_bytes((int)lo, kRing2) << 16,
+                              lr, __float_as_uint((1.0f / (float)n2) * 0x1p-20f),
+                              __float_as_uint((float)n2 * 0x1p20f));
+    } else {
+        b[0] = __float_as_uint((1.0f / (float)n1) * 0x1p-20f);
+        b[1] = __float_as_uint((float)n1 * 0x1p20f);
+    }
 }
 
 // ===========================================================================
 // Streaming two-stage aggregation (Eq. 2 twice), one slice x one column strip
 // ===========================================================================
 //
-// The strip's 256 threads own 256 consecutive columns: 2 kLMax apron columns
-// on each side and kStripOut output columns in the middle.  The workgroup
-// streams down the rows; per row
-//   H1: E1 = row range sum of q             (block prefix scan + 2 LDS reads)
-//   V1: S1 = column range sum of E1         (per-column ring of prefix sums)
-//       a1 = floor((S1 + N1/2) / N1)        (exact multiply-shift division)
-//   V2: E2 = column range sum of a1         (second per-column ring)
-//   H2: S2 = row range sum of E2            (block prefix scan + 2 LDS reads)
-//       out = RN(S2 / N2) * 2^-20           (reciprocal + one FMA correction)
-// Each ring keeps the last kRing column-prefix rows of one column; only the
-// thread owning that column touches it.  Rows come in chunks of kRowChunk
-// (four barriers per chunk) and the next chunk's loads are issued before the
-// current chunk is processed.  V1 finalises row y - kLMax and H2 row
-// y - 2 kLMax - 1 while H1 consumes row y.
-//
-// Per-pixel data comes from the padded records (zero apron, zero row H)
-// through buffer loads with a per-lane column offset and a uniform row
-// offset, so the chunk body has no address arithmetic and no bounds branches.
+// A strip is 256 consecutive columns: 2 kLMax apron columns on each side and
+// kStripOut output columns in the middle.  The workgroup streams down the
+// rows in chunks of kAggK = 4 rows, in three steps per chunk:
+//   1 (wavefront w, row yc + w, all 256 columns as 4 segments of 64):
+//       raw cost q (fused: Eq. 1 from the images; staged: read), inclusive
+//       row prefix P1 by a wavefront scan per segment plus segment carries
+//   2 (thread t owns column t, rows yc .. yc + 3 in order):
+//       H1: E1 = P1(t + r) - P1(t - l - 1); push the column prefix of E1
+//       V1: S1 of row y - kLMax from two prefix rows of ring 1
+//           a1 = floor((S1 + N1/2) / N1) (multiply-shift), push into ring 2
+//   3 (wavefront w, output row y - 2 kLMax - 1 of row yc + w, 4 segments):
+//       V2: E2 from two prefix rows of ring 2; row prefix P2 as in step 1
+//       H2: S2 = P2(t + r) - P2(t - l - 1); out = RN(S2 / N2) * 2^-20
+// Two barriers per chunk: after step 1 (P1 rows) and after step 2 (ring 2,
+// and the end of step 2's reads of P1).  Row prefixes of steps 1 and 3 share
+// one LDS row per wavefront: only the wavefront that owns a row writes it.
+// Ring 1 holds kAggK - 1 rows more than a vertical range spans so that a
+// chunk's four pushes can precede its four range reads; ring 2 is read in
+// step 3, after all four pushes of step 2, so it holds kAggK rows more.
 //
 // Every sum is an integer and differences of prefix sums are taken mod 2^32
 // (every true range sum is below 2^31), so the result does not depend on the
 // summation order, and a band of output rows [y0, y1) can start from zero
 // prefixes 2 kLMax + 1 rows above y0: the rows before the start then shift
 // every prefix by the same constant.
+//
+// Per-pixel data comes from padded records (zero apron, zero row H) through
+// buffer loads with a per-lane column offset and a uniform row offset, so the
+// chunk body has no bounds branches.
 
-constexpr int kRingCols = kStripThreads - 2 * kLMax;  // ring columns used: 222
-constexpr int kRingStride = 224;
-constexpr int kPB = kStripThreads + 4;                // prefix row stride (P[-1] at 0)
-constexpr uint32_t kRingBytes = kRing * kRingStride * 4;
-constexpr uint32_t kOOB = 0x7fffffffu;                // buffer offset that reads as 0
-
-template <int ITERS, bool kFused, int K = kRowChunk>
+template <int ITERS, bool kFused>
 struct AggLds {
-    uint32_t ring1[kRing * kRingStride];
-    uint32_t ring2[ITERS == 2 ? kRing * kRingStride : 1];
-    uint32_t pbuf[K][kPB];
-    __attribute__((aligned(16))) uint32_t wsum[2][K][4];
+    uint32_t ring1[kRing1 * kRingStride];
+    uint32_t ring2[ITERS == 2 ? kRing2 * kRingStride : 1];
+    uint32_t prow[kAggK][kPStride];
     float tabA[kFused ? 768 : 1];
-    float tabC[kFused ? 65 : 1];
-    float ab[kFused ? 2 * (kLMax + 1) : 1];
+    float tabC[kFused ? 68 : 1];
+    float2 ab[kFused ? kLMax + 1 : 1];
 };
 
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
@@ -194,57 +225,49 @@ __device__ inline uint32_t ld32(rsrc_t r, uint32_t voff, uint32_t soff) {
 __device__ inline uint2 ld64(rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
+__device__ inline uint3 ld96(rsrc_t r, uint32_t voff, uint32_t soff) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0);
+    return make_uint3(v[0], v[1], v[2]);
+}
+__device__ inline uint4 ld128(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+__device__ inline void st32(float v, rsrc_t r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+}
 
 template <unsigned Ctrl, unsigned RowMask>
 __device__ inline uint32_t dpp(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, Ctrl, RowMask, 0xf, false);
 }
 
-// Inclusive scans of K rows at once across the 256 threads of the block.
-// Within a wavefront: DPP row shifts 1, 2, 4, 8 and the gfx9 row broadcasts
-// 15 and 31, issued step-major so that the K rows' steps interleave.  Across
-// the four wavefronts: totals through LDS.  Writes P(t) to pb[k][t + 1]
-// (pb[k][0] holds 0).  Two barriers; on return every thread sees every row.
-template <int K>
-__device__ inline void block_scan_rows(uint32_t (&v)[K], uint32_t (*pb)[kPB],
-                                       uint32_t (*ws)[4]) {
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+// Inclusive prefix sums of the kSeg segments across the wavefront: DPP row
+// shifts 1, 2, 4, 8 and the gfx9 row broadcasts 15 and 31, step-major so the
+// segments interleave; then each segment adds the totals of the ones before.
+__device__ inline void wave_scan_segments(uint32_t (&v)[kSeg]) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] += dpp<0x111, 0xf>(v[k]);
+    for (int j = 0; j < kSeg; ++j) v[j] += dpp<0x111, 0xf>(v[j]);
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] += dpp<0x112, 0xf>(v[k]);
+    for (int j = 0; j < kSeg; ++j) v[j] += dpp<0x112, 0xf>(v[j]);
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] += dpp<0x114, 0xf>(v[k]);
+    for (int j = 0; j < kSeg; ++j) v[j] += dpp<0x114, 0xf>(v[j]);
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] += dpp<0x118, 0xf>(v[k]);
+    for (int j = 0; j < kSeg; ++j) v[j] += dpp<0x118, 0xf>(v[j]);
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] += dpp<0x142, 0xa>(v[k]);
+    for (int j = 0; j < kSeg; ++j) v[j] += dpp<0x142, 0xa>(v[j]);
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] += dpp<0x143, 0xc>(v[k]);
-    if (lane == 63) {
+    for (int j = 0; j < kSeg; ++j) v[j] += dpp<0x143, 0xc>(v[j]);
+    uint32_t carry = 0;
 #pragma unroll
-        for (int k = 0; k < K; ++k) ws[k][w] = v[k];
+    for (int j = 0; j < kSeg; ++j) {
+        const uint32_t tot = __builtin_amdgcn_readlane(v[j], 63);
+        v[j] += carry;
+        carry += tot;
     }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const uint4 s = *reinterpret_cast<const uint4*>(ws[k]);
-        uint32_t off = 0;
-        if (w > 0) off += s.x;
-        if (w > 1) off += s.y;
-        if (w > 2) off += s.z;
-        pb[k][t + 1] = v[k] + off;
-    }
-    __syncthreads();
 }
 
-// Byte offset inside a ring of the row `back` rows behind the row whose slot
-// byte offset is `slot_off` (0 <= back < kRing).  The unsigned minimum picks
-// the wrapped value when the subtraction goes below zero.
-__device__ inline uint32_t ring_off(uint32_t slot_off, int back) {
-    const uint32_t a = slot_off - (uint32_t)back * (kRingStride * 4);
-    return min(a, a + kRingBytes);
-}
+// Wavefront index inside the workgroup, known to the compiler as uniform.
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6); }
 
 __device__ inline uint32_t lds_ld(const uint32_t* base, uint32_t byte_off) {
     return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(base) + byte_off);
@@ -253,14 +276,16 @@ __device__ inline void lds_st(uint32_t* base, uint32_t byte_off, uint32_t v) {
     *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 
-// RN((float)s / N) given N and RN(1/N).  Exact: q0 = RN(s * y) is within two
-// ulps of s/N, r = s - q0 * N is then exact, and s/N is never a float
-// midpoint for integer N, so RN(q0 + r * y) = RN(s / N).
-__device__ inline float div_rn(uint32_t s, float n, float rcp) {
+// RN((float)s / N) * 2^-20 given N' = N * 2^20 and y' = RN(1/N) * 2^-20.
+// With y = RN(1/N): q0 = RN(s * y) is within two ulps of s/N, r = s - q0 * N
+// is then exact, and s/N is never a float midpoint for integer N, so
+// RN(q0 + r * y) = RN(s / N).  Scaling y and q0 by 2^-20 and N by 2^20 is
+// exact and commutes with the roundings (no result is subnormal).
+__device__ inline float div_q20(uint32_t s, float n_scaled, float rcp_scaled) {
     const float a = (float)s;
-    const float q0 = a * rcp;
-    const float r = __builtin_fmaf(-q0, n, a);
-    return __builtin_fmaf(r, rcp, q0);
+    const float q0 = a * rcp_scaled;
+    const float r = __builtin_fmaf(-q0, n_scaled, a);
+    return __builtin_fmaf(r, rcp_scaled, q0);
 }
 
 struct AggArgs {
@@ -278,193 +303,234 @@ struct AggArgs {
     int W, H, D, nstrips, ref, L1;
 };
 
-// Everything one thread loads for one row step: rows y (H1), y - kLMax (V1)
-// and y - 2 kLMax - 1 (V2, H2; row y - kLMax for one stage) of its column.
+// Loads of one chunk.  Step 1 and step 3 loads are for this lane's four
+// segment columns of its wavefront's row; step 2 loads are for the owned
+// column and the chunk's four rows.
 template <bool kFused>
-struct RowData {
-    uint32_t q;        // staged: q of row y; fused: 0 or ~0 (row inside the image)
-    uint32_t rrgb, prgb;
-    uint2 rcen, pcen;  // fused: reference and partner census words
-    uint32_t recA;     // arms of row y
-    uint2 recB;        // stage-1 division data and vertical arms of row y - kLMax
-    uint2 recC;        // final division data and arms of the output row
+struct ChunkIn {
+    uint32_t q[kSeg];           // staged: raw cost bits; fused: reference RGB
+    uint32_t prgb[kSeg];        // fused: partner RGB
+    uint2 rcen[kSeg], pcen[kSeg];
+    uint32_t a1[kSeg];          // step 1: records a (shortest arm)
+    uint32_t a2[kAggK];         // step 2: records a of rows yc + k
+    uint3 b2[kAggK];            // step 2: records b of rows yc + k - kLMax
+    uint4 c3[kSeg];             // step 3: records c of the output row
 };
 
-struct Lane {
-    uint32_t rec4, rec8;     // record byte offsets of this column (4- and 8-byte records)
-    uint32_t img4, img8;     // byte offsets of the clamped column in H x W maps
-    uint32_t par4, par8;     // fused: the partner column
-    uint32_t col_mask;       // ~0 when the column is inside the image
-    uint32_t par_ok;         // ~0 when the partner column is inside the image
+// Per-lane constants of a strip.
+struct AggLane {
+    uint32_t img[kSeg];   // byte offset (x4) of each segment column in an H x W map, or kOOB
+    uint32_t par[kSeg];   // fused: the partner column, or kOOB
+    uint32_t okm[kSeg];   // fused: ~0 when the partner is inside the image, else 0
+    uint32_t inval[kSeg]; // fused: raw cost when the partner is outside (2^20; 0 off-image)
+    uint32_t recw;        // record column offset (x4) of segment 0 of this lane
+    uint32_t reco;        // record column offset (x4) of the owned column
+    uint32_t cb1, cb2;    // ring byte offsets of the owned column
+    uint32_t cbs[kSeg];   // ring-2 byte offset of each segment column
+    uint32_t vout[kSeg];  // output byte offset of each segment column, or kOOB
+    uint32_t vout_o;      // output byte offset of the owned column, or kOOB (one stage)
+    bool rok[kSeg];       // segment column has a ring
 };
 
 struct AggRes {
-    rsrc_t rA, rB, rC, rq, rIr, rIp, rCr, rCp;
+    rsrc_t rA, rB, rC, rq, rIr, rIp, rCr, rCp, rOut;
 };
 
-template <int ITERS, bool kFused, int K>
-__device__ inline void load_rows(const AggArgs& A, int yc, const Lane& ln, const AggRes& R,
-                                 RowData<kFused> (&rd)[K]) {
+template <int ITERS, bool kFused>
+__device__ inline void load_chunk(const AggArgs& A, int yc, const AggLane& ln, const AggRes& R,
+                                  ChunkIn<kFused>& in) {
     const int H = A.H;
     const uint32_t Wp = (uint32_t)A.rec.Wp, W = (uint32_t)A.W;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int y = yc + k;
-        const int y1 = y - kLMax;
-        const int yo = ITERS == 2 ? y - 2 * kLMax - 1 : y1;
-        // records: rows outside the image map to the zero row H
-        const uint32_t ra = (uint32_t)(y < H ? y : H);
-        const uint32_t rb = (uint32_t)(y1 >= 0 && y1 < H ? y1 : H);
-        const uint32_t rc = (uint32_t)(yo >= 0 && yo < H ? yo : H);
-        rd[k].recA = ld32(R.rA, ln.rec4, ra * Wp * 4);
-        rd[k].recB = ld64(R.rB, ln.rec8, rb * Wp * 8);
-        rd[k].recC = ld64(R.rC, ln.rec8, rc * Wp * 8);
+    const int w = wave_id();
+    {   // step 1: row yc + w
+        const int y = yc + w;
         const uint32_t yq = (uint32_t)min(y, H - 1);
-        const uint32_t row_mask = y < H ? ~0u : 0u;
-        if (kFused) {
-            rd[k].rrgb = ld32(R.rIr, ln.img4, yq * W * 4);
-            rd[k].prgb = ld32(R.rIp, ln.par4, yq * W * 4);
-            rd[k].rcen = ld64(R.rCr, ln.img8, yq * W * 8);
-            rd[k].pcen = ld64(R.rCp, ln.par8, yq * W * 8);
-            rd[k].q = row_mask;
-        } else {
-            const float v = __builtin_bit_cast(float, ld32(R.rq, ln.img4, yq * W * 4));
-            rd[k].q = (uint32_t)(v * 1048576.0f) & row_mask;
-        }
-    }
-}
-
-template <int ITERS, bool kFused, int K>
-__device__ inline void process_rows(int yc, int y0, int y1, int W, int c, int t, bool ring_thr,
-                                    bool out_thr, const Lane& ln, float* __restrict__ out,
-                                    RowData<kFused> (&rd)[K], uint32_t& cp1, uint32_t& cp2,
-                                    uint32_t& slot_off, uint32_t* ring1, uint32_t* ring2,
-                                    AggLds<ITERS, kFused, K>& S) {
-    uint32_t v[K];
+        const uint32_t ra = (uint32_t)(y < H ? y : H);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        if (kFused) {
-            const uint32_t a = rd[k].recA;
-            const int lmin = min(min((int)(a & 0xff), (int)((a >> 8) & 0xff)),
-                                 min((int)((a >> 16) & 0xff), (int)(a >> 24)));
-            const uint32_t s = __builtin_amdgcn_sad_u8(rd[k].rrgb, rd[k].prgb, 0u);
-            const int h =
-                __popc(rd[k].rcen.x ^ rd[k].pcen.x) + __popc(rd[k].rcen.y ^ rd[k].pcen.y);
-            const float qa = __builtin_rintf(S.ab[lmin] * S.tabA[s]);
-            const float qc = __builtin_rintf(S.ab[kLMax + 1 + lmin] * S.tabC[h]);
-            const uint32_t qv = ln.par_ok ? (uint32_t)qa + (uint32_t)qc : (1u << 20);
-            v[k] = qv & rd[k].q & ln.col_mask;
-        } else {
-            v[k] = rd[k].q;
-        }
-    }
-    block_scan_rows<K>(v, S.pbuf, S.wsum[0]);
-
-    uint32_t e2[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        {   // H1: E1 of row y = yc + k, pushed as the column prefix of row y
-            const uint32_t a = rd[k].recA;
-            const int l = a & 0xff, r = (a >> 8) & 0xff;
-            const uint32_t e1 = S.pbuf[k][t + r + 1] - S.pbuf[k][t - l];
-            cp1 += e1;
-            lds_st(ring1, slot_off, cp1);
-        }
-        if (ITERS == 2) {
-            // V2: E2 of row y - 2 kLMax - 1 from the a1 prefix rows: row
-            // y2 + dn is 2 kLMax + 1 - dn rows behind y, row y2 - u - 1 shares
-            // the slot of row y - u
-            const uint32_t g = rd[k].recC.y;
-            const int u = (g >> 10) & 31, dn = (g >> 15) & 31;
-            const uint32_t e = lds_ld(ring2, ring_off(slot_off, 2 * kLMax + 1 - dn)) -
-                               lds_ld(ring2, ring_off(slot_off, u));
-            e2[k] = ring_thr ? e : 0u;
-        }
-        {   // V1: S1 of row yv = y - kLMax (prefix rows yv - u - 1 .. yv + dn)
-            const uint32_t g = rd[k].recB.y;
-            const int u = (g >> 16) & 31, dn = (g >> 21) & 31;
-            const uint32_t s1 = lds_ld(ring1, ring_off(slot_off, kLMax - dn)) -
-                                lds_ld(ring1, ring_off(slot_off, kLMax + u + 1));
-            if (ITERS == 2) {
-                const uint64_t n = (uint64_t)(s1 + (g & 1023));
-                cp2 += (uint32_t)((n * rd[k].recB.x) >> ((g >> 10) & 63));
-                lds_st(ring2, ring_off(slot_off, kLMax), cp2);
+        for (int j = 0; j < kSeg; ++j) {
+            in.a1[j] = kFused ? ld32(R.rA, ln.recw + 256 * j, ra * Wp * 4) : 0u;
+            if (kFused) {
+                in.q[j] = ld32(R.rIr, ln.img[j], yq * W * 4);
+                in.prgb[j] = ld32(R.rIp, ln.par[j], yq * W * 4);
+                in.rcen[j] = ld64(R.rCr, ln.img[j] * 2, yq * W * 8);
+                in.pcen[j] = ld64(R.rCp, ln.par[j] * 2, yq * W * 8);
             } else {
-                const int yv = yc + k - kLMax;
-                const uint32_t gc = rd[k].recC.y;
-                const float a1 =
-                    div_rn(s1, (float)(gc >> 20), __builtin_bit_cast(float, rd[k].recC.x));
-                if (out_thr && yv >= y0 && yv < y1) out[(size_t)yv * W + c] = a1 * 0x1p-20f;
+                in.q[j] = ld32(R.rq, ln.img[j], yq * W * 4);
             }
         }
-        slot_off = slot_off + kRingStride * 4 == kRingBytes ? 0u : slot_off + kRingStride * 4;
     }
-    if (ITERS == 2) {
-        block_scan_rows<K>(e2, S.pbuf, S.wsum[1]);
-        float a2[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {  // H2: S2 of row y - 2 kLMax - 1
-            const uint32_t g = rd[k].recC.y;
-            const int l = g & 31, r = (g >> 5) & 31;
-            const uint32_t s2 = S.pbuf[k][t + r + 1] - S.pbuf[k][t - l];
-            a2[k] = div_rn(s2, (float)(g >> 20), __builtin_bit_cast(float, rd[k].recC.x)) *
-                    0x1p-20f;
-        }
-        if (out_thr) {
+    for (int k = 0; k < kAggK; ++k) {  // step 2: rows yc + k and yc + k - kLMax
+        const int y = yc + k, yv = y - kLMax;
+        const uint32_t ra = (uint32_t)(y < H ? y : H);
+        const uint32_t rb = (uint32_t)(yv >= 0 && yv < H ? yv : H);
+        in.a2[k] = ld32(R.rA, ln.reco, ra * Wp * 4);
+        in.b2[k] = ld96(R.rB, ln.reco * 3, rb * Wp * 12);
+    }
+    if (ITERS == 2) {  // step 3: output row yc + w - 2 kLMax - 1
+        const int y2 = yc + w - 2 * kLMax - 1;
+        const uint32_t rc = (uint32_t)(y2 >= 0 && y2 < H ? y2 : H);
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int y2 = yc + k - 2 * kLMax - 1;
-                if (y2 >= y0 && y2 < y1) out[(size_t)y2 * W + c] = a2[k];
+        for (int j = 0; j < kSeg; ++j) in.c3[j] = ld128(R.rC, ln.recw * 4 + 1024 * j, rc * Wp * 16);
+    }
+}
+
+template <int ITERS, bool kFused>
+__device__ inline void process_chunk(const AggArgs& A, int yc, int y0, int y1, const AggLane& ln,
+                                     const AggRes& R, const ChunkIn<kFused>& in,
+                                     uint32_t& cp1, uint32_t& cp2, uint32_t& s1off,
+                                     uint32_t& s2off, AggLds<ITERS, kFused>& S) {
+    const int t = threadIdx.x, w = wave_id(), lane = t & 63;
+    const int H = A.H, W = A.W;
+    uint32_t* prow_w = S.prow[w];
+    // ---- step 1: raw costs and row prefixes of row yc + w ----
+    {
+        const int y = yc + w;
+        uint32_t v[kSeg];
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) {
+            uint32_t q;
+            if (kFused) {
+                const uint32_t s = __builtin_amdgcn_sad_u8(in.q[j], in.prgb[j], 0u);
+                const uint32_t h = __popc(in.rcen[j].x ^ in.pcen[j].x) +
+                                   __popc(in.rcen[j].y ^ in.pcen[j].y);
+                const float2 ab = *reinterpret_cast<const float2*>(
+                    reinterpret_cast<const char*>(S.ab) + (in.a1[j] >> 16));
+                const float qa = __builtin_rintf(ab.x * S.tabA[s]);
+                const float qc = __builtin_rintf(ab.y * S.tabC[h]);
+                // blend with lane masks rather than a branch, so the four
+                // segments' lookups stay interleaved
+                q = ((uint32_t)(qa + qc) & ln.okm[j]) | ln.inval[j];
+            } else {
+                q = (uint32_t)(__builtin_bit_cast(float, in.q[j]) * 1048576.0f);
             }
+            v[j] = y < H ? q : 0u;
+        }
+        wave_scan_segments(v);
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) prow_w[64 * j + lane + 1] = v[j];
+    }
+    __syncthreads();
+    // ---- step 2: column prefixes, stage-1 means of rows yc + k - kLMax ----
+    // Ring 1 keeps kAggK - 1 rows more than a range needs, so the chunk's
+    // four pushes can all go before its four range reads.
+    uint32_t e1[kAggK], s1[kAggK];
+#pragma unroll
+    for (int k = 0; k < kAggK; ++k) {
+        const uint32_t a = in.a2[k];
+        const uint32_t pb = (uint32_t)(k * kPStride + t) * 4;
+        e1[k] = lds_ld(S.prow[0], pb + (a & 0xff)) - lds_ld(S.prow[0], pb - ((a >> 8) & 0xff));
+    }
+    uint32_t off = s1off;
+#pragma unroll
+    for (int k = 0; k < kAggK; ++k) {
+        cp1 += e1[k];
+        lds_st(S.ring1, ln.cb1 + off, cp1);
+        off = off + kSlotBytes == kRing1 * kSlotBytes ? 0u : off + kSlotBytes;
+    }
+    s1off = off;
+#pragma unroll
+    for (int k = 0; k < kAggK; ++k) {
+        const uint32_t o = in.b2[k].z;
+        s1[k] = lds_ld(S.ring1, ln.cb1 + (o & 0xffff)) - lds_ld(S.ring1, ln.cb1 + (o >> 16));
+    }
+#pragma unroll
+    for (int k = 0; k < kAggK; ++k) {
+        const uint3 b = in.b2[k];
+        if (ITERS == 2) {
+            const uint64_t n = (uint64_t)(s1[k] + (b.y & 1023)) * b.x;
+            cp2 += (uint32_t)(n >> (b.y >> 10));
+            lds_st(S.ring2, ln.cb2 + s2off, cp2);
+            s2off = s2off + kSlotBytes == kRing2 * kSlotBytes ? 0u : s2off + kSlotBytes;
+        } else {
+            const int yv = yc + k - kLMax;
+            const float a1 = div_q20(s1[k], __builtin_bit_cast(float, b.y),
+                                     __builtin_bit_cast(float, b.x));
+            if (yv >= y0 && yv < y1) st32(a1, R.rOut, ln.vout_o, (uint32_t)(yv * W) * 4);
+        }
+    }
+    __syncthreads();
+    if (ITERS == 2) {
+        // ---- step 3: stage-2 means of output row yc + w - 2 kLMax - 1 ----
+        const int y2 = yc + w - 2 * kLMax - 1;
+        uint32_t v[kSeg];
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) {
+            const uint32_t o = in.c3[j].x;
+            const uint32_t e = lds_ld(S.ring2, ln.cbs[j] + (o & 0xffff)) -
+                               lds_ld(S.ring2, ln.cbs[j] + (o >> 16));
+            v[j] = ln.rok[j] ? e : 0u;
+        }
+        wave_scan_segments(v);
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) prow_w[64 * j + lane + 1] = v[j];
+        // the row was written by this wavefront only: LDS keeps its order
+        float out[kSeg];
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) {
+            const uint32_t lr = in.c3[j].y;
+            const uint32_t pb = (uint32_t)(64 * j + lane) * 4;
+            const uint32_t s2 = lds_ld(prow_w, pb + (lr & 0xff)) - lds_ld(prow_w, pb - ((lr >> 8) & 0xff));
+            out[j] = div_q20(s2, __builtin_bit_cast(float, in.c3[j].w),
+                             __builtin_bit_cast(float, in.c3[j].z));
+        }
+        if (y2 >= y0 && y2 < y1) {
+#pragma unroll
+            for (int j = 0; j < kSeg; ++j) st32(out[j], R.rOut, ln.vout[j], (uint32_t)(y2 * W) * 4);
         }
     }
 }
 
-// Output rows [y0, y1) of slice d and column strip `strip` (256 threads),
-// K rows per block-scan round.
-template <int ITERS, bool kFused, int K = kRowChunk>
+// Output rows [y0, y1) of slice d and column strip `strip` (256 threads).
+template <int ITERS, bool kFused>
 __device__ inline void agg_stream(const AggArgs& A, int d, int strip, int y0, int y1,
-                                  AggLds<ITERS, kFused, K>& S) {
+                                  AggLds<ITERS, kFused>& S) {
     const int W = A.W, H = A.H;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63;
     const int x0 = strip * kStripOut;
-    const int c = x0 - 2 * kLMax + t;
-    const bool in_img = c >= 0 && c < W;
-    const int cc = min(max(c, 0), W - 1);
-    const int j = t - kLMax;
-    const bool ring_thr = j >= 0 && j < kRingCols;
-    // threads without a ring column share two scratch columns
-    const int jj = ring_thr ? j : kRingCols + (t & 1);
-    const bool out_thr = t >= 2 * kLMax && t < 2 * kLMax + kStripOut && c < W;
     const size_t slice = (size_t)W * H;
-    float* out = A.out + (size_t)d * slice;
 
     if (kFused) {
         for (int i = t; i < 766; i += kStripThreads) S.tabA[i] = A.tabA[i];
         if (t < 65) S.tabC[t] = A.tabC[t];
         if (t <= kLMax) {
             const int L = min(t, A.L1);
-            S.ab[t] = A.alpha[L];
-            S.ab[kLMax + 1 + t] = A.beta[L];
+            S.ab[t] = make_float2(A.alpha[L], A.beta[L]);
         }
     }
-    if (t < K) S.pbuf[t][0] = 0;  // P(-1) of every prefix row
+    if (t < kAggK) S.prow[t][0] = 0;  // P(-1) of every prefix row
     // zero column prefixes: rows before the start contribute nothing
-    for (int i = t; i < kRing * kRingStride; i += kStripThreads) {
-        S.ring1[i] = 0;
-        if (ITERS == 2) S.ring2[i] = 0;
+    for (int i = t; i < kRing1 * kRingStride; i += kStripThreads) S.ring1[i] = 0;
+    if (ITERS == 2)
+        for (int i = t; i < kRing2 * kRingStride; i += kStripThreads) S.ring2[i] = 0;
+
+    AggLane ln;
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j) {
+        const int i = 64 * j + lane;            // strip column of segment j
+        const int c = x0 - 2 * kLMax + i;       // image column
+        const bool in_img = c >= 0 && c < W;
+        const int cp = A.ref == 0 ? c - d : c + d;
+        const bool pok = in_img && cp >= 0 && cp < W;
+        ln.img[j] = in_img ? (uint32_t)c * 4 : kOOB;
+        ln.par[j] = pok ? (uint32_t)cp * 4 : kOOB;
+        ln.okm[j] = pok ? ~0u : 0u;
+        ln.inval[j] = in_img && !pok ? (1u << 20) : 0u;
+        ln.rok[j] = i >= kLMax && i < kLMax + kRingCols;
+        ln.cbs[j] = (uint32_t)(ln.rok[j] ? i - kLMax : kRingCols) * 4;
+        ln.vout[j] = i >= 2 * kLMax && i < 2 * kLMax + kStripOut && c < W ? (uint32_t)c * 4 : kOOB;
     }
-    const int cp = A.ref == 0 ? c - d : c + d;
-    const int cpc = min(max(cp, 0), W - 1);
-    Lane ln;
-    ln.rec4 = (uint32_t)(c + A.rec.apron) * 4;
-    ln.rec8 = (uint32_t)(c + A.rec.apron) * 8;
-    ln.img4 = in_img ? (uint32_t)cc * 4 : kOOB;
-    ln.img8 = (uint32_t)cc * 8;
-    ln.par4 = (uint32_t)cpc * 4;
-    ln.par8 = (uint32_t)cpc * 8;
-    ln.col_mask = in_img ? ~0u : 0u;
-    ln.par_ok = in_img && cp >= 0 && cp < W ? ~0u : 0u;
+    {
+        const int c = x0 - 2 * kLMax + t;
+        const int jj = t - kLMax;
+        const bool ring = jj >= 0 && jj < kRingCols;
+        // owners without a ring column share two scratch columns
+        ln.cb1 = (uint32_t)(ring ? jj : kRingCols + (t & 1)) * 4;
+        ln.cb2 = ln.cb1;
+        ln.reco = (uint32_t)(c + A.rec.apron) * 4;
+        ln.recw = (uint32_t)(x0 - 2 * kLMax + lane + A.rec.apron) * 4;
+        ln.vout_o = t >= 2 * kLMax && t < 2 * kLMax + kStripOut && c < W ? (uint32_t)c * 4 : kOOB;
+    }
     const uint32_t recN = (uint32_t)(A.rec.Wp * (H + 1));
     const uint32_t P4 = (uint32_t)(slice * 4);
     const uint32_t* Iref = A.ref == 0 ? A.rgbL : A.rgbR;
@@ -473,16 +539,16 @@ __device__ inline void agg_stream(const AggArgs& A, int d, int strip, int y0, in
     const uint64_t* Cpar = A.ref == 0 ? A.cenR : A.cenL;
     AggRes R;
     R.rA = make_rsrc(A.rec.a, recN * 4);
-    R.rB = make_rsrc(A.rec.b, recN * 8);
-    R.rC = make_rsrc(A.rec.c, recN * 8);
-    R.rq = make_rsrc(
-        kFused ? (const void*)A.rec.a : (const void*)(A.cost + (size_t)d * slice), P4);
-    R.rIr = make_rsrc(kFused ? (const void*)Iref : nullptr, P4);
-    R.rIp = make_rsrc(kFused ? (const void*)Ipar : nullptr, P4);
-    R.rCr = make_rsrc(kFused ? (const void*)Cref : nullptr, 2 * P4);
-    R.rCp = make_rsrc(kFused ? (const void*)Cpar : nullptr, 2 * P4);
-    uint32_t* r1 = S.ring1 + jj;
-    uint32_t* r2 = S.ring2 + (ITERS == 2 ? jj : 0);
+    R.rB = make_rsrc(A.rec.b, recN * 12);
+    R.rC = make_rsrc(ITERS == 2 ? (const void*)A.rec.c : (const void*)A.rec.a,
+                     ITERS == 2 ? recN * 16 : recN * 4);
+    R.rq = make_rsrc(kFused ? (const void*)A.rec.a : (const void*)(A.cost + (size_t)d * slice),
+                     kFused ? recN * 4 : P4);
+    R.rIr = make_rsrc(kFused ? (const void*)Iref : (const void*)A.rec.a, kFused ? P4 : 0u);
+    R.rIp = make_rsrc(kFused ? (const void*)Ipar : (const void*)A.rec.a, kFused ? P4 : 0u);
+    R.rCr = make_rsrc(kFused ? (const void*)Cref : (const void*)A.rec.a, kFused ? 2 * P4 : 0u);
+    R.rCp = make_rsrc(kFused ? (const void*)Cpar : (const void*)A.rec.a, kFused ? 2 * P4 : 0u);
+    R.rOut = make_rsrc(A.out + (size_t)d * slice, P4);
     __syncthreads();
 
     // warm-up rows so that the first output row sees complete ranges
@@ -490,18 +556,18 @@ __device__ inline void agg_stream(const AggArgs& A, int d, int strip, int y0, in
     const int ys = max(0, y0 - warm);
     const int yend = y1 + warm;
     uint32_t cp1 = 0, cp2 = 0;
-    uint32_t slot_off = 0;  // ring byte offset of the current row
-    RowData<kFused> ra[K], rb[K];
-    load_rows<ITERS, kFused, K>(A, ys, ln, R, ra);
-    for (int yc = ys; yc < yend; yc += 2 * K) {
+    uint32_t s1off = ring_slot_bytes(ys, kRing1);
+    uint32_t s2off = ring_slot_bytes(ys - kLMax, kRing2);
+    ChunkIn<kFused> ca, cb;
+    load_chunk<ITERS, kFused>(A, ys, ln, R, ca);
+    for (int yc = ys; yc < yend; yc += 2 * kAggK) {
         // the next chunk's loads are in flight while this chunk is processed
-        load_rows<ITERS, kFused, K>(A, yc + K, ln, R, rb);
-        process_rows<ITERS, kFused, K>(yc, y0, y1, W, c, t, ring_thr, out_thr, ln, out, ra, cp1,
-                                       cp2, slot_off, r1, r2, S);
-        if (yc + K >= yend) break;
-        load_rows<ITERS, kFused, K>(A, yc + 2 * K, ln, R, ra);
-        process_rows<ITERS, kFused, K>(yc + K, y0, y1, W, c, t, ring_thr, out_thr, ln, out, rb,
-                                       cp1, cp2, slot_off, r1, r2, S);
+        load_chunk<ITERS, kFused>(A, yc + kAggK, ln, R, cb);
+        process_chunk<ITERS, kFused>(A, yc, y0, y1, ln, R, ca, cp1, cp2, s1off, s2off, S);
+        if (yc + kAggK >= yend) break;
+        load_chunk<ITERS, kFused>(A, yc + 2 * kAggK, ln, R, ca);
+        process_chunk<ITERS, kFused>(A, yc + kAggK, y0, y1, ln, R, cb, cp1, cp2, s1off, s2off,
+                                     S);
     }
 }
 

@@ -14,28 +14,26 @@
 // Largest arm length the kernels are built for.  The aggregation halo is
 // 2 * kLMax columns/rows on each side of an output pixel.
 constexpr int kLMax = 17;
-// Rows of column-prefix history one streaming column keeps: a vertical range
-// [y - u - 1, y + dn] spans at most 2 * kLMax + 2 prefix rows.
-constexpr int kRing = 2 * kLMax + 2;
 // Threads of a streaming-aggregation workgroup = input columns of a strip.
 constexpr int kStripThreads = 256;
 // Output columns of one strip.
 constexpr int kStripOut = kStripThreads - 4 * kLMax;
-// Rows processed per block-scan round in the streaming kernels.
-constexpr int kRowChunk = 8;
 
 // Packed per-pixel records of one view for the aggregation kernels, written
 // by k_geometry.  Each array has H + 1 rows of Wp entries; pixel (x, y) sits
 // at y * Wp + x + apron, and the apron columns and row H are zero.
-//   a[p] = l | r << 8 | u << 16 | dn << 24                        (arms)
-//   b[p] = (m, half | sh << 10 | u << 16 | dn << 21)   stage-1 rounding
-//          floor((S1 + half) / N1) = ((S1 + half) * m) >> sh, half = N1 / 2
-//   c[p] = (bits of RN(1/N), l | r << 5 | u << 10 | dn << 15 | N << 20)
-//          with N = N2 for two stages and N1 for one
+//   a[p] = 4 (r + 1) | 4 l << 8 | 8 L_min << 16          (horizontal arms, alpha index)
+//   b[p] = three words for the stage-1 vertical range of p:
+//          two stages: m, N1 / 2 | sh << 10  with floor((S1 + N1/2) / N1) =
+//                      ((S1 + N1/2) * m) >> sh
+//          one stage:  RN(1/N1) * 2^-20, N1 * 2^20   (floats)
+//          then the ring-1 byte offsets of prefix rows y + dn | y - u - 1 << 16
+//   c[p] = ring-2 byte offsets of prefix rows y + dn | y - u - 1 << 16,
+//          4 (r + 1) | 4 l << 8, RN(1/N2) * 2^-20, N2 * 2^20   (two stages)
 struct AggRecords {
     uint32_t* a;
-    uint2* b;
-    uint2* c;
+    uint32_t* b;
+    uint4* c;
     int Wp, apron;
 };
 constexpr int kRecApronL = 2 * kLMax;        // left apron of the records

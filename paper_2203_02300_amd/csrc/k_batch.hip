@@ -19,12 +19,6 @@
 
 namespace {
 
-// Rows per block-scan round of the batched aggregation: fewer than the
-// one-call kernel's, so that the stage kernel's item loop fits in registers
-// without spilling (the sums are exact, so every chunk size gives the same
-// result).
-constexpr int kBatchChunk = 4;
-
 struct NoLds {
     int unused;
 };
@@ -33,7 +27,7 @@ struct NoLds {
 template <int ITERS, int STAGE>
 using StageLds = typename std::conditional<
     STAGE == 0, dco::CensusLds,
-    typename std::conditional<STAGE == 2, dco::AggLds<ITERS, true, kBatchChunk>, NoLds>::type>::type;
+    typename std::conditional<STAGE == 2, dco::AggLds<ITERS, true>, NoLds>::type>::type;
 
 template <int ITERS, int STAGE>
 __global__ __launch_bounds__(256, 2) void k_batch_stage(BatchArgs B, int first, int count) {
@@ -81,7 +75,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BatchArgs B, int first, 
             const int y0 = I.c * pr.band, y1 = min(H, y0 + pr.band);
             const int dend = min(pr.D, I.a + pr.dchunk);
             for (int d = I.a; d < dend; ++d) {
-                dco::agg_stream<ITERS, true, kBatchChunk>(A, d, I.b, y0, y1, S);
+                dco::agg_stream<ITERS, true>(A, d, I.b, y0, y1, S);
                 __syncthreads();
             }
         } else if constexpr (STAGE == 3) {  // WTA of both views for pixels [a, a + kWtaPx)
