@@ -136,10 +136,10 @@ dco_status alloc_records(AggRecords* r, int W, int H) {
     r->Wp = W + kRecApronL + kRecApronR;
     const size_t n = (size_t)r->Wp * (H + 1);
     DCO_TRY(dev_alloc(&r->a, n));
-    DCO_TRY(dev_alloc(&r->b, 3 * n));
+    DCO_TRY(dev_alloc(&r->b, n));
     DCO_TRY(dev_alloc(&r->c, n));
     DCO_HIP_CHECK(hipMemset(r->a, 0, n * sizeof(uint32_t)));
-    DCO_HIP_CHECK(hipMemset(r->b, 0, 3 * n * sizeof(uint32_t)));
+    DCO_HIP_CHECK(hipMemset(r->b, 0, n * sizeof(uint4)));
     DCO_HIP_CHECK(hipMemset(r->c, 0, n * sizeof(uint4)));
     return DCO_OK;
 }

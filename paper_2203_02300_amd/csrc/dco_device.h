@@ -131,41 +131,93 @@ __device__ inline uint32_t ring_slot_bytes(int row, int ring) {
     return (uint32_t)s * kSlotBytes;
 }
 
-__device__ inline void geometry_pixel(const uint32_t* __restrict__ arms, int W, int H, int iters,
-                                      const AggRecords& rec, int x, int y) {
-    const uint32_t a = arms[(size_t)y * W + x];
+// Records of pixel (x, y) with arms word a and region counts n1, n2.
+__device__ inline void write_records(const AggRecords& rec, int x, int y, int iters, uint32_t a,
+                                     uint32_t n1, uint32_t n2) {
     const uint32_t l = a & 0xff, r = (a >> 8) & 0xff, u = (a >> 16) & 0xff, dn = a >> 24;
-    uint32_t n1 = 0, n2 = 0;
-    // arms from census_tile stay inside the image; the clamps only keep a
-    // corrupted arms buffer from reading outside it
-    for (int yy = max(0, y - (int)u); yy <= min(H - 1, y + (int)dn); ++yy) {
-        uint32_t b = arms[(size_t)yy * W + x];
-        n1 += (b & 0xff) + ((b >> 8) & 0xff) + 1;
-    }
-    for (int xx = max(0, x - (int)l); xx <= min(W - 1, x + (int)r); ++xx) {
-        uint32_t b = arms[(size_t)y * W + xx];
-        n2 += ((b >> 16) & 0xff) + (b >> 24) + 1;
-    }
     const uint32_t lmin = min(min(l, r), min(u, dn));
     const uint32_t lr = 4 * (r + 1) | (4 * l) << 8;
     const uint32_t hi = (uint32_t)y + dn, lo = (uint32_t)y - u - 1;
     const size_t i = (size_t)y * rec.Wp + x + rec.apron;
     rec.a[i] = lr | (8 * lmin) << 16;
-    uint32_t* b = rec.b + 3 * i;
-    b[2] = ring_slot_bytes((int)hi, kRing1) | ring_slot_bytes((int)lo, kRing1) << 16;
+    const uint32_t v1 = ring_slot_bytes((int)hi, kRing1) | ring_slot_bytes((int)lo, kRing1) << 16;
     if (iters == 2) {
         const uint32_t lg = n1 <= 1 ? 0u : 32u - (uint32_t)__clz((int)(n1 - 1));
         const uint32_t sh = 31u + lg;
         const uint64_t num = (uint64_t)1 << sh;
-        b[0] = (uint32_t)((num + n1 - 1) / n1);
-        b[1] = (n1 >> 1) | (sh << 10);
+        rec.b[i] = make_uint4((uint32_t)((num + n1 - 1) / n1), n1 >> 1, sh, v1);
         rec.c[i] = make_uint4(ring_slot_bytes((int)hi, kRing2) |
                                   ring_slot_bytes((int)lo, kRing2) << 16,
                               lr, __float_as_uint((1.0f / (float)n2) * 0x1p-20f),
                               __float_as_uint((float)n2 * 0x1p20f));
     } else {
-        b[0] = __float_as_uint((1.0f / (float)n1) * 0x1p-20f);
-        b[1] = __float_as_uint((float)n1 * 0x1p20f);
+        rec.b[i] = make_uint4(__float_as_uint((1.0f / (float)n1) * 0x1p-20f),
+                              __float_as_uint((float)n1 * 0x1p20f), 0u, v1);
+    }
+}
+
+// Region counts and records of a 64 x 16 tile at (x0, y0), 256 threads.  The
+// arms of the tile plus a kLMax apron go to LDS as h = l + r + 1 and
+// v = u + dn + 1; prefix sums of h down each tile column and of v along each
+// tile row then give every N1 and N2 with two reads.  Apron cells outside the
+// image hold 0 and never fall inside a region (arms stop at the border).
+constexpr int kGeoTW = 64, kGeoTH = 16;
+constexpr int kGeoRW = kGeoTW + 2 * kLMax, kGeoRH = kGeoTH + 2 * kLMax;
+
+struct GeomLds {
+    uint32_t hv[kGeoRH][kGeoRW];       // h | v << 16
+    uint32_t cp[kGeoRH + 1][kGeoTW];   // column prefixes of h (row 0 = 0)
+    uint32_t rp[kGeoTH][kGeoRW + 1];   // row prefixes of v (column 0 = 0)
+};
+
+__device__ inline void geometry_tile(const uint32_t* __restrict__ arms, int W, int H, int iters,
+                                     const AggRecords& rec, int x0, int y0, GeomLds& S) {
+    const int t = threadIdx.x;
+    for (int i = t; i < kGeoRW * kGeoRH; i += 256) {
+        const int ry = i / kGeoRW, rx = i - ry * kGeoRW;
+        const int x = x0 - kLMax + rx, y = y0 - kLMax + ry;
+        uint32_t hv = 0;
+        if (x >= 0 && x < W && y >= 0 && y < H) {
+            const uint32_t a = arms[(size_t)y * W + x];
+            hv = ((a & 0xff) + ((a >> 8) & 0xff) + 1) | ((a >> 16 & 0xff) + (a >> 24) + 1) << 16;
+        }
+        S.hv[ry][rx] = hv;
+    }
+    __syncthreads();
+    if (t < kGeoTW) {  // column prefixes of h
+        uint32_t acc = 0;
+        S.cp[0][t] = 0;
+#pragma unroll 10
+        for (int ry = 0; ry < kGeoRH; ++ry) {
+            acc += S.hv[ry][t + kLMax] & 0xffff;
+            S.cp[ry + 1][t] = acc;
+        }
+    } else if (t < kGeoTW + kGeoTH) {  // row prefixes of v
+        const int ty = t - kGeoTW;
+        uint32_t acc = 0;
+        S.rp[ty][0] = 0;
+#pragma unroll 14
+        for (int rx = 0; rx < kGeoRW; ++rx) {
+            acc += S.hv[ty + kLMax][rx] >> 16;
+            S.rp[ty][rx + 1] = acc;
+        }
+    }
+    __syncthreads();
+    const int tx = t & 63;
+    const int x = x0 + tx;
+    for (int k = 0; k < kGeoTH / 4; ++k) {
+        const int ty = (t >> 6) + 4 * k;
+        const int y = y0 + ty;
+        if (x >= W || y >= H) continue;
+        // arms from census_tile never exceed kLMax; the clamp only keeps an
+        // arbitrary caller-supplied arms map from indexing outside the tile
+        const uint32_t a0 = arms[(size_t)y * W + x];
+        const int l = min((int)(a0 & 0xff), kLMax), r = min((int)((a0 >> 8) & 0xff), kLMax);
+        const int u = min((int)((a0 >> 16) & 0xff), kLMax), dn = min((int)(a0 >> 24), kLMax);
+        const uint32_t a = (uint32_t)l | (uint32_t)r << 8 | (uint32_t)u << 16 | (uint32_t)dn << 24;
+        const uint32_t n1 = S.cp[ty + kLMax + dn + 1][tx] - S.cp[ty + kLMax - u][tx];
+        const uint32_t n2 = S.rp[ty][tx + kLMax + r + 1] - S.rp[ty][tx + kLMax - l];
+        write_records(rec, x, y, iters, a, n1, n2);
     }
 }
 
@@ -203,14 +255,19 @@ __device__ inline void geometry_pixel(const uint32_t* __restrict__ arms, int W, 
 // buffer loads with a per-lane column offset and a uniform row offset, so the
 // chunk body has no bounds branches.
 
+// Every member starts below 64 KB, so LDS addresses fold into the 16-bit
+// instruction offsets.  Reads of a prefix row reach up to kLMax words before
+// it (apron lanes, results unused): `guard` and the tables keep them inside
+// the allocation.
 template <int ITERS, bool kFused>
 struct AggLds {
-    uint32_t ring1[kRing1 * kRingStride];
-    uint32_t ring2[ITERS == 2 ? kRing2 * kRingStride : 1];
-    uint32_t prow[kAggK][kPStride];
     float tabA[kFused ? 768 : 1];
     float tabC[kFused ? 68 : 1];
     float2 ab[kFused ? kLMax + 1 : 1];
+    uint32_t guard[32];
+    uint32_t prow[kAggK][kPStride];
+    uint32_t ring1[kRing1 * kRingStride];
+    uint32_t ring2[ITERS == 2 ? kRing2 * kRingStride : 1];
 };
 
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
@@ -224,10 +281,6 @@ __device__ inline uint32_t ld32(rsrc_t r, uint32_t voff, uint32_t soff) {
 }
 __device__ inline uint2 ld64(rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-}
-__device__ inline uint3 ld96(rsrc_t r, uint32_t voff, uint32_t soff) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0);
-    return make_uint3(v[0], v[1], v[2]);
 }
 __device__ inline uint4 ld128(rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
@@ -313,7 +366,7 @@ struct ChunkIn {
     uint2 rcen[kSeg], pcen[kSeg];
     uint32_t a1[kSeg];          // step 1: records a (shortest arm)
     uint32_t a2[kAggK];         // step 2: records a of rows yc + k
-    uint3 b2[kAggK];            // step 2: records b of rows yc + k - kLMax
+    uint4 b2[kAggK];            // step 2: records b of rows yc + k - kLMax
     uint4 c3[kSeg];             // step 3: records c of the output row
 };
 
@@ -321,15 +374,15 @@ struct ChunkIn {
 struct AggLane {
     uint32_t img[kSeg];   // byte offset (x4) of each segment column in an H x W map, or kOOB
     uint32_t par[kSeg];   // fused: the partner column, or kOOB
-    uint32_t okm[kSeg];   // fused: ~0 when the partner is inside the image, else 0
     uint32_t inval[kSeg]; // fused: raw cost when the partner is outside (2^20; 0 off-image)
     uint32_t recw;        // record column offset (x4) of segment 0 of this lane
     uint32_t reco;        // record column offset (x4) of the owned column
     uint32_t cb1, cb2;    // ring byte offsets of the owned column
-    uint32_t cbs[kSeg];   // ring-2 byte offset of each segment column
+    uint32_t cbs[kSeg];   // ring-2 byte offset of each segment column (column
+                          // kRingCols + 1, never written, for columns without a ring)
     uint32_t vout[kSeg];  // output byte offset of each segment column, or kOOB
     uint32_t vout_o;      // output byte offset of the owned column, or kOOB (one stage)
-    bool rok[kSeg];       // segment column has a ring
+    bool pok[kSeg];       // fused: partner inside the image
 };
 
 struct AggRes {
@@ -365,7 +418,7 @@ __device__ inline void load_chunk(const AggArgs& A, int yc, const AggLane& ln, c
         const uint32_t ra = (uint32_t)(y < H ? y : H);
         const uint32_t rb = (uint32_t)(yv >= 0 && yv < H ? yv : H);
         in.a2[k] = ld32(R.rA, ln.reco, ra * Wp * 4);
-        in.b2[k] = ld96(R.rB, ln.reco * 3, rb * Wp * 12);
+        in.b2[k] = ld128(R.rB, ln.reco * 4, rb * Wp * 16);
     }
     if (ITERS == 2) {  // step 3: output row yc + w - 2 kLMax - 1
         const int y2 = yc + w - 2 * kLMax - 1;
@@ -387,24 +440,30 @@ __device__ inline void process_chunk(const AggArgs& A, int yc, int y0, int y1, c
     {
         const int y = yc + w;
         uint32_t v[kSeg];
+        if (y < H) {  // uniform: rows below the image contribute nothing
 #pragma unroll
-        for (int j = 0; j < kSeg; ++j) {
-            uint32_t q;
-            if (kFused) {
-                const uint32_t s = __builtin_amdgcn_sad_u8(in.q[j], in.prgb[j], 0u);
-                const uint32_t h = __popc(in.rcen[j].x ^ in.pcen[j].x) +
-                                   __popc(in.rcen[j].y ^ in.pcen[j].y);
-                const float2 ab = *reinterpret_cast<const float2*>(
-                    reinterpret_cast<const char*>(S.ab) + (in.a1[j] >> 16));
-                const float qa = __builtin_rintf(ab.x * S.tabA[s]);
-                const float qc = __builtin_rintf(ab.y * S.tabC[h]);
-                // blend with lane masks rather than a branch, so the four
-                // segments' lookups stay interleaved
-                q = ((uint32_t)(qa + qc) & ln.okm[j]) | ln.inval[j];
-            } else {
-                q = (uint32_t)(__builtin_bit_cast(float, in.q[j]) * 1048576.0f);
+            for (int j = 0; j < kSeg; ++j) {
+                if (kFused) {
+                    const uint32_t s = __builtin_amdgcn_sad_u8(in.q[j], in.prgb[j], 0u);
+                    const uint64_t x = ((uint64_t)in.rcen[j].y << 32 | in.rcen[j].x) ^
+                                       ((uint64_t)in.pcen[j].y << 32 | in.pcen[j].x);
+                    const uint32_t h = (uint32_t)__popcll(x);
+                    const float2 ab = *reinterpret_cast<const float2*>(
+                        reinterpret_cast<const char*>(S.ab) + (in.a1[j] >> 16));
+                    const float qa = __builtin_rintf(ab.x * S.tabA[s]);
+                    const float qc = __builtin_rintf(ab.y * S.tabC[h]);
+                    uint32_t q = (uint32_t)(qa + qc);
+                    // keep the lookups unconditional (interleaved across
+                    // segments); the select is then one lane-mask cndmask
+                    asm volatile("" : "+v"(q));
+                    v[j] = ln.pok[j] ? q : ln.inval[j];
+                } else {
+                    v[j] = (uint32_t)(__builtin_bit_cast(float, in.q[j]) * 1048576.0f);
+                }
             }
-            v[j] = y < H ? q : 0u;
+        } else {
+#pragma unroll
+            for (int j = 0; j < kSeg; ++j) v[j] = 0u;
         }
         wave_scan_segments(v);
 #pragma unroll
@@ -431,15 +490,15 @@ __device__ inline void process_chunk(const AggArgs& A, int yc, int y0, int y1, c
     s1off = off;
 #pragma unroll
     for (int k = 0; k < kAggK; ++k) {
-        const uint32_t o = in.b2[k].z;
+        const uint32_t o = in.b2[k].w;
         s1[k] = lds_ld(S.ring1, ln.cb1 + (o & 0xffff)) - lds_ld(S.ring1, ln.cb1 + (o >> 16));
     }
 #pragma unroll
     for (int k = 0; k < kAggK; ++k) {
-        const uint3 b = in.b2[k];
+        const uint4 b = in.b2[k];
         if (ITERS == 2) {
-            const uint64_t n = (uint64_t)(s1[k] + (b.y & 1023)) * b.x;
-            cp2 += (uint32_t)(n >> (b.y >> 10));
+            const uint64_t n = (uint64_t)(s1[k] + b.y) * b.x;
+            cp2 += (uint32_t)(n >> b.z);
             lds_st(S.ring2, ln.cb2 + s2off, cp2);
             s2off = s2off + kSlotBytes == kRing2 * kSlotBytes ? 0u : s2off + kSlotBytes;
         } else {
@@ -457,20 +516,20 @@ __device__ inline void process_chunk(const AggArgs& A, int yc, int y0, int y1, c
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) {
             const uint32_t o = in.c3[j].x;
-            const uint32_t e = lds_ld(S.ring2, ln.cbs[j] + (o & 0xffff)) -
-                               lds_ld(S.ring2, ln.cbs[j] + (o >> 16));
-            v[j] = ln.rok[j] ? e : 0u;
+            v[j] = lds_ld(S.ring2, ln.cbs[j] + (o & 0xffff)) -
+                   lds_ld(S.ring2, ln.cbs[j] + (o >> 16));
         }
         wave_scan_segments(v);
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) prow_w[64 * j + lane + 1] = v[j];
         // the row was written by this wavefront only: LDS keeps its order
         float out[kSeg];
+        const uint32_t pbw = (uint32_t)(w * kPStride + lane) * 4;
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) {
             const uint32_t lr = in.c3[j].y;
-            const uint32_t pb = (uint32_t)(64 * j + lane) * 4;
-            const uint32_t s2 = lds_ld(prow_w, pb + (lr & 0xff)) - lds_ld(prow_w, pb - ((lr >> 8) & 0xff));
+            const uint32_t s2 = lds_ld(S.prow[0], pbw + 256 * j + (lr & 0xff)) -
+                                lds_ld(S.prow[0], pbw + 256 * j - ((lr >> 8) & 0xff));
             out[j] = div_q20(s2, __builtin_bit_cast(float, in.c3[j].w),
                              __builtin_bit_cast(float, in.c3[j].z));
         }
@@ -514,18 +573,19 @@ __device__ inline void agg_stream(const AggArgs& A, int d, int strip, int y0, in
         const bool pok = in_img && cp >= 0 && cp < W;
         ln.img[j] = in_img ? (uint32_t)c * 4 : kOOB;
         ln.par[j] = pok ? (uint32_t)cp * 4 : kOOB;
-        ln.okm[j] = pok ? ~0u : 0u;
-        ln.inval[j] = in_img && !pok ? (1u << 20) : 0u;
-        ln.rok[j] = i >= kLMax && i < kLMax + kRingCols;
-        ln.cbs[j] = (uint32_t)(ln.rok[j] ? i - kLMax : kRingCols) * 4;
+        ln.pok[j] = pok;
+        ln.inval[j] = in_img ? (1u << 20) : 0u;
+        const bool rok = i >= kLMax && i < kLMax + kRingCols;
+        ln.cbs[j] = (uint32_t)(rok ? i - kLMax : kRingCols + 1) * 4;
         ln.vout[j] = i >= 2 * kLMax && i < 2 * kLMax + kStripOut && c < W ? (uint32_t)c * 4 : kOOB;
     }
     {
         const int c = x0 - 2 * kLMax + t;
         const int jj = t - kLMax;
         const bool ring = jj >= 0 && jj < kRingCols;
-        // owners without a ring column share two scratch columns
-        ln.cb1 = (uint32_t)(ring ? jj : kRingCols + (t & 1)) * 4;
+        // owners without a ring column share one scratch column; column
+        // kRingCols + 1 stays zero
+        ln.cb1 = (uint32_t)(ring ? jj : kRingCols) * 4;
         ln.cb2 = ln.cb1;
         ln.reco = (uint32_t)(c + A.rec.apron) * 4;
         ln.recw = (uint32_t)(x0 - 2 * kLMax + lane + A.rec.apron) * 4;
@@ -539,7 +599,7 @@ __device__ inline void agg_stream(const AggArgs& A, int d, int strip, int y0, in
     const uint64_t* Cpar = A.ref == 0 ? A.cenR : A.cenL;
     AggRes R;
     R.rA = make_rsrc(A.rec.a, recN * 4);
-    R.rB = make_rsrc(A.rec.b, recN * 12);
+    R.rB = make_rsrc(A.rec.b, recN * 16);
     R.rC = make_rsrc(ITERS == 2 ? (const void*)A.rec.c : (const void*)A.rec.a,
                      ITERS == 2 ? recN * 16 : recN * 4);
     R.rq = make_rsrc(kFused ? (const void*)A.rec.a : (const void*)(A.cost + (size_t)d * slice),
@@ -584,6 +644,22 @@ __device__ inline int xcd_work_item(int b, int n) {
 // Winner-take-all (Eq. 3) with parabola sub-pixel refinement; LR check
 // ===========================================================================
 
+// Parabola vertex offset through (d-1, m), (d, c), (d+1, pl), in this FP32
+// order, clamped to [-0.5, 0.5]; 0 at the range ends or for den <= 0.
+__device__ inline float subpixel_delta(float m, float c, float pl, int bd, int D) {
+    float del = 0.f;
+    if (bd > 0 && bd < D - 1) {
+        const float num = m - pl;
+        const float den = (m - c) + (pl - c);
+        if (den > 0.f) {
+            del = num / (2.0f * den);
+            del = fminf(fmaxf(del, -0.5f), 0.5f);
+        }
+    }
+    return del;
+}
+
+
 // Pixel i of a D-slice volume: smallest d minimising agg, with the values at
 // d - 1 and d + 1 tracked on the fly (ties keep the smallest d).
 __device__ inline void wta_pixel(const float* __restrict__ agg, int P, int D, int i,
@@ -618,17 +694,68 @@ __device__ inline void wta_pixel(const float* __restrict__ agg, int P, int D, in
         prev = v;
     }
     *dout = (int16_t)bd;
-    if (delta_out) {
-        float del = 0.f;
-        if (subpixel && bd > 0 && bd < D - 1) {
-            const float num = m - pl;
-            const float den = (m - best) + (pl - best);
-            if (den > 0.f) {
-                del = num / (2.0f * den);
-                del = fminf(fmaxf(del, -0.5f), 0.5f);
-            }
+    if (delta_out) *delta_out = subpixel ? subpixel_delta(m, best, pl, bd, D) : 0.f;
+}
+
+// Four consecutive pixels i4 .. i4 + 3 of a D-slice volume (P % 4 == 0, so
+// every slice row of four is 16-byte aligned): the same rule as wta_pixel
+// per component, with one 16-byte load per slice and eight slices in flight.
+__device__ inline void wta_quad_step(float v, int d, float& best, int& bd, float& m, float& pl,
+                                     float& prev) {
+    if (d == bd + 1) pl = v;
+    if (v < best) {
+        best = v;
+        bd = d;
+        m = prev;
+    }
+    prev = v;
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline void wta_quad(const float* __restrict__ agg, int P, int D, int i4, int subpixel,
+                                int16_t* __restrict__ dout, float* __restrict__ delta_out) {
+    // each volume is read once: non-temporal loads keep it from evicting
+    // reused data from the caches
+    const f32x4* __restrict__ a4 = reinterpret_cast<const f32x4*>(agg + i4);
+    const size_t s4 = (size_t)P / 4;
+    const f32x4 v0 = __builtin_nontemporal_load(a4);
+    float best[4] = {v0.x, v0.y, v0.z, v0.w}, prev[4] = {v0.x, v0.y, v0.z, v0.w};
+    float m[4] = {0.f, 0.f, 0.f, 0.f}, pl[4] = {0.f, 0.f, 0.f, 0.f};
+    int bd[4] = {0, 0, 0, 0};
+    constexpr int U = 8;
+    int d = 1;
+    for (; d + U <= D; d += U) {
+        f32x4 v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) v[k] = __builtin_nontemporal_load(a4 + (size_t)(d + k) * s4);
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            wta_quad_step(v[k].x, d + k, best[0], bd[0], m[0], pl[0], prev[0]);
+            wta_quad_step(v[k].y, d + k, best[1], bd[1], m[1], pl[1], prev[1]);
+            wta_quad_step(v[k].z, d + k, best[2], bd[2], m[2], pl[2], prev[2]);
+            wta_quad_step(v[k].w, d + k, best[3], bd[3], m[3], pl[3], prev[3]);
         }
-        *delta_out = del;
+    }
+    for (; d < D; ++d) {
+        const f32x4 v = __builtin_nontemporal_load(a4 + (size_t)d * s4);
+        wta_quad_step(v.x, d, best[0], bd[0], m[0], pl[0], prev[0]);
+        wta_quad_step(v.y, d, best[1], bd[1], m[1], pl[1], prev[1]);
+        wta_quad_step(v.z, d, best[2], bd[2], m[2], pl[2], prev[2]);
+        wta_quad_step(v.w, d, best[3], bd[3], m[3], pl[3], prev[3]);
+    }
+    const uint32_t lo = (uint32_t)(uint16_t)bd[0] | (uint32_t)(uint16_t)bd[1] << 16;
+    const uint32_t hi = (uint32_t)(uint16_t)bd[2] | (uint32_t)(uint16_t)bd[3] << 16;
+    *reinterpret_cast<uint2*>(dout + i4) = make_uint2(lo, hi);
+    if (delta_out) {
+        float4 del = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (subpixel) {
+            del.x = subpixel_delta(m[0], best[0], pl[0], bd[0], D);
+            del.y = subpixel_delta(m[1], best[1], pl[1], bd[1], D);
+            del.z = subpixel_delta(m[2], best[2], pl[2], bd[2], D);
+            del.w = subpixel_delta(m[3], best[3], pl[3], bd[3], D);
+        }
+        *reinterpret_cast<float4*>(delta_out + i4) = del;
     }
 }
 

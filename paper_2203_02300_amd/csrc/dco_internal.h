@@ -23,16 +23,16 @@ constexpr int kStripOut = kStripThreads - 4 * kLMax;
 // by k_geometry.  Each array has H + 1 rows of Wp entries; pixel (x, y) sits
 // at y * Wp + x + apron, and the apron columns and row H are zero.
 //   a[p] = 4 (r + 1) | 4 l << 8 | 8 L_min << 16          (horizontal arms, alpha index)
-//   b[p] = three words for the stage-1 vertical range of p:
-//          two stages: m, N1 / 2 | sh << 10  with floor((S1 + N1/2) / N1) =
+//   b[p] = four words for the stage-1 vertical range of p:
+//          two stages: m, N1 / 2, sh  with floor((S1 + N1/2) / N1) =
 //                      ((S1 + N1/2) * m) >> sh
-//          one stage:  RN(1/N1) * 2^-20, N1 * 2^20   (floats)
+//          one stage:  RN(1/N1) * 2^-20, N1 * 2^20 (floats), 0
 //          then the ring-1 byte offsets of prefix rows y + dn | y - u - 1 << 16
 //   c[p] = ring-2 byte offsets of prefix rows y + dn | y - u - 1 << 16,
 //          4 (r + 1) | 4 l << 8, RN(1/N2) * 2^-20, N2 * 2^20   (two stages)
 struct AggRecords {
     uint32_t* a;
-    uint32_t* b;
+    uint4* b;
     uint4* c;
     int Wp, apron;
 };

@@ -27,7 +27,9 @@ struct NoLds {
 template <int ITERS, int STAGE>
 using StageLds = typename std::conditional<
     STAGE == 0, dco::CensusLds,
-    typename std::conditional<STAGE == 2, dco::AggLds<ITERS, true>, NoLds>::type>::type;
+    typename std::conditional<
+        STAGE == 1, dco::GeomLds,
+        typename std::conditional<STAGE == 2, dco::AggLds<ITERS, true>, NoLds>::type>::type>::type;
 
 template <int ITERS, int STAGE>
 __global__ __launch_bounds__(256, 2) void k_batch_stage(BatchArgs B, int first, int count) {
@@ -48,11 +50,12 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BatchArgs B, int first, 
                 __syncthreads();
             }
         } else if constexpr (STAGE == 1) {  // region counts and records of a 64 x 64 block
-            const int x = I.a * 64 + (t & 63);
-            for (int r = t >> 6; r < 64; r += 4) {
-                const int y = I.b * 64 + r;
-                if (x < W && y < H)
-                    dco::geometry_pixel(pr.arms[I.view], W, H, ITERS, pr.rec[I.view], x, y);
+            for (int r = 0; r < 64 / dco::kGeoTH; ++r) {
+                const int y0 = I.b * 64 + r * dco::kGeoTH;
+                if (y0 >= H) break;
+                dco::geometry_tile(pr.arms[I.view], W, H, ITERS, pr.rec[I.view], I.a * dco::kGeoTW,
+                                   y0, S);
+                __syncthreads();
             }
         } else if constexpr (STAGE == 2) {  // slices a .. a+dchunk-1, strip b, row band c
             dco::AggArgs A{};

@@ -17,9 +17,9 @@ __global__ __launch_bounds__(256) void k_census_arms(const uint8_t* __restrict__
 
 __global__ __launch_bounds__(256) void k_geometry(const uint32_t* __restrict__ arms, int W, int H,
                                                   int iters, AggRecords rec) {
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (x < W && y < H) dco::geometry_pixel(arms, W, H, iters, rec, x, y);
+    __shared__ dco::GeomLds S;
+    dco::geometry_tile(arms, W, H, iters, rec, blockIdx.x * dco::kGeoTW, blockIdx.y * dco::kGeoTH,
+                       S);
 }
 
 }  // namespace
@@ -35,7 +35,7 @@ hipError_t launch_census_arms(const uint8_t* rgb, int W, int H, int cw, int ch, 
 
 hipError_t launch_geometry(const uint32_t* arms, int W, int H, int iters, const AggRecords& rec,
                            hipStream_t st) {
-    dim3 grid((W + 63) / 64, (H + 3) / 4);
+    dim3 grid((W + dco::kGeoTW - 1) / dco::kGeoTW, (H + dco::kGeoTH - 1) / dco::kGeoTH);
     hipLaunchKernelGGL(k_geometry, grid, dim3(256), 0, st, arms, W, H, iters, rec);
     return hipGetLastError();
 }

@@ -1,7 +1,8 @@
 // k_wta.hip -- winner-take-all over the aggregated volumes (Eq. 3) with
 // parabola sub-pixel refinement, and the left-right consistency check.
-// One thread per pixel walks d = 0 .. D-1 (loads of one slice are coalesced
-// across the block), so each volume is read exactly once.  The stage bodies
+// One thread per pixel (or per four pixels, with 16-byte loads, when W * H is
+// a multiple of four) walks d = 0 .. D-1; loads of one slice are coalesced
+// across the block, so each volume is read exactly once.  The stage bodies
 // live in dco_device.h.
 #include "dco_device.h"
 
@@ -20,6 +21,19 @@ __global__ __launch_bounds__(256) void k_wta(const float* __restrict__ aggL,
         dco::wta_pixel(aggR, P, D, i, subpixel, dR + i, nullptr);
 }
 
+__global__ __launch_bounds__(256) void k_wta4(const float* __restrict__ aggL,
+                                              const float* __restrict__ aggR, int P, int D,
+                                              int subpixel, int16_t* __restrict__ dL,
+                                              float* __restrict__ deltaL,
+                                              int16_t* __restrict__ dR) {
+    const int i4 = (blockIdx.x * 256 + threadIdx.x) * 4;
+    if (i4 >= P) return;
+    if (blockIdx.y == 0)
+        dco::wta_quad(aggL, P, D, i4, subpixel, dL, deltaL);
+    else
+        dco::wta_quad(aggR, P, D, i4, subpixel, dR, nullptr);
+}
+
 __global__ __launch_bounds__(256) void k_lrcheck(const int16_t* __restrict__ dL,
                                                  const float* __restrict__ deltaL,
                                                  const int16_t* __restrict__ dR, int W, int H,
@@ -34,8 +48,17 @@ __global__ __launch_bounds__(256) void k_lrcheck(const int16_t* __restrict__ dL,
 hipError_t launch_wta2(const float* aggL, const float* aggR, int W, int H, int D, int subpixel,
                        int16_t* dL, float* deltaL, int16_t* dR, hipStream_t st) {
     const int P = W * H;
-    dim3 grid((P + 255) / 256, 2);
-    hipLaunchKernelGGL(k_wta, grid, dim3(256), 0, st, aggL, aggR, P, D, subpixel, dL, deltaL, dR);
+    const bool aligned = ((uintptr_t)aggL | (uintptr_t)aggR | (uintptr_t)deltaL) % 16 == 0 &&
+                         ((uintptr_t)dL | (uintptr_t)dR) % 8 == 0;
+    if (P % 4 == 0 && aligned) {
+        dim3 grid((P / 4 + 255) / 256, 2);
+        hipLaunchKernelGGL(k_wta4, grid, dim3(256), 0, st, aggL, aggR, P, D, subpixel, dL, deltaL,
+                           dR);
+    } else {
+        dim3 grid((P + 255) / 256, 2);
+        hipLaunchKernelGGL(k_wta, grid, dim3(256), 0, st, aggL, aggR, P, D, subpixel, dL, deltaL,
+                           dR);
+    }
     return hipGetLastError();
 }
 
