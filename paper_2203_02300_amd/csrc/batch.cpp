@@ -65,7 +65,7 @@ dco_status alloc_pair(dco_batch* b, BatchPair& pr, int W, int H, int D) {
         DCO_TRY(balloc(b, &pr.arms[v], P));
         DCO_TRY(balloc(b, &pr.rgbp[v], P));
         const dco_status s = alloc_records(&pr.rec[v], W, H);
-        for (void* q : {(void*)pr.rec[v].a, (void*)pr.rec[v].b, (void*)pr.rec[v].c})
+        for (void* q : {(void*)pr.rec[v].b, (void*)pr.rec[v].c})
             if (q) b->allocs.push_back(q);
         DCO_TRY(s);
         DCO_TRY(balloc(b, &pr.agg[v], V));

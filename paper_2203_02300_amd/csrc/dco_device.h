@@ -32,13 +32,22 @@ __device__ inline uint32_t grey_of(uint32_t c) {
     return (77u * r + 150u * g + 29u * b + 128u) >> 8;
 }
 
-// Largest per-channel absolute difference below tau?
-__device__ inline bool close_rgb(uint32_t a, uint32_t b, int tau) {
-    int dr = (int)(a & 0xffu) - (int)(b & 0xffu);
-    int dg = (int)((a >> 8) & 0xffu) - (int)((b >> 8) & 0xffu);
-    int db = (int)((a >> 16) & 0xffu) - (int)((b >> 16) & 0xffu);
-    int m = max(max(abs(dr), abs(dg)), abs(db));
-    return m < tau;
+// Largest per-channel absolute difference below tau?  With the centre's
+// channels biased as A_c = a_c + tau - 1, |a_c - b_c| < tau holds exactly when
+// the unsigned A_c - b_c is below 2 tau - 1, so one test is three byte
+// subtractions, a max3 and a compare.
+struct Centre {
+    uint32_t r, g, b, lim;
+};
+__device__ inline Centre centre_of(uint32_t a, int tau) {
+    const uint32_t t = (uint32_t)tau - 1;
+    return Centre{(a & 0xffu) + t, ((a >> 8) & 0xffu) + t, ((a >> 16) & 0xffu) + t,
+                  2u * (uint32_t)tau - 1u};
+}
+__device__ inline bool close_rgb(const Centre& c, uint32_t b) {
+    const uint32_t dr = c.r - (b & 0xffu), dg = c.g - ((b >> 8) & 0xffu),
+                   db = c.b - ((b >> 16) & 0xffu);
+    return max(max(dr, dg), db) < c.lim;
 }
 
 // One 64 x 16 tile at (x0, y0), 256 threads.  The tile plus a kLMax apron
@@ -50,7 +59,7 @@ __device__ inline bool close_rgb(uint32_t a, uint32_t b, int tau) {
 __device__ inline void census_tile(const uint8_t* __restrict__ rgb, int W, int H, int cw, int ch,
                                    int L1, int tau1, uint64_t* __restrict__ census,
                                    uint32_t* __restrict__ arms, uint32_t* __restrict__ rgb_packed,
-                                   int x0, int y0, CensusLds& S) {
+                                   bool lmin_byte, int x0, int y0, CensusLds& S) {
     const int t = threadIdx.x;
     for (int i = t; i < kCenRW * kCenRH; i += 256) {
         int ry = i / kCenRW, rx = i - ry * kCenRW;
@@ -86,16 +95,21 @@ __device__ inline void census_tile(const uint8_t* __restrict__ rgb, int W, int H
 
         const int rx = tx + kLMax, ry = ty + kLMax;
         const uint32_t cp = S.rgb[ry][rx];
-        if (rgb_packed) rgb_packed[(size_t)y * W + x] = cp;
         int al = 0, ar = 0, au = 0, ad = 0;
         const int ml = min(L1, x), mr = min(L1, W - 1 - x);
         const int mu = min(L1, y), md = min(L1, H - 1 - y);
-        while (al < ml && close_rgb(S.rgb[ry][rx - al - 1], cp, tau1)) ++al;
-        while (ar < mr && close_rgb(S.rgb[ry][rx + ar + 1], cp, tau1)) ++ar;
-        while (au < mu && close_rgb(S.rgb[ry - au - 1][rx], cp, tau1)) ++au;
-        while (ad < md && close_rgb(S.rgb[ry + ad + 1][rx], cp, tau1)) ++ad;
+        const Centre cc = centre_of(cp, tau1);
+        while (al < ml && close_rgb(cc, S.rgb[ry][rx - al - 1])) ++al;
+        while (ar < mr && close_rgb(cc, S.rgb[ry][rx + ar + 1])) ++ar;
+        while (au < mu && close_rgb(cc, S.rgb[ry - au - 1][rx])) ++au;
+        while (ad < md && close_rgb(cc, S.rgb[ry + ad + 1][rx])) ++ad;
         arms[(size_t)y * W + x] =
             (uint32_t)al | ((uint32_t)ar << 8) | ((uint32_t)au << 16) | ((uint32_t)ad << 24);
+        // packed RGB; with lmin_byte the spare top byte holds 8 L_min (the
+        // alpha-table byte offset of the aggregation kernel's raw cost)
+        if (rgb_packed)
+            rgb_packed[(size_t)y * W + x] =
+                cp | (lmin_byte ? (uint32_t)(8 * min(min(al, ar), min(au, ad))) << 24 : 0u);
     }
 }
 
@@ -131,28 +145,32 @@ __device__ inline uint32_t ring_slot_bytes(int row, int ring) {
     return (uint32_t)s * kSlotBytes;
 }
 
-// Records of pixel (x, y) with arms word a and region counts n1, n2.
+// Records of pixel (x, y) with arms word a and region counts n1, n2 (layout:
+// AggRecords).  The b row of the pixel's own row gets its horizontal arms
+// (low half of word 2); the b row kLMax rows below gets its stage-1 data.
 __device__ inline void write_records(const AggRecords& rec, int x, int y, int iters, uint32_t a,
                                      uint32_t n1, uint32_t n2) {
     const uint32_t l = a & 0xff, r = (a >> 8) & 0xff, u = (a >> 16) & 0xff, dn = a >> 24;
-    const uint32_t lmin = min(min(l, r), min(u, dn));
     const uint32_t lr = 4 * (r + 1) | (4 * l) << 8;
     const uint32_t hi = (uint32_t)y + dn, lo = (uint32_t)y - u - 1;
-    const size_t i = (size_t)y * rec.Wp + x + rec.apron;
-    rec.a[i] = lr | (8 * lmin) << 16;
-    const uint32_t v1 = ring_slot_bytes((int)hi, kRing1) | ring_slot_bytes((int)lo, kRing1) << 16;
+    const size_t col = (size_t)x + rec.apron;
+    uint32_t* bo = rec.b + 3 * ((size_t)y * rec.Wp + col);
+    reinterpret_cast<uint16_t*>(bo + 2)[0] = (uint16_t)lr;
+    uint32_t* bv = rec.b + 3 * ((size_t)(y + kLMax) * rec.Wp + col);
+    bv[1] = ring_slot_bytes((int)hi, kRing1) | ring_slot_bytes((int)lo, kRing1) << 16;
     if (iters == 2) {
         const uint32_t lg = n1 <= 1 ? 0u : 32u - (uint32_t)__clz((int)(n1 - 1));
         const uint32_t sh = 31u + lg;
         const uint64_t num = (uint64_t)1 << sh;
-        rec.b[i] = make_uint4((uint32_t)((num + n1 - 1) / n1), n1 >> 1, sh, v1);
-        rec.c[i] = make_uint4(ring_slot_bytes((int)hi, kRing2) |
-                                  ring_slot_bytes((int)lo, kRing2) << 16,
-                              lr, __float_as_uint((1.0f / (float)n2) * 0x1p-20f),
-                              __float_as_uint((float)n2 * 0x1p20f));
+        bv[0] = (uint32_t)((num + n1 - 1) / n1);
+        reinterpret_cast<uint16_t*>(bv + 2)[1] = (uint16_t)((n1 >> 1) | sh << 10);
+        uint32_t* c = rec.c + 3 * ((size_t)y * rec.Wp + col);
+        c[0] = ring_slot_bytes((int)hi, kRing2) | ring_slot_bytes((int)lo, kRing2) << 16;
+        c[1] = __float_as_uint((1.0f / (float)n2) * 0x1p-20f);
+        c[2] = lr | n2 << 16;
     } else {
-        rec.b[i] = make_uint4(__float_as_uint((1.0f / (float)n1) * 0x1p-20f),
-                              __float_as_uint((float)n1 * 0x1p20f), 0u, v1);
+        bv[0] = __float_as_uint((1.0f / (float)n1) * 0x1p-20f);
+        reinterpret_cast<uint16_t*>(bv + 2)[1] = (uint16_t)n1;
     }
 }
 
@@ -282,6 +300,10 @@ __device__ inline uint32_t ld32(rsrc_t r, uint32_t voff, uint32_t soff) {
 __device__ inline uint2 ld64(rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
+__device__ inline uint3 ld96(rsrc_t r, uint32_t voff, uint32_t soff) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0);
+    return make_uint3(v[0], v[1], v[2]);
+}
 __device__ inline uint4 ld128(rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
@@ -361,13 +383,11 @@ struct AggArgs {
 // column and the chunk's four rows.
 template <bool kFused>
 struct ChunkIn {
-    uint32_t q[kSeg];           // staged: raw cost bits; fused: reference RGB
-    uint32_t prgb[kSeg];        // fused: partner RGB
+    uint32_t q[kSeg];           // staged: raw cost bits; fused: reference RGB (+ 8 L_min)
+    uint32_t prgb[kSeg];        // fused: partner RGB (+ its own 8 L_min)
     uint2 rcen[kSeg], pcen[kSeg];
-    uint32_t a1[kSeg];          // step 1: records a (shortest arm)
-    uint32_t a2[kAggK];         // step 2: records a of rows yc + k
-    uint4 b2[kAggK];            // step 2: records b of rows yc + k - kLMax
-    uint4 c3[kSeg];             // step 3: records c of the output row
+    uint3 b2[kAggK];            // step 2: records b of rows yc + k
+    uint3 c3[kSeg];             // step 3: records c of the output row
 };
 
 // Per-lane constants of a strip.
@@ -375,8 +395,8 @@ struct AggLane {
     uint32_t img[kSeg];   // byte offset (x4) of each segment column in an H x W map, or kOOB
     uint32_t par[kSeg];   // fused: the partner column, or kOOB
     uint32_t inval[kSeg]; // fused: raw cost when the partner is outside (2^20; 0 off-image)
-    uint32_t recw;        // record column offset (x4) of segment 0 of this lane
-    uint32_t reco;        // record column offset (x4) of the owned column
+    uint32_t recw;        // record column index x4 of segment 0 of this lane
+    uint32_t reco;        // record column index x4 of the owned column
     uint32_t cb1, cb2;    // ring byte offsets of the owned column
     uint32_t cbs[kSeg];   // ring-2 byte offset of each segment column (column
                           // kRingCols + 1, never written, for columns without a ring)
@@ -386,7 +406,7 @@ struct AggLane {
 };
 
 struct AggRes {
-    rsrc_t rA, rB, rC, rq, rIr, rIp, rCr, rCp, rOut;
+    rsrc_t rB, rC, rq, rIr, rIp, rCr, rCp, rOut;
 };
 
 template <int ITERS, bool kFused>
@@ -398,10 +418,8 @@ __device__ inline void load_chunk(const AggArgs& A, int yc, const AggLane& ln, c
     {   // step 1: row yc + w
         const int y = yc + w;
         const uint32_t yq = (uint32_t)min(y, H - 1);
-        const uint32_t ra = (uint32_t)(y < H ? y : H);
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) {
-            in.a1[j] = kFused ? ld32(R.rA, ln.recw + 256 * j, ra * Wp * 4) : 0u;
             if (kFused) {
                 in.q[j] = ld32(R.rIr, ln.img[j], yq * W * 4);
                 in.prgb[j] = ld32(R.rIp, ln.par[j], yq * W * 4);
@@ -413,18 +431,16 @@ __device__ inline void load_chunk(const AggArgs& A, int yc, const AggLane& ln, c
         }
     }
 #pragma unroll
-    for (int k = 0; k < kAggK; ++k) {  // step 2: rows yc + k and yc + k - kLMax
-        const int y = yc + k, yv = y - kLMax;
-        const uint32_t ra = (uint32_t)(y < H ? y : H);
-        const uint32_t rb = (uint32_t)(yv >= 0 && yv < H ? yv : H);
-        in.a2[k] = ld32(R.rA, ln.reco, ra * Wp * 4);
-        in.b2[k] = ld128(R.rB, ln.reco * 4, rb * Wp * 16);
+    for (int k = 0; k < kAggK; ++k) {  // step 2: b row yc + k (rows past the last read zeros)
+        const int y = yc + k;
+        const uint32_t rb = (uint32_t)min(y, H + kLMax);
+        in.b2[k] = ld96(R.rB, ln.reco * 3, rb * Wp * 12);
     }
     if (ITERS == 2) {  // step 3: output row yc + w - 2 kLMax - 1
         const int y2 = yc + w - 2 * kLMax - 1;
         const uint32_t rc = (uint32_t)(y2 >= 0 && y2 < H ? y2 : H);
 #pragma unroll
-        for (int j = 0; j < kSeg; ++j) in.c3[j] = ld128(R.rC, ln.recw * 4 + 1024 * j, rc * Wp * 16);
+        for (int j = 0; j < kSeg; ++j) in.c3[j] = ld96(R.rC, ln.recw * 3 + 768 * j, rc * Wp * 12);
     }
 }
 
@@ -444,12 +460,13 @@ __device__ inline void process_chunk(const AggArgs& A, int yc, int y0, int y1, c
 #pragma unroll
             for (int j = 0; j < kSeg; ++j) {
                 if (kFused) {
-                    const uint32_t s = __builtin_amdgcn_sad_u8(in.q[j], in.prgb[j], 0u);
+                    // the top bytes hold L_min: shifted out of the SAD
+                    const uint32_t s = __builtin_amdgcn_sad_u8(in.q[j] << 8, in.prgb[j] << 8, 0u);
                     const uint64_t x = ((uint64_t)in.rcen[j].y << 32 | in.rcen[j].x) ^
                                        ((uint64_t)in.pcen[j].y << 32 | in.pcen[j].x);
                     const uint32_t h = (uint32_t)__popcll(x);
                     const float2 ab = *reinterpret_cast<const float2*>(
-                        reinterpret_cast<const char*>(S.ab) + (in.a1[j] >> 16));
+                        reinterpret_cast<const char*>(S.ab) + (in.q[j] >> 24));
                     const float qa = __builtin_rintf(ab.x * S.tabA[s]);
                     const float qc = __builtin_rintf(ab.y * S.tabC[h]);
                     uint32_t q = (uint32_t)(qa + qc);
@@ -476,7 +493,7 @@ __device__ inline void process_chunk(const AggArgs& A, int yc, int y0, int y1, c
     uint32_t e1[kAggK], s1[kAggK];
 #pragma unroll
     for (int k = 0; k < kAggK; ++k) {
-        const uint32_t a = in.a2[k];
+        const uint32_t a = in.b2[k].z;
         const uint32_t pb = (uint32_t)(k * kPStride + t) * 4;
         e1[k] = lds_ld(S.prow[0], pb + (a & 0xff)) - lds_ld(S.prow[0], pb - ((a >> 8) & 0xff));
     }
@@ -490,20 +507,20 @@ __device__ inline void process_chunk(const AggArgs& A, int yc, int y0, int y1, c
     s1off = off;
 #pragma unroll
     for (int k = 0; k < kAggK; ++k) {
-        const uint32_t o = in.b2[k].w;
+        const uint32_t o = in.b2[k].y;
         s1[k] = lds_ld(S.ring1, ln.cb1 + (o & 0xffff)) - lds_ld(S.ring1, ln.cb1 + (o >> 16));
     }
 #pragma unroll
     for (int k = 0; k < kAggK; ++k) {
-        const uint4 b = in.b2[k];
+        const uint3 b = in.b2[k];
         if (ITERS == 2) {
-            const uint64_t n = (uint64_t)(s1[k] + b.y) * b.x;
-            cp2 += (uint32_t)(n >> b.z);
+            const uint64_t n = (uint64_t)(s1[k] + ((b.z >> 16) & 1023)) * b.x;
+            cp2 += (uint32_t)(n >> (b.z >> 26));
             lds_st(S.ring2, ln.cb2 + s2off, cp2);
             s2off = s2off + kSlotBytes == kRing2 * kSlotBytes ? 0u : s2off + kSlotBytes;
         } else {
             const int yv = yc + k - kLMax;
-            const float a1 = div_q20(s1[k], __builtin_bit_cast(float, b.y),
+            const float a1 = div_q20(s1[k], (float)(b.z >> 16) * 0x1p20f,
                                      __builtin_bit_cast(float, b.x));
             if (yv >= y0 && yv < y1) st32(a1, R.rOut, ln.vout_o, (uint32_t)(yv * W) * 4);
         }
@@ -527,11 +544,11 @@ __device__ inline void process_chunk(const AggArgs& A, int yc, int y0, int y1, c
         const uint32_t pbw = (uint32_t)(w * kPStride + lane) * 4;
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) {
-            const uint32_t lr = in.c3[j].y;
+            const uint32_t lr = in.c3[j].z;
             const uint32_t s2 = lds_ld(S.prow[0], pbw + 256 * j + (lr & 0xff)) -
                                 lds_ld(S.prow[0], pbw + 256 * j - ((lr >> 8) & 0xff));
-            out[j] = div_q20(s2, __builtin_bit_cast(float, in.c3[j].w),
-                             __builtin_bit_cast(float, in.c3[j].z));
+            out[j] = div_q20(s2, (float)(in.c3[j].z >> 16) * 0x1p20f,
+                             __builtin_bit_cast(float, in.c3[j].y));
         }
         if (y2 >= y0 && y2 < y1) {
 #pragma unroll
@@ -598,16 +615,15 @@ __device__ inline void agg_stream(const AggArgs& A, int d, int strip, int y0, in
     const uint64_t* Cref = A.ref == 0 ? A.cenL : A.cenR;
     const uint64_t* Cpar = A.ref == 0 ? A.cenR : A.cenL;
     AggRes R;
-    R.rA = make_rsrc(A.rec.a, recN * 4);
-    R.rB = make_rsrc(A.rec.b, recN * 16);
-    R.rC = make_rsrc(ITERS == 2 ? (const void*)A.rec.c : (const void*)A.rec.a,
-                     ITERS == 2 ? recN * 16 : recN * 4);
-    R.rq = make_rsrc(kFused ? (const void*)A.rec.a : (const void*)(A.cost + (size_t)d * slice),
-                     kFused ? recN * 4 : P4);
-    R.rIr = make_rsrc(kFused ? (const void*)Iref : (const void*)A.rec.a, kFused ? P4 : 0u);
-    R.rIp = make_rsrc(kFused ? (const void*)Ipar : (const void*)A.rec.a, kFused ? P4 : 0u);
-    R.rCr = make_rsrc(kFused ? (const void*)Cref : (const void*)A.rec.a, kFused ? 2 * P4 : 0u);
-    R.rCp = make_rsrc(kFused ? (const void*)Cpar : (const void*)A.rec.a, kFused ? 2 * P4 : 0u);
+    R.rB = make_rsrc(A.rec.b, (uint32_t)(A.rec.Wp * (H + kLMax + 1)) * 12);
+    R.rC = make_rsrc(ITERS == 2 ? (const void*)A.rec.c : (const void*)A.rec.b,
+                     ITERS == 2 ? recN * 12 : 0u);
+    R.rq = make_rsrc(kFused ? (const void*)A.rec.b : (const void*)(A.cost + (size_t)d * slice),
+                     kFused ? 0u : P4);
+    R.rIr = make_rsrc(kFused ? (const void*)Iref : (const void*)A.rec.b, kFused ? P4 : 0u);
+    R.rIp = make_rsrc(kFused ? (const void*)Ipar : (const void*)A.rec.b, kFused ? P4 : 0u);
+    R.rCr = make_rsrc(kFused ? (const void*)Cref : (const void*)A.rec.b, kFused ? 2 * P4 : 0u);
+    R.rCp = make_rsrc(kFused ? (const void*)Cpar : (const void*)A.rec.b, kFused ? 2 * P4 : 0u);
     R.rOut = make_rsrc(A.out + (size_t)d * slice, P4);
     __syncthreads();
 

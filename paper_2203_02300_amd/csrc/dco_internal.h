@@ -20,20 +20,20 @@ constexpr int kStripThreads = 256;
 constexpr int kStripOut = kStripThreads - 4 * kLMax;
 
 // Packed per-pixel records of one view for the aggregation kernels, written
-// by k_geometry.  Each array has H + 1 rows of Wp entries; pixel (x, y) sits
-// at y * Wp + x + apron, and the apron columns and row H are zero.
-//   a[p] = 4 (r + 1) | 4 l << 8 | 8 L_min << 16          (horizontal arms, alpha index)
-//   b[p] = four words for the stage-1 vertical range of p:
-//          two stages: m, N1 / 2, sh  with floor((S1 + N1/2) / N1) =
-//                      ((S1 + N1/2) * m) >> sh
-//          one stage:  RN(1/N1) * 2^-20, N1 * 2^20 (floats), 0
-//          then the ring-1 byte offsets of prefix rows y + dn | y - u - 1 << 16
-//   c[p] = ring-2 byte offsets of prefix rows y + dn | y - u - 1 << 16,
-//          4 (r + 1) | 4 l << 8, RN(1/N2) * 2^-20, N2 * 2^20   (two stages)
+// by k_geometry.  Both arrays hold 3-word entries, Wp per row; column x sits
+// at x + apron, and the apron columns are zero.  With hw(p) = 4 (r + 1) | 4 l << 8
+// (horizontal arms as byte offsets) and ring offsets rb(p) = the byte offsets
+// of prefix rows y + dn and y - u - 1 in a ring (16 bits each):
+//   b row r (H + kLMax + 1 rows; the last is zero), read at stream row r:
+//     two stages: m, rb1, hw(x, r) | (N1/2 | sh << 10) << 16    of pixel (x, r - kLMax)
+//                 for its stage-1 rounding floor((S1 + N1/2) / N1) = ((S1 + N1/2) m) >> sh
+//     one stage:  RN(1/N1) 2^-20, rb1, hw(x, r) | N1 << 16
+//     (hw of row r is 0 from row H on; the rest is 0 above row kLMax)
+//   c row y (H + 1 rows; row H is zero), two stages only:
+//     rb2, RN(1/N2) 2^-20, hw | N2 << 16                         of pixel (x, y)
 struct AggRecords {
-    uint32_t* a;
-    uint4* b;
-    uint4* c;
+    uint32_t* b;
+    uint32_t* c;
     int Wp, apron;
 };
 constexpr int kRecApronL = 2 * kLMax;        // left apron of the records
@@ -150,9 +150,10 @@ void build_tables(const dco_params& p, std::vector<float>& tabA, std::vector<flo
 dco_status alloc_records(AggRecords* r, int W, int H);
 
 // ---- kernel launchers (one per .hip file) ----
+// rgb_packed (optional): R | G << 8 | B << 16, plus 8 L_min << 24 with lmin_byte
 hipError_t launch_census_arms(const uint8_t* rgb, int W, int H, int cw, int ch, int L1, int tau1,
                               uint64_t* census, uint32_t* arms, uint32_t* rgb_packed,
-                              hipStream_t st);
+                              bool lmin_byte, hipStream_t st);
 hipError_t launch_geometry(const uint32_t* arms, int W, int H, int iters, const AggRecords& rec,
                            hipStream_t st);
 hipError_t launch_cost(int ref, const uint8_t* rgbL, const uint8_t* rgbR, const uint64_t* cenL,

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BatchArgs B, int first, 
                 const int y0 = I.b * 64 + r * dco::kCenTH;
                 if (y0 >= H) break;
                 dco::census_tile(img, W, H, B.cw, B.ch, B.L1, B.tau1, pr.cen[I.view],
-                                 pr.arms[I.view], pr.rgbp[I.view], I.a * dco::kCenTW, y0, S);
+                                 pr.arms[I.view], pr.rgbp[I.view], true, I.a * dco::kCenTW, y0, S);
                 __syncthreads();
             }
         } else if constexpr (STAGE == 1) {  // region counts and records of a 64 x 64 block
