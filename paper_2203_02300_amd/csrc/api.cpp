@@ -117,10 +117,10 @@ void build_tables(const dco_params& p, std::vector<float>& tabA, std::vector<flo
 
 static void free_handle_memory(dco_stereo* h) {
     void* ptrs[] = {h->tabA,         h->tabC,         h->alpha,        h->beta,
-                    h->alpha_soft,   h->s.cen[0],     h->s.cen[1],     h->s.arms[0],
+                    h->alpha_soft,   h->s.pix[0],     h->s.pix[1],     h->s.arms[0],
                     h->s.arms[1],    h->s.rec[0].b,   h->s.rec[0].c,
-                    h->s.rec[1].b,   h->s.rec[1].c,   h->s.rgbp[0],
-                    h->s.rgbp[1],    h->s.agg[0],     h->s.agg[1],     h->s.dint[0],
+                    h->s.rec[1].b,   h->s.rec[1].c,
+                    h->s.agg[0],     h->s.agg[1],     h->s.dint[0],
                     h->s.dint[1],    h->s.delta,      h->soft.cen[0],  h->soft.cen[1],
                     h->soft.arms,    h->soft.rgbp[0], h->soft.rgbp[1], h->soft.arms_r,
                     h->soft.n1,      h->soft.n2,      h->soft.tab,     h->soft.vol[0],
@@ -136,10 +136,10 @@ dco_status alloc_records(AggRecords* r, int W, int H) {
     r->Wp = W + kRecApronL + kRecApronR;
     const size_t n = (size_t)r->Wp * (H + 1);
     const size_t nb = (size_t)r->Wp * (H + kLMax + 1);
-    DCO_TRY(dev_alloc(&r->b, 3 * nb));
-    DCO_TRY(dev_alloc(&r->c, 3 * n));
-    DCO_HIP_CHECK(hipMemset(r->b, 0, 3 * nb * sizeof(uint32_t)));
-    DCO_HIP_CHECK(hipMemset(r->c, 0, 3 * n * sizeof(uint32_t)));
+    DCO_TRY(dev_alloc(&r->b, 4 * nb));
+    DCO_TRY(dev_alloc(&r->c, 4 * n));
+    DCO_HIP_CHECK(hipMemset(r->b, 0, 4 * nb * sizeof(uint32_t)));
+    DCO_HIP_CHECK(hipMemset(r->c, 0, 4 * n * sizeof(uint32_t)));
     return DCO_OK;
 }
 
@@ -147,10 +147,9 @@ static dco_status alloc_scratch(dco_stereo* h) {
     const size_t P = (size_t)h->W * h->H, V = P * h->D;
     dco_scratch& s = h->s;
     for (int v = 0; v < 2; ++v) {
-        DCO_TRY(dev_alloc(&s.cen[v], P));
         DCO_TRY(dev_alloc(&s.arms[v], P));
         DCO_TRY(alloc_records(&s.rec[v], h->W, h->H));
-        DCO_TRY(dev_alloc(&s.rgbp[v], P));
+        DCO_TRY(dev_alloc(&s.pix[v], P));
         DCO_TRY(dev_alloc(&s.agg[v], V));
         DCO_TRY(dev_alloc(&s.dint[v], P));
     }
@@ -304,7 +303,7 @@ extern "C" dco_status dco_census(dco_stereo* h, const uint8_t* rgb, uint64_t* ce
     DCO_TRY(need_align(census, 8, "census"));
     DCO_TRY(need_align(arms, 4, "arms"));
     DCO_HIP_CHECK(launch_census_arms(rgb, h->W, h->H, h->p.census_w, h->p.census_h, h->p.arm_L1,
-                                     h->p.arm_tau1, census, (uint32_t*)arms, nullptr, false,
+                                     h->p.arm_tau1, census, (uint32_t*)arms, nullptr, nullptr,
                                      h->stream));
     return DCO_OK;
 }
@@ -387,13 +386,14 @@ extern "C" dco_status dco_stereo_match(dco_stereo* h, const uint8_t* rgbL, const
     DCO_TRY(prof_mark(h));
     for (int v = 0; v < 2; ++v) {
         DCO_HIP_CHECK(launch_census_arms(img[v], h->W, h->H, p.census_w, p.census_h, p.arm_L1,
-                                         p.arm_tau1, s.cen[v], s.arms[v], s.rgbp[v], true, h->stream));
+                                         p.arm_tau1, nullptr, s.arms[v], nullptr, s.pix[v],
+                                         h->stream));
         DCO_HIP_CHECK(launch_geometry(s.arms[v], h->W, h->H, p.agg_iters, s.rec[v], h->stream));
     }
     DCO_TRY(prof_mark(h));
     for (int v = 0; v < 2; ++v) {
         DCO_TRY(prof_mark(h));
-        DCO_HIP_CHECK(launch_cost_aggregate(v, s.rgbp[0], s.rgbp[1], s.cen[0], s.cen[1], s.rec[v],
+        DCO_HIP_CHECK(launch_cost_aggregate(v, s.pix[0], s.pix[1], s.rec[v],
                                             h->W, h->H, h->D, p.agg_iters, h->tabA, h->tabC,
                                             h->alpha, h->beta, p.arm_L1, s.agg[v], h->stream));
         DCO_TRY(prof_mark(h));
@@ -462,10 +462,11 @@ static dco_status soft_front(dco_stereo* h, int B, const uint8_t* L, const uint8
     for (int b = 0; b < B; ++b) {
         DCO_HIP_CHECK(launch_census_arms(L + 3 * P * b, h->W, h->H, p.census_w, p.census_h,
                                          p.arm_L1, p.arm_tau1, f.cen[0] + P * b, f.arms + P * b,
-                                         f.rgbp[0] + P * b, false, h->stream));
+                                         f.rgbp[0] + P * b, nullptr, h->stream));
         DCO_HIP_CHECK(launch_census_arms(R + 3 * P * b, h->W, h->H, p.census_w, p.census_h,
                                          p.arm_L1, p.arm_tau1, f.cen[1] + P * b,
-                                         f.arms_r + P * b, f.rgbp[1] + P * b, false, h->stream));
+                                         f.arms_r + P * b, f.rgbp[1] + P * b, nullptr,
+                                         h->stream));
     }
     DCO_HIP_CHECK(soft_prepare(theta, f.tab, f.arms, B, h->W, h->H, h->D, f.n1, f.n2, h->stream));
     *sb = SoftBuffers{f.arms, f.n1, f.n2, f.rgbp[0], f.rgbp[1], f.cen[0], f.cen[1], h->alpha, f.tab};

@@ -61,9 +61,8 @@ dco_status alloc_pair(dco_batch* b, BatchPair& pr, int W, int H, int D) {
     pr.D = D;
     pr.nstrips = (W + kStripOut - 1) / kStripOut;
     for (int v = 0; v < 2; ++v) {
-        DCO_TRY(balloc(b, &pr.cen[v], P));
         DCO_TRY(balloc(b, &pr.arms[v], P));
-        DCO_TRY(balloc(b, &pr.rgbp[v], P));
+        DCO_TRY(balloc(b, &pr.pix[v], P));
         const dco_status s = alloc_records(&pr.rec[v], W, H);
         for (void* q : {(void*)pr.rec[v].b, (void*)pr.rec[v].c})
             if (q) b->allocs.push_back(q);

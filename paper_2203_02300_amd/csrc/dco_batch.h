@@ -14,9 +14,8 @@ struct BatchPair {
     int band;     // output rows per aggregation item (tuned)
     int dchunk;   // disparities per aggregation item (tuned)
     int nitems[kBatchStages];
-    uint64_t* cen[2];
     uint32_t* arms[2];
-    uint32_t* rgbp[2];
+    uint4* pix[2];   // packed pixels: census, RGB | 8 L_min << 24
     AggRecords rec[2];
     float* agg[2];
     int16_t* dint[2];

@@ -59,7 +59,7 @@ __device__ inline bool close_rgb(const Centre& c, uint32_t b) {
 __device__ inline void census_tile(const uint8_t* __restrict__ rgb, int W, int H, int cw, int ch,
                                    int L1, int tau1, uint64_t* __restrict__ census,
                                    uint32_t* __restrict__ arms, uint32_t* __restrict__ rgb_packed,
-                                   bool lmin_byte, int x0, int y0, CensusLds& S) {
+                                   uint4* __restrict__ pix, int x0, int y0, CensusLds& S) {
     const int t = threadIdx.x;
     for (int i = t; i < kCenRW * kCenRH; i += 256) {
         int ry = i / kCenRW, rx = i - ry * kCenRW;
@@ -91,7 +91,7 @@ __device__ inline void census_tile(const uint8_t* __restrict__ rgb, int W, int H
                 ++bit;
             }
         }
-        census[(size_t)y * W + x] = code;
+        if (census) census[(size_t)y * W + x] = code;
 
         const int rx = tx + kLMax, ry = ty + kLMax;
         const uint32_t cp = S.rgb[ry][rx];
@@ -105,11 +105,14 @@ __device__ inline void census_tile(const uint8_t* __restrict__ rgb, int W, int H
         while (ad < md && close_rgb(cc, S.rgb[ry + ad + 1][rx])) ++ad;
         arms[(size_t)y * W + x] =
             (uint32_t)al | ((uint32_t)ar << 8) | ((uint32_t)au << 16) | ((uint32_t)ad << 24);
-        // packed RGB; with lmin_byte the spare top byte holds 8 L_min (the
-        // alpha-table byte offset of the aggregation kernel's raw cost)
-        if (rgb_packed)
-            rgb_packed[(size_t)y * W + x] =
-                cp | (lmin_byte ? (uint32_t)(8 * min(min(al, ar), min(au, ad))) << 24 : 0u);
+        if (rgb_packed) rgb_packed[(size_t)y * W + x] = cp;
+        // everything the fused raw cost needs of one pixel in one 16-byte
+        // load: census code, packed RGB, and 8 L_min (the byte offset of the
+        // pixel's (alpha, beta) pair) in the top byte
+        if (pix)
+            pix[(size_t)y * W + x] =
+                make_uint4((uint32_t)code, (uint32_t)(code >> 32),
+                           cp | (uint32_t)(8 * min(min(al, ar), min(au, ad))) << 24, 0u);
     }
 }
 
@@ -154,9 +157,9 @@ __device__ inline void write_records(const AggRecords& rec, int x, int y, int it
     const uint32_t lr = 4 * (r + 1) | (4 * l) << 8;
     const uint32_t hi = (uint32_t)y + dn, lo = (uint32_t)y - u - 1;
     const size_t col = (size_t)x + rec.apron;
-    uint32_t* bo = rec.b + 3 * ((size_t)y * rec.Wp + col);
+    uint32_t* bo = rec.b + 4 * ((size_t)y * rec.Wp + col);
     reinterpret_cast<uint16_t*>(bo + 2)[0] = (uint16_t)lr;
-    uint32_t* bv = rec.b + 3 * ((size_t)(y + kLMax) * rec.Wp + col);
+    uint32_t* bv = rec.b + 4 * ((size_t)(y + kLMax) * rec.Wp + col);
     bv[1] = ring_slot_bytes((int)hi, kRing1) | ring_slot_bytes((int)lo, kRing1) << 16;
     if (iters == 2) {
         const uint32_t lg = n1 <= 1 ? 0u : 32u - (uint32_t)__clz((int)(n1 - 1));
@@ -164,7 +167,7 @@ __device__ inline void write_records(const AggRecords& rec, int x, int y, int it
         const uint64_t num = (uint64_t)1 << sh;
         bv[0] = (uint32_t)((num + n1 - 1) / n1);
         reinterpret_cast<uint16_t*>(bv + 2)[1] = (uint16_t)((n1 >> 1) | sh << 10);
-        uint32_t* c = rec.c + 3 * ((size_t)y * rec.Wp + col);
+        uint32_t* c = rec.c + 4 * ((size_t)y * rec.Wp + col);
         c[0] = ring_slot_bytes((int)hi, kRing2) | ring_slot_bytes((int)lo, kRing2) << 16;
         c[1] = __float_as_uint((1.0f / (float)n2) * 0x1p-20f);
         c[2] = lr | n2 << 16;
@@ -300,15 +303,13 @@ __device__ inline uint32_t ld32(rsrc_t r, uint32_t voff, uint32_t soff) {
 __device__ inline uint2 ld64(rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
-__device__ inline uint3 ld96(rsrc_t r, uint32_t voff, uint32_t soff) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0);
-    return make_uint3(v[0], v[1], v[2]);
-}
 __device__ inline uint4 ld128(rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
+// Stores of the aggregated volume are non-temporal (the volume is streamed to
+// HBM and read once by WTA), so they do not evict reused inputs from L2.
 __device__ inline void st32(float v, rsrc_t r, uint32_t voff, uint32_t soff) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 2);
 }
 
 template <unsigned Ctrl, unsigned RowMask>
@@ -365,10 +366,8 @@ __device__ inline float div_q20(uint32_t s, float n_scaled, float rcp_scaled) {
 
 struct AggArgs {
     const float* cost;         // staged: D x H x W raw costs
-    const uint32_t* rgbL;      // fused: packed RGB of both views (H x W)
-    const uint32_t* rgbR;
-    const uint64_t* cenL;      // fused: census codes (H x W)
-    const uint64_t* cenR;
+    const uint4* pixL;         // fused: packed pixels of both views (H x W):
+    const uint4* pixR;         //   census lo, census hi, RGB | 8 L_min << 24, 0
     const float* tabA;         // fused: Eq. 1 tables
     const float* tabC;
     const float* alpha;
@@ -383,17 +382,17 @@ struct AggArgs {
 // column and the chunk's four rows.
 template <bool kFused>
 struct ChunkIn {
-    uint32_t q[kSeg];           // staged: raw cost bits; fused: reference RGB (+ 8 L_min)
-    uint32_t prgb[kSeg];        // fused: partner RGB (+ its own 8 L_min)
-    uint2 rcen[kSeg], pcen[kSeg];
-    uint3 b2[kAggK];            // step 2: records b of rows yc + k
-    uint3 c3[kSeg];             // step 3: records c of the output row
+    uint4 ref[kSeg];            // fused: reference pixel; staged: .x = raw cost bits
+    uint4 par[kSeg];            // fused: partner pixel
+    uint4 b2[kAggK];            // step 2: records b of rows yc + k
+    uint4 c3[kSeg];             // step 3: records c of the output row
 };
 
 // Per-lane constants of a strip.
 struct AggLane {
-    uint32_t img[kSeg];   // byte offset (x4) of each segment column in an H x W map, or kOOB
-    uint32_t par[kSeg];   // fused: the partner column, or kOOB
+    uint32_t img[kSeg];   // byte offset of each segment column in an H x W row (packed
+                          // pixels: x16; cost slice: x4), or kOOB
+    uint32_t par[kSeg];   // fused: the partner column's byte offset, or kOOB
     uint32_t inval[kSeg]; // fused: raw cost when the partner is outside (2^20; 0 off-image)
     uint32_t recw;        // record column index x4 of segment 0 of this lane
     uint32_t reco;        // record column index x4 of the owned column
@@ -406,7 +405,7 @@ struct AggLane {
 };
 
 struct AggRes {
-    rsrc_t rB, rC, rq, rIr, rIp, rCr, rCp, rOut;
+    rsrc_t rB, rC, rq, rIr, rIp, rOut;
 };
 
 template <int ITERS, bool kFused>
@@ -421,12 +420,10 @@ __device__ inline void load_chunk(const AggArgs& A, int yc, const AggLane& ln, c
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) {
             if (kFused) {
-                in.q[j] = ld32(R.rIr, ln.img[j], yq * W * 4);
-                in.prgb[j] = ld32(R.rIp, ln.par[j], yq * W * 4);
-                in.rcen[j] = ld64(R.rCr, ln.img[j] * 2, yq * W * 8);
-                in.pcen[j] = ld64(R.rCp, ln.par[j] * 2, yq * W * 8);
+                in.ref[j] = ld128(R.rIr, ln.img[j], yq * W * 16);
+                in.par[j] = ld128(R.rIp, ln.par[j], yq * W * 16);
             } else {
-                in.q[j] = ld32(R.rq, ln.img[j], yq * W * 4);
+                in.ref[j].x = ld32(R.rq, ln.img[j], yq * W * 4);
             }
         }
     }
@@ -434,13 +431,13 @@ __device__ inline void load_chunk(const AggArgs& A, int yc, const AggLane& ln, c
     for (int k = 0; k < kAggK; ++k) {  // step 2: b row yc + k (rows past the last read zeros)
         const int y = yc + k;
         const uint32_t rb = (uint32_t)min(y, H + kLMax);
-        in.b2[k] = ld96(R.rB, ln.reco * 3, rb * Wp * 12);
+        in.b2[k] = ld128(R.rB, ln.reco * 4, rb * Wp * 16);
     }
     if (ITERS == 2) {  // step 3: output row yc + w - 2 kLMax - 1
         const int y2 = yc + w - 2 * kLMax - 1;
         const uint32_t rc = (uint32_t)(y2 >= 0 && y2 < H ? y2 : H);
 #pragma unroll
-        for (int j = 0; j < kSeg; ++j) in.c3[j] = ld96(R.rC, ln.recw * 3 + 768 * j, rc * Wp * 12);
+        for (int j = 0; j < kSeg; ++j) in.c3[j] = ld128(R.rC, ln.recw * 4 + 1024 * j, rc * Wp * 16);
     }
 }
 
@@ -461,12 +458,13 @@ __device__ inline void process_chunk(const AggArgs& A, int yc, int y0, int y1, c
             for (int j = 0; j < kSeg; ++j) {
                 if (kFused) {
                     // the top bytes hold L_min: shifted out of the SAD
-                    const uint32_t s = __builtin_amdgcn_sad_u8(in.q[j] << 8, in.prgb[j] << 8, 0u);
-                    const uint64_t x = ((uint64_t)in.rcen[j].y << 32 | in.rcen[j].x) ^
-                                       ((uint64_t)in.pcen[j].y << 32 | in.pcen[j].x);
+                    const uint32_t s =
+                        __builtin_amdgcn_sad_u8(in.ref[j].z << 8, in.par[j].z << 8, 0u);
+                    const uint64_t x = ((uint64_t)in.ref[j].y << 32 | in.ref[j].x) ^
+                                       ((uint64_t)in.par[j].y << 32 | in.par[j].x);
                     const uint32_t h = (uint32_t)__popcll(x);
                     const float2 ab = *reinterpret_cast<const float2*>(
-                        reinterpret_cast<const char*>(S.ab) + (in.q[j] >> 24));
+                        reinterpret_cast<const char*>(S.ab) + (in.ref[j].z >> 24));
                     const float qa = __builtin_rintf(ab.x * S.tabA[s]);
                     const float qc = __builtin_rintf(ab.y * S.tabC[h]);
                     uint32_t q = (uint32_t)(qa + qc);
@@ -475,7 +473,7 @@ __device__ inline void process_chunk(const AggArgs& A, int yc, int y0, int y1, c
                     asm volatile("" : "+v"(q));
                     v[j] = ln.pok[j] ? q : ln.inval[j];
                 } else {
-                    v[j] = (uint32_t)(__builtin_bit_cast(float, in.q[j]) * 1048576.0f);
+                    v[j] = (uint32_t)(__builtin_bit_cast(float, in.ref[j].x) * 1048576.0f);
                 }
             }
         } else {
@@ -512,7 +510,7 @@ __device__ inline void process_chunk(const AggArgs& A, int yc, int y0, int y1, c
     }
 #pragma unroll
     for (int k = 0; k < kAggK; ++k) {
-        const uint3 b = in.b2[k];
+        const uint4 b = in.b2[k];
         if (ITERS == 2) {
             const uint64_t n = (uint64_t)(s1[k] + ((b.z >> 16) & 1023)) * b.x;
             cp2 += (uint32_t)(n >> (b.z >> 26));
@@ -588,8 +586,8 @@ __device__ inline void agg_stream(const AggArgs& A, int d, int strip, int y0, in
         const bool in_img = c >= 0 && c < W;
         const int cp = A.ref == 0 ? c - d : c + d;
         const bool pok = in_img && cp >= 0 && cp < W;
-        ln.img[j] = in_img ? (uint32_t)c * 4 : kOOB;
-        ln.par[j] = pok ? (uint32_t)cp * 4 : kOOB;
+        ln.img[j] = in_img ? (uint32_t)c * (kFused ? 16 : 4) : kOOB;
+        ln.par[j] = pok ? (uint32_t)cp * 16 : kOOB;
         ln.pok[j] = pok;
         ln.inval[j] = in_img ? (1u << 20) : 0u;
         const bool rok = i >= kLMax && i < kLMax + kRingCols;
@@ -610,20 +608,16 @@ __device__ inline void agg_stream(const AggArgs& A, int d, int strip, int y0, in
     }
     const uint32_t recN = (uint32_t)(A.rec.Wp * (H + 1));
     const uint32_t P4 = (uint32_t)(slice * 4);
-    const uint32_t* Iref = A.ref == 0 ? A.rgbL : A.rgbR;
-    const uint32_t* Ipar = A.ref == 0 ? A.rgbR : A.rgbL;
-    const uint64_t* Cref = A.ref == 0 ? A.cenL : A.cenR;
-    const uint64_t* Cpar = A.ref == 0 ? A.cenR : A.cenL;
+    const uint4* Iref = A.ref == 0 ? A.pixL : A.pixR;
+    const uint4* Ipar = A.ref == 0 ? A.pixR : A.pixL;
     AggRes R;
-    R.rB = make_rsrc(A.rec.b, (uint32_t)(A.rec.Wp * (H + kLMax + 1)) * 12);
+    R.rB = make_rsrc(A.rec.b, (uint32_t)(A.rec.Wp * (H + kLMax + 1)) * 16);
     R.rC = make_rsrc(ITERS == 2 ? (const void*)A.rec.c : (const void*)A.rec.b,
-                     ITERS == 2 ? recN * 12 : 0u);
+                     ITERS == 2 ? recN * 16 : 0u);
     R.rq = make_rsrc(kFused ? (const void*)A.rec.b : (const void*)(A.cost + (size_t)d * slice),
                      kFused ? 0u : P4);
-    R.rIr = make_rsrc(kFused ? (const void*)Iref : (const void*)A.rec.b, kFused ? P4 : 0u);
-    R.rIp = make_rsrc(kFused ? (const void*)Ipar : (const void*)A.rec.b, kFused ? P4 : 0u);
-    R.rCr = make_rsrc(kFused ? (const void*)Cref : (const void*)A.rec.b, kFused ? 2 * P4 : 0u);
-    R.rCp = make_rsrc(kFused ? (const void*)Cpar : (const void*)A.rec.b, kFused ? 2 * P4 : 0u);
+    R.rIr = make_rsrc(kFused ? (const void*)Iref : (const void*)A.rec.b, kFused ? 4 * P4 : 0u);
+    R.rIp = make_rsrc(kFused ? (const void*)Ipar : (const void*)A.rec.b, kFused ? 4 * P4 : 0u);
     R.rOut = make_rsrc(A.out + (size_t)d * slice, P4);
     __syncthreads();
 
@@ -648,8 +642,8 @@ __device__ inline void agg_stream(const AggArgs& A, int d, int strip, int y0, in
 }
 
 // Work item of block b of n, remapped so that the blocks one XCD runs
-// (round-robin block -> XCD dispatch) get consecutive items: neighbouring
-// strips of the same slice share their apron columns in that XCD's L2.
+// (round-robin block -> XCD dispatch) get consecutive items, which then
+// share their inputs in that XCD's L2.
 __device__ inline int xcd_work_item(int b, int n) {
     const int xcd = b & 7, i = b >> 3;
     const int per = n >> 3, rem = n & 7;

@@ -20,8 +20,9 @@ constexpr int kStripThreads = 256;
 constexpr int kStripOut = kStripThreads - 4 * kLMax;
 
 // Packed per-pixel records of one view for the aggregation kernels, written
-// by k_geometry.  Both arrays hold 3-word entries, Wp per row; column x sits
-// at x + apron, and the apron columns are zero.  With hw(p) = 4 (r + 1) | 4 l << 8
+// by k_geometry.  Both arrays hold 4-word entries (the fourth is unused: one
+// 16-byte load per pixel is cheaper than a 12-byte one), Wp per row; column x
+// sits at x + apron, and the apron columns are zero.  With hw(p) = 4 (r + 1) | 4 l << 8
 // (horizontal arms as byte offsets) and ring offsets rb(p) = the byte offsets
 // of prefix rows y + dn and y - u - 1 in a ring (16 bits each):
 //   b row r (H + kLMax + 1 rows; the last is zero), read at stream row r:
@@ -41,10 +42,9 @@ constexpr int kRecApronR = kStripThreads;    // right apron (covers a strip's ov
 
 // Scratch owned by a matcher handle for the one-call path.
 struct dco_scratch {
-    uint64_t* cen[2];
     uint32_t* arms[2];
     AggRecords rec[2];
-    uint32_t* rgbp[2];  // packed RGB of both views
+    uint4* pix[2];      // packed pixels of both views: census, RGB | 8 L_min << 24
     float* agg[2];      // aggregated volumes of both views (D x H x W)
     int16_t* dint[2];
     float* delta;
@@ -150,10 +150,11 @@ void build_tables(const dco_params& p, std::vector<float>& tabA, std::vector<flo
 dco_status alloc_records(AggRecords* r, int W, int H);
 
 // ---- kernel launchers (one per .hip file) ----
-// rgb_packed (optional): R | G << 8 | B << 16, plus 8 L_min << 24 with lmin_byte
+// census, rgb_packed (R | G << 8 | B << 16) and pix (census lo, census hi,
+// packed RGB | 8 L_min << 24, 0) are optional outputs
 hipError_t launch_census_arms(const uint8_t* rgb, int W, int H, int cw, int ch, int L1, int tau1,
-                              uint64_t* census, uint32_t* arms, uint32_t* rgb_packed,
-                              bool lmin_byte, hipStream_t st);
+                              uint64_t* census, uint32_t* arms, uint32_t* rgb_packed, uint4* pix,
+                              hipStream_t st);
 hipError_t launch_geometry(const uint32_t* arms, int W, int H, int iters, const AggRecords& rec,
                            hipStream_t st);
 hipError_t launch_cost(int ref, const uint8_t* rgbL, const uint8_t* rgbR, const uint64_t* cenL,
@@ -162,8 +163,7 @@ hipError_t launch_cost(int ref, const uint8_t* rgbL, const uint8_t* rgbR, const 
                        const float* beta, int L1, float* cost, hipStream_t st);
 hipError_t launch_aggregate(const float* cost, const AggRecords& rec, int W, int H, int D,
                             int iters, float* out, hipStream_t st);
-hipError_t launch_cost_aggregate(int ref, const uint32_t* rgbL, const uint32_t* rgbR,
-                                 const uint64_t* cenL, const uint64_t* cenR,
+hipError_t launch_cost_aggregate(int ref, const uint4* pixL, const uint4* pixR,
                                  const AggRecords& rec, int W, int H, int D, int iters,
                                  const float* tabA, const float* tabC, const float* alpha,
                                  const float* beta, int L1, float* out, hipStream_t st);

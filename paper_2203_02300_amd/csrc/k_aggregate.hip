@@ -12,8 +12,11 @@ namespace {
 template <int ITERS, bool kFused>
 __global__ __launch_bounds__(kStripThreads, 2) void k_agg_stream(dco::AggArgs A) {
     __shared__ dco::AggLds<ITERS, kFused> S;
+    // strip-major items, consecutive per XCD: the workgroups one XCD runs at
+    // a time share a strip (its records and reference pixels) and read
+    // overlapping partner columns, so most loads hit that XCD's L2
     const int work = dco::xcd_work_item(blockIdx.x, A.nstrips * A.D);
-    const int d = work / A.nstrips, strip = work - d * A.nstrips;
+    const int strip = work / A.D, d = work - strip * A.D;
     dco::agg_stream<ITERS, kFused>(A, d, strip, 0, A.H, S);
 }
 
@@ -39,16 +42,13 @@ hipError_t launch_aggregate(const float* cost, const AggRecords& rec, int W, int
     return iters == 1 ? launch_stream<1, false>(a, st) : launch_stream<2, false>(a, st);
 }
 
-hipError_t launch_cost_aggregate(int ref, const uint32_t* rgbL, const uint32_t* rgbR,
-                                 const uint64_t* cenL, const uint64_t* cenR,
+hipError_t launch_cost_aggregate(int ref, const uint4* pixL, const uint4* pixR,
                                  const AggRecords& rec, int W, int H, int D, int iters,
                                  const float* tabA, const float* tabC, const float* alpha,
                                  const float* beta, int L1, float* out, hipStream_t st) {
     dco::AggArgs a{};
-    a.rgbL = rgbL;
-    a.rgbR = rgbR;
-    a.cenL = cenL;
-    a.cenR = cenR;
+    a.pixL = pixL;
+    a.pixR = pixR;
     a.tabA = tabA;
     a.tabC = tabC;
     a.alpha = alpha;

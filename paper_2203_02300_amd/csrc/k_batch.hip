@@ -45,8 +45,8 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BatchArgs B, int first, 
             for (int r = 0; r < 4; ++r) {
                 const int y0 = I.b * 64 + r * dco::kCenTH;
                 if (y0 >= H) break;
-                dco::census_tile(img, W, H, B.cw, B.ch, B.L1, B.tau1, pr.cen[I.view],
-                                 pr.arms[I.view], pr.rgbp[I.view], true, I.a * dco::kCenTW, y0, S);
+                dco::census_tile(img, W, H, B.cw, B.ch, B.L1, B.tau1, nullptr, pr.arms[I.view],
+                                 nullptr, pr.pix[I.view], I.a * dco::kCenTW, y0, S);
                 __syncthreads();
             }
         } else if constexpr (STAGE == 1) {  // region counts and records of a 64 x 64 block
@@ -59,10 +59,8 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BatchArgs B, int first, 
             }
         } else if constexpr (STAGE == 2) {  // slices a .. a+dchunk-1, strip b, row band c
             dco::AggArgs A{};
-            A.rgbL = pr.rgbp[0];
-            A.rgbR = pr.rgbp[1];
-            A.cenL = pr.cen[0];
-            A.cenR = pr.cen[1];
+            A.pixL = pr.pix[0];
+            A.pixR = pr.pix[1];
             A.tabA = B.tabA;
             A.tabC = B.tabC;
             A.alpha = B.alpha;

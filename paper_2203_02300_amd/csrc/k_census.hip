@@ -10,9 +10,9 @@ __global__ __launch_bounds__(256) void k_census_arms(const uint8_t* __restrict__
                                                      uint64_t* __restrict__ census,
                                                      uint32_t* __restrict__ arms,
                                                      uint32_t* __restrict__ rgb_packed,
-                                                     bool lmin_byte) {
+                                                     uint4* __restrict__ pix) {
     __shared__ dco::CensusLds S;
-    dco::census_tile(rgb, W, H, cw, ch, L1, tau1, census, arms, rgb_packed, lmin_byte,
+    dco::census_tile(rgb, W, H, cw, ch, L1, tau1, census, arms, rgb_packed, pix,
                      blockIdx.x * dco::kCenTW, blockIdx.y * dco::kCenTH, S);
 }
 
@@ -26,11 +26,11 @@ __global__ __launch_bounds__(256) void k_geometry(const uint32_t* __restrict__ a
 }  // namespace
 
 hipError_t launch_census_arms(const uint8_t* rgb, int W, int H, int cw, int ch, int L1, int tau1,
-                              uint64_t* census, uint32_t* arms, uint32_t* rgb_packed,
-                              bool lmin_byte, hipStream_t st) {
+                              uint64_t* census, uint32_t* arms, uint32_t* rgb_packed, uint4* pix,
+                              hipStream_t st) {
     dim3 grid((W + dco::kCenTW - 1) / dco::kCenTW, (H + dco::kCenTH - 1) / dco::kCenTH);
     hipLaunchKernelGGL(k_census_arms, grid, dim3(256), 0, st, rgb, W, H, cw, ch, L1, tau1, census,
-                       arms, rgb_packed, lmin_byte);
+                       arms, rgb_packed, pix);
     return hipGetLastError();
 }
 
