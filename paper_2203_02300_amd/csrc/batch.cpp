@@ -37,6 +37,7 @@ struct dco_batch {
     bool io_pending = false;
     BatchItem* d_items = nullptr;
     int first[kBatchStages + 1] = {};  // stage s owns items [first[s], first[s + 1])
+    int xsplit[kXcds + 1] = {};        // stage-2 items of each XCD
     int cus = 0;
     int per_cu[kBatchStages] = {};
     float *tabA = nullptr, *tabC = nullptr, *alpha = nullptr, *beta = nullptr;
@@ -75,7 +76,7 @@ dco_status alloc_pair(dco_batch* b, BatchPair& pr, int W, int H, int D) {
 }
 
 // Stage-ordered work list; within stage 2 the longest items come first.
-std::vector<BatchItem> make_items(std::vector<BatchPair>& pairs) {
+std::vector<BatchItem> make_items(std::vector<BatchPair>& pairs, int* xsplit) {
     std::vector<BatchItem> st[kBatchStages];
     for (int i = 0; i < (int)pairs.size(); ++i) {
         BatchPair& pr = pairs[i];
@@ -88,10 +89,12 @@ std::vector<BatchItem> make_items(std::vector<BatchPair>& pairs) {
                     st[0].push_back(BatchItem{i, 0, v, x, y, 0});
                     st[1].push_back(BatchItem{i, 1, v, x, y, 0});
                 }
+        // neighbouring disparities of one strip and band next to each other:
+        // the workgroups that run them at the same time share their inputs
         for (int v = 0; v < 2; ++v)
-            for (int c = 0; c < nb; ++c)
-                for (int d = 0; d < nd; ++d)
-                    for (int s = 0; s < pr.nstrips; ++s)
+            for (int s = 0; s < pr.nstrips; ++s)
+                for (int c = 0; c < nb; ++c)
+                    for (int d = 0; d < nd; ++d)
                         st[2].push_back(BatchItem{i, 2, v, d * pr.dchunk, s, c});
         const int P = pr.W * pr.H;
         for (int a = 0; a < P; a += kWtaPx) st[3].push_back(BatchItem{i, 3, 0, a, 0, 0});
@@ -107,8 +110,18 @@ std::vector<BatchItem> make_items(std::vector<BatchPair>& pairs) {
         const int dn = std::min(pr.dchunk, pr.D - it.a);
         return (long long)(rows + 4 * kLMax + 2) * dn;
     };
-    std::stable_sort(st[2].begin(), st[2].end(),
-                     [&](const BatchItem& a, const BatchItem& b) { return cost(a) > cost(b); });
+    // stage 2 in kXcds contiguous parts of about equal cost, one per XCD
+    const int s2 = (int)(st[0].size() + st[1].size());
+    long long total = 0;
+    for (const BatchItem& it : st[2]) total += cost(it);
+    long long acc = 0;
+    int x = 1;
+    xsplit[0] = s2;
+    for (size_t k = 0; k < st[2].size() && x < kXcds; ++k) {
+        acc += cost(st[2][k]);
+        while (x < kXcds && acc * kXcds >= total * x) xsplit[x++] = s2 + (int)k + 1;
+    }
+    while (x <= kXcds) xsplit[x++] = s2 + (int)st[2].size();
     std::vector<BatchItem> all;
     for (auto& s : st) all.insert(all.end(), s.begin(), s.end());
     return all;
@@ -129,6 +142,7 @@ BatchArgs make_args(const dco_batch* b) {
     a.tau1 = b->p.arm_tau1;
     a.subpixel = b->p.subpixel;
     a.maxdiff = b->p.lr_max_diff;
+    for (int x = 0; x <= kXcds; ++x) a.xsplit[x] = b->xsplit[x];
     return a;
 }
 
@@ -162,7 +176,7 @@ dco_status check_items(const std::vector<BatchItem>& items, const std::vector<Ba
 
 // (Re)build the work list and upload pairs and items.
 dco_status upload(dco_batch* b) {
-    std::vector<BatchItem> items = make_items(b->pairs);
+    std::vector<BatchItem> items = make_items(b->pairs, b->xsplit);
     DCO_TRY(check_items(items, b->pairs, b->first));
     if (b->d_items) {
         (void)hipFree(b->d_items);
@@ -216,6 +230,7 @@ hipError_t launch(const dco_batch* b, hipStream_t st) {
     int grid[kBatchStages];
     for (int s = 0; s < kBatchStages; ++s)
         grid[s] = std::max(1, std::min(b->first[s + 1] - b->first[s], b->cus * b->per_cu[s]));
+    grid[2] = std::max(kXcds, b->cus * b->per_cu[2] / kXcds * kXcds);
     return launch_batch(make_args(b), b->p.agg_iters, b->first, grid, st);
 }
 

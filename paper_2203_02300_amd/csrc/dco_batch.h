@@ -7,6 +7,7 @@
 constexpr int kBatchStages = 5;  // census, records, cost + aggregation, WTA, LR
 constexpr int kWtaPx = 4096;     // pixels per WTA item
 constexpr int kLrRows = 16;      // rows per LR item
+constexpr int kXcds = 8;         // accelerator dies; workgroup b runs on XCD b % 8
 
 // Static description and scratch of one pair.
 struct BatchPair {
@@ -43,10 +44,15 @@ struct BatchArgs {
     const float* alpha;
     const float* beta;
     int cw, ch, L1, tau1, subpixel, maxdiff;
+    // stage 2: XCD x runs items [xsplit[x], xsplit[x + 1]) (absolute indices);
+    // the parts are contiguous runs of one (pair, view, strip, band) with
+    // neighbouring disparities, of about equal cost
+    int xsplit[kXcds + 1];
 };
 
 // Launches the five stage kernels on `st`: stage s handles items
-// [first[s], first[s + 1]) with grid[s] workgroups.
+// [first[s], first[s + 1]) with grid[s] workgroups (a multiple of kXcds for
+// stage 2).
 hipError_t launch_batch(const BatchArgs& a, int iters, const int* first, const int* grid,
                         hipStream_t st);
 // Resident workgroups per CU of each stage kernel.

@@ -50,6 +50,38 @@ __device__ inline bool close_rgb(const Centre& c, uint32_t b) {
     return max(max(dr, dg), db) < c.lim;
 }
 
+// Census code of tile pixel (tx, ty) from the grey levels in LDS: bit k is
+// set when neighbour k (row-major over the window, centre skipped) is darker
+// than the centre.  The fixed-size form unrolls, so its LDS reads pipeline.
+template <int HW, int HH>
+__device__ inline uint64_t census_code(const CensusLds& S, int tx, int ty) {
+    const uint32_t c = S.grey[ty + kCenHH][tx + kCenHW];
+    uint64_t code = 0;
+    int bit = 0;
+#pragma unroll
+    for (int dy = -HH; dy <= HH; ++dy)
+#pragma unroll
+        for (int dx = -HW; dx <= HW; ++dx) {
+            if (dy == 0 && dx == 0) continue;
+            code |= (uint64_t)(S.grey[ty + kCenHH + dy][tx + kCenHW + dx] < c) << bit;
+            ++bit;
+        }
+    return code;
+}
+
+__device__ inline uint64_t census_code_any(const CensusLds& S, int tx, int ty, int hw, int hh) {
+    const uint32_t c = S.grey[ty + kCenHH][tx + kCenHW];
+    uint64_t code = 0;
+    int bit = 0;
+    for (int dy = -hh; dy <= hh; ++dy)
+        for (int dx = -hw; dx <= hw; ++dx) {
+            if (dy == 0 && dx == 0) continue;
+            code |= (uint64_t)(S.grey[ty + kCenHH + dy][tx + kCenHW + dx] < c) << bit;
+            ++bit;
+        }
+    return code;
+}
+
 // One 64 x 16 tile at (x0, y0), 256 threads.  The tile plus a kLMax apron
 // (edge-clamped) is staged in LDS as packed RGB words; grey levels of the
 // tile plus the census apron go to a second array.
@@ -80,29 +112,29 @@ __device__ inline void census_tile(const uint8_t* __restrict__ rgb, int W, int H
         const int ty = (t >> 6) + 4 * k;
         const int x = x0 + tx, y = y0 + ty;
         if (x >= W || y >= H) continue;
-        const uint32_t c = S.grey[ty + kCenHH][tx + kCenHW];
-        uint64_t code = 0;
-        int bit = 0;
-        for (int dy = -hh; dy <= hh; ++dy) {
-            for (int dx = -hw; dx <= hw; ++dx) {
-                if (dy == 0 && dx == 0) continue;
-                uint32_t v = S.grey[ty + kCenHH + dy][tx + kCenHW + dx];
-                code |= (uint64_t)(v < c) << bit;
-                ++bit;
-            }
-        }
+        const uint64_t code = cw == 9 && ch == 7
+                                  ? census_code<4, 3>(S, tx, ty)
+                                  : census_code_any(S, tx, ty, hw, hh);
         if (census) census[(size_t)y * W + x] = code;
 
         const int rx = tx + kLMax, ry = ty + kLMax;
         const uint32_t cp = S.rgb[ry][rx];
-        int al = 0, ar = 0, au = 0, ad = 0;
-        const int ml = min(L1, x), mr = min(L1, W - 1 - x);
-        const int mu = min(L1, y), md = min(L1, H - 1 - y);
+        // each arm: the closeness of all kLMax steps as a bit mask (the reads
+        // are independent, so they pipeline), then the run of ones from
+        // step 1, capped by L1 and the border
         const Centre cc = centre_of(cp, tau1);
-        while (al < ml && close_rgb(cc, S.rgb[ry][rx - al - 1])) ++al;
-        while (ar < mr && close_rgb(cc, S.rgb[ry][rx + ar + 1])) ++ar;
-        while (au < mu && close_rgb(cc, S.rgb[ry - au - 1][rx])) ++au;
-        while (ad < md && close_rgb(cc, S.rgb[ry + ad + 1][rx])) ++ad;
+        uint32_t ml = 0, mr = 0, mu = 0, md = 0;
+#pragma unroll
+        for (int j = 1; j <= kLMax; ++j) {
+            ml |= (uint32_t)close_rgb(cc, S.rgb[ry][rx - j]) << (j - 1);
+            mr |= (uint32_t)close_rgb(cc, S.rgb[ry][rx + j]) << (j - 1);
+            mu |= (uint32_t)close_rgb(cc, S.rgb[ry - j][rx]) << (j - 1);
+            md |= (uint32_t)close_rgb(cc, S.rgb[ry + j][rx]) << (j - 1);
+        }
+        const int al = min(min(L1, x), __builtin_ctz(~ml));
+        const int ar = min(min(L1, W - 1 - x), __builtin_ctz(~mr));
+        const int au = min(min(L1, y), __builtin_ctz(~mu));
+        const int ad = min(min(L1, H - 1 - y), __builtin_ctz(~md));
         arms[(size_t)y * W + x] =
             (uint32_t)al | ((uint32_t)ar << 8) | ((uint32_t)au << 16) | ((uint32_t)ad << 24);
         if (rgb_packed) rgb_packed[(size_t)y * W + x] = cp;

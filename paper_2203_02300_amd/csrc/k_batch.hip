@@ -35,7 +35,16 @@ template <int ITERS, int STAGE>
 __global__ __launch_bounds__(256, 2) void k_batch_stage(BatchArgs B, int first, int count) {
     __shared__ StageLds<ITERS, STAGE> S;
     const int t = threadIdx.x;
-    for (int k = blockIdx.x; k < count; k += gridDim.x) {
+    // stage 2: the workgroups of XCD x (blockIdx % kXcds) share that XCD's
+    // contiguous part of the list; other stages stride over the whole list
+    int k0 = blockIdx.x, kend = count, kstep = gridDim.x;
+    if (STAGE == 2) {
+        const int x = blockIdx.x % kXcds;
+        k0 = B.xsplit[x] - first + blockIdx.x / kXcds;
+        kend = B.xsplit[x + 1] - first;
+        kstep = gridDim.x / kXcds;
+    }
+    for (int k = k0; k < kend; k += kstep) {
         const BatchItem I = B.items[first + k];
         const BatchPair& pr = B.pairs[I.pair];
         const BatchIO& io = B.io[I.pair];
