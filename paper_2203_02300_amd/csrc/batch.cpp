@@ -230,7 +230,9 @@ hipError_t launch(const dco_batch* b, hipStream_t st) {
     int grid[kBatchStages];
     for (int s = 0; s < kBatchStages; ++s)
         grid[s] = std::max(1, std::min(b->first[s + 1] - b->first[s], b->cus * b->per_cu[s]));
-    grid[2] = std::max(kXcds, b->cus * b->per_cu[2] / kXcds * kXcds);
+    int most = 1;  // stage 2: one workgroup per item, kXcds x the largest XCD part
+    for (int x = 0; x < kXcds; ++x) most = std::max(most, b->xsplit[x + 1] - b->xsplit[x]);
+    grid[2] = kXcds * most;
     return launch_batch(make_args(b), b->p.agg_iters, b->first, grid, st);
 }
 
@@ -293,11 +295,26 @@ std::vector<Tile> candidates(int H, int D) {
     return out;
 }
 
-// Times every candidate tile on a synthetic pair of one size class.
+// Times every candidate tile on copies of a synthetic pair of one size class.
+// There are enough copies that the untiled cost + aggregation stage has about
+// four times as many items as resident workgroups, as in a full batch:
+// timed alone, one small pair would favour short bands for parallelism that
+// a batch gets from its other pairs anyway.
 dco_status tune_class(const dco_params& p, int W, int H, int D, hipStream_t st, Tile* best) {
     dco_batch tb;
     dco_status s = make_base(&tb, 1, p);
-    if (s == DCO_OK) s = alloc_pair(&tb, tb.pairs[0], W, H, D);
+    int copies = 1;
+    if (s == DCO_OK) {
+        const int nstrips = (W + kStripOut - 1) / kStripOut;
+        const long long slots = (long long)tb.cus * std::max(1, tb.per_cu[2]);
+        copies = (int)std::min<long long>(16, std::max<long long>(
+                                                   1, (4 * slots + 2LL * nstrips * D - 1) /
+                                                          (2LL * nstrips * D)));
+        release(&tb);
+        tb = dco_batch{};
+        s = make_base(&tb, copies, p);
+    }
+    for (int i = 0; i < copies && s == DCO_OK; ++i) s = alloc_pair(&tb, tb.pairs[i], W, H, D);
     uint8_t *L = nullptr, *R = nullptr;
     if (s == DCO_OK) s = balloc(&tb, &L, (size_t)W * H * 3);
     if (s == DCO_OK) s = balloc(&tb, &R, (size_t)W * H * 3);
@@ -322,8 +339,10 @@ dco_status tune_class(const dco_params& p, int W, int H, int D, hipStream_t st, 
                 img2[((size_t)y * W + c) * 3 + k] = img[((size_t)y * W + std::min(W - 1, c + D / 2)) * 3 + k];
     hipError_t e = hipMemcpy(L, img.data(), img.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(R, img2.data(), img2.size(), hipMemcpyHostToDevice);
-    BatchIO io{L, R, disp, valid};
-    if (e == hipSuccess) e = hipMemcpy(tb.d_io, &io, sizeof io, hipMemcpyHostToDevice);
+    // every copy reads the same pair and writes the same maps (identical values)
+    const std::vector<BatchIO> io(copies, BatchIO{L, R, disp, valid});
+    if (e == hipSuccess)
+        e = hipMemcpy(tb.d_io, io.data(), io.size() * sizeof(BatchIO), hipMemcpyHostToDevice);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -331,8 +350,10 @@ dco_status tune_class(const dco_params& p, int W, int H, int D, hipStream_t st, 
     *best = Tile{H, 1};
     for (const Tile& c : candidates(H, D)) {
         if (e != hipSuccess) break;
-        tb.pairs[0].band = c.band;
-        tb.pairs[0].dchunk = c.dchunk;
+        for (BatchPair& pr : tb.pairs) {
+            pr.band = c.band;
+            pr.dchunk = c.dchunk;
+        }
         if ((s = upload(&tb)) != DCO_OK) break;
         float ms[3];
         e = launch(&tb, st);  // warm-up

@@ -6,7 +6,7 @@
 
 constexpr int kBatchStages = 5;  // census, records, cost + aggregation, WTA, LR
 constexpr int kWtaPx = 4096;     // pixels per WTA item
-constexpr int kLrRows = 16;      // rows per LR item
+constexpr int kLrRows = 2;       // rows per LR item
 constexpr int kXcds = 8;         // accelerator dies; workgroup b runs on XCD b % 8
 
 // Static description and scratch of one pair.
@@ -51,8 +51,8 @@ struct BatchArgs {
 };
 
 // Launches the five stage kernels on `st`: stage s handles items
-// [first[s], first[s + 1]) with grid[s] workgroups (a multiple of kXcds for
-// stage 2).
+// [first[s], first[s + 1]) with grid[s] workgroups (stage 2: one per item,
+// kXcds times the largest per-XCD part).
 hipError_t launch_batch(const BatchArgs& a, int iters, const int* first, const int* grid,
                         hipStream_t st);
 // Resident workgroups per CU of each stage kernel.

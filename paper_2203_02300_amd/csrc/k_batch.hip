@@ -35,14 +35,16 @@ template <int ITERS, int STAGE>
 __global__ __launch_bounds__(256, 2) void k_batch_stage(BatchArgs B, int first, int count) {
     __shared__ StageLds<ITERS, STAGE> S;
     const int t = threadIdx.x;
-    // stage 2: the workgroups of XCD x (blockIdx % kXcds) share that XCD's
-    // contiguous part of the list; other stages stride over the whole list
+    // stage 2: one item per workgroup, the workgroups of XCD x (blockIdx %
+    // kXcds, dispatched in order) taking that XCD's contiguous part of the
+    // list, so the hardware dispatcher balances the items; the other stages
+    // are persistent and stride over the whole list
     int k0 = blockIdx.x, kend = count, kstep = gridDim.x;
     if (STAGE == 2) {
         const int x = blockIdx.x % kXcds;
         k0 = B.xsplit[x] - first + blockIdx.x / kXcds;
-        kend = B.xsplit[x + 1] - first;
-        kstep = gridDim.x / kXcds;
+        kend = min(B.xsplit[x + 1] - first, k0 + 1);
+        kstep = 1;
     }
     for (int k = k0; k < kend; k += kstep) {
         const BatchItem I = B.items[first + k];
@@ -90,11 +92,21 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BatchArgs B, int first, 
             }
         } else if constexpr (STAGE == 3) {  // WTA of both views for pixels [a, a + kWtaPx)
             const int P = W * H;
-            for (int r = 0; r < kWtaPx / 256; ++r) {
-                const int i = I.a + r * 256 + t;
-                if (i >= P) break;
-                dco::wta_pixel(pr.agg[0], P, pr.D, i, B.subpixel, pr.dint[0] + i, pr.delta + i);
-                dco::wta_pixel(pr.agg[1], P, pr.D, i, B.subpixel, pr.dint[1] + i, nullptr);
+            if (P % 4 == 0) {  // 16-byte loads (the pair's buffers are 256-byte aligned)
+                for (int r = 0; r < kWtaPx / 1024; ++r) {
+                    const int i4 = I.a + (r * 256 + t) * 4;
+                    if (i4 >= P) break;
+                    dco::wta_quad(pr.agg[0], P, pr.D, i4, B.subpixel, pr.dint[0], pr.delta);
+                    dco::wta_quad(pr.agg[1], P, pr.D, i4, B.subpixel, pr.dint[1], nullptr);
+                }
+            } else {
+                for (int r = 0; r < kWtaPx / 256; ++r) {
+                    const int i = I.a + r * 256 + t;
+                    if (i >= P) break;
+                    dco::wta_pixel(pr.agg[0], P, pr.D, i, B.subpixel, pr.dint[0] + i,
+                                   pr.delta + i);
+                    dco::wta_pixel(pr.agg[1], P, pr.D, i, B.subpixel, pr.dint[1] + i, nullptr);
+                }
             }
         } else {  // LR check of rows [a, a + kLrRows)
             for (int y = I.a; y < min(H, I.a + kLrRows); ++y)
