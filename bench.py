@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # 4 cycles (16 lanes per cycle each): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 METRIC = "Mpix·disp/s and ms/frame at 1280x720 D=128 vs oracle; batched & fwd+bwd vs plain"
-STAGES = ("census+arms+counts", "cost+aggregate L", "cost+aggregate R", "wta", "lrcheck")
+STAGES = ("census+arms+counts", "cost+aggregate L+R", "wta", "lrcheck")
 
 
 TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
@@ -140,16 +140,16 @@ def main():
     units = W * H * D
     value = units / (ms_step / 1e3) / 1e6
     P, V = W * H, W * H * D
-    # dominant kernel: cost + aggregation of one view (stages 1 and 2)
-    agg_ms = (per_call[1] + per_call[2]) / 2
-    # algorithmic VALU work of one cost+aggregation launch: ~14 ops for the
-    # raw cost and ~26 for the four range sums and two divisions per (p, d)
+    # dominant kernel: cost + two-stage aggregation of both views (one launch)
+    agg_ms = per_call[1]
+    # algorithmic VALU work of the launch: ~14 ops for the raw cost and ~26
+    # for the four range sums and two divisions per (p, d), for 2 V entries
     ops_per_unit = 40
-    achieved = ops_per_unit * V / (agg_ms / 1e3) / 1e12
+    achieved = ops_per_unit * 2 * V / (agg_ms / 1e3) / 1e12
     roofline = dict(bound="alu", achieved=round(achieved, 2), peak=round(VALU_PEAK_TOPS, 2),
                     unit="TOP/s", frac=round(achieved / VALU_PEAK_TOPS, 4), traffic=measured_traffic(),
-                    kernel="k_agg_stream<2,fused>", kernel_ms=round(agg_ms, 4),
-                    ops_per_pd=ops_per_unit)
+                    kernel="k_agg_pair<2>", kernel_ms=round(agg_ms, 4),
+                    ops_per_pd=ops_per_unit, units_per_launch=2 * V)
 
     extras = {"stage_ms": {n: round(t, 4) for n, t in zip(STAGES, per_call)}}
     if not args.no_extras:

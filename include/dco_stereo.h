@@ -154,9 +154,9 @@ dco_status dco_stereo_last_disparities(dco_stereo* h, int16_t* dL, int16_t* dR);
  * dco_stereo_stage_times waits for the recorded events and writes, for each
  * stage s < n, ms[s] = total milliseconds over the recorded calls, and
  * *calls = the number of recorded calls.  Stages: 0 census + arms + region
- * counts of both views, 1 cost + aggregation of the left view, 2 the same for
- * the right view, 3 WTA of both views, 4 LR check.  ms: host array of n floats. */
-#define DCO_NUM_STAGES 5
+ * counts of both views, 1 cost + aggregation of both views (one launch),
+ * 2 WTA of both views, 3 LR check.  ms: host array of n floats. */
+#define DCO_NUM_STAGES 4
 dco_status dco_stereo_profile(dco_stereo* h, int enable);
 dco_status dco_stereo_stage_times(dco_stereo* h, float* ms, int n, int* calls);
 

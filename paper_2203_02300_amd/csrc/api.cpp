@@ -391,13 +391,11 @@ extern "C" dco_status dco_stereo_match(dco_stereo* h, const uint8_t* rgbL, const
         DCO_HIP_CHECK(launch_geometry(s.arms[v], h->W, h->H, p.agg_iters, s.rec[v], h->stream));
     }
     DCO_TRY(prof_mark(h));
-    for (int v = 0; v < 2; ++v) {
-        DCO_TRY(prof_mark(h));
-        DCO_HIP_CHECK(launch_cost_aggregate(v, s.pix[0], s.pix[1], s.rec[v],
-                                            h->W, h->H, h->D, p.agg_iters, h->tabA, h->tabC,
-                                            h->alpha, h->beta, p.arm_L1, s.agg[v], h->stream));
-        DCO_TRY(prof_mark(h));
-    }
+    DCO_TRY(prof_mark(h));
+    DCO_HIP_CHECK(launch_cost_aggregate2(s.pix[0], s.pix[1], s.rec[0], s.rec[1], h->W, h->H, h->D,
+                                         p.agg_iters, h->tabA, h->tabC, h->alpha, h->beta,
+                                         p.arm_L1, s.agg[0], s.agg[1], h->stream));
+    DCO_TRY(prof_mark(h));
     DCO_TRY(prof_mark(h));
     DCO_HIP_CHECK(launch_wta2(s.agg[0], s.agg[1], h->W, h->H, h->D, p.subpixel, s.dint[0],
                               s.delta, s.dint[1], h->stream));

@@ -163,6 +163,12 @@ hipError_t launch_cost(int ref, const uint8_t* rgbL, const uint8_t* rgbR, const 
                        const float* beta, int L1, float* cost, hipStream_t st);
 hipError_t launch_aggregate(const float* cost, const AggRecords& rec, int W, int H, int D,
                             int iters, float* out, hipStream_t st);
+// Both views in one launch (the one-call path).
+hipError_t launch_cost_aggregate2(const uint4* pixL, const uint4* pixR, const AggRecords& recL,
+                                  const AggRecords& recR, int W, int H, int D, int iters,
+                                  const float* tabA, const float* tabC, const float* alpha,
+                                  const float* beta, int L1, float* outL, float* outR,
+                                  hipStream_t st);
 hipError_t launch_cost_aggregate(int ref, const uint4* pixL, const uint4* pixR,
                                  const AggRecords& rec, int W, int H, int D, int iters,
                                  const float* tabA, const float* tabC, const float* alpha,

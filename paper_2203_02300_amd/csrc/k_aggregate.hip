@@ -20,6 +20,87 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_agg_stream(dco::AggArgs A)
     dco::agg_stream<ITERS, kFused>(A, d, strip, 0, A.H, S);
 }
 
+// Blocks of XCD x in the two-view launch: its nx items (a contiguous,
+// strip-major run), the last m of them split into a top and a bottom half so
+// that the final round of workgroups is not left part-empty.  s8 = resident
+// workgroups per XCD.
+__host__ __device__ inline void pair_part(int N, int x, int s8, int H, int& start, int& nx,
+                                          int& m) {
+    const int per = N / 8, rem = N % 8;
+    nx = per + (x < rem ? 1 : 0);
+    start = x * per + (x < rem ? x : rem);
+    m = 0;
+    if (H < 8 || s8 < 1) return;
+    if (nx <= s8) {
+        m = 2 * nx <= s8 ? nx : 0;
+    } else {
+        const int r = nx % s8;
+        m = r ? (r + s8 < nx ? r + s8 : nx) : 0;
+    }
+}
+
+// Cost + two-stage aggregation of both views in one launch (one-call path).
+// Items: view, then strip, then disparity (strip-major); each XCD runs a
+// contiguous part of them.
+template <int ITERS>
+__global__ __launch_bounds__(kStripThreads, 2) void k_agg_pair(dco::AggArgs A0, AggRecords rec1,
+                                                              float* out1, int s8) {
+    __shared__ dco::AggLds<ITERS, true> S;
+    const int per_view = A0.nstrips * A0.D, N = 2 * per_view;
+    const int x = blockIdx.x % 8, i = blockIdx.x / 8;
+    int start, nx, m;
+    pair_part(N, x, s8, A0.H, start, nx, m);
+    int item, y0 = 0, y1 = A0.H;
+    if (i < nx - m) {
+        item = start + i;
+    } else {
+        const int j = i - (nx - m);
+        if (j >= 2 * m) return;  // uniform: the whole workgroup leaves
+        item = start + nx - m + j / 2;
+        if (j & 1)
+            y0 = A0.H / 2;
+        else
+            y1 = A0.H / 2;
+    }
+    const int view = item / per_view, rest = item - view * per_view;
+    const int strip = rest / A0.D, d = rest - strip * A0.D;
+    dco::AggArgs A = A0;  // left view; the right view differs in three fields
+    if (view) {
+        A.ref = 1;
+        A.rec = rec1;
+        A.out = out1;
+    }
+    dco::agg_stream<ITERS, true>(A, d, strip, y0, y1, S);
+}
+
+template <int ITERS>
+hipError_t launch_pair(const dco::AggArgs& a0, const AggRecords& rec1, float* out1,
+                       hipStream_t st) {
+    static int slots_per_cu = 0, cus = 0;
+    if (!slots_per_cu) {
+        int dev = 0, nb = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_agg_pair<ITERS>,
+                                                             kStripThreads, 0);
+        if (e != hipSuccess) return e;
+        slots_per_cu = nb > 0 ? nb : 1;
+    }
+    const int s8 = slots_per_cu * cus / 8;
+    const int N = 2 * a0.nstrips * a0.D;
+    int most = 1;
+    for (int x = 0; x < 8; ++x) {
+        int start, nx, m;
+        pair_part(N, x, s8, a0.H, start, nx, m);
+        most = nx + m > most ? nx + m : most;
+    }
+    hipLaunchKernelGGL((k_agg_pair<ITERS>), dim3(8 * most), dim3(kStripThreads), 0, st, a0, rec1,
+                       out1, s8);
+    return hipGetLastError();
+}
+
 template <int ITERS, bool kFused>
 hipError_t launch_stream(const dco::AggArgs& a, hipStream_t st) {
     const int nblk = a.nstrips * a.D;
@@ -40,6 +121,29 @@ hipError_t launch_aggregate(const float* cost, const AggRecords& rec, int W, int
     a.D = D;
     a.nstrips = (W + kStripOut - 1) / kStripOut;
     return iters == 1 ? launch_stream<1, false>(a, st) : launch_stream<2, false>(a, st);
+}
+
+hipError_t launch_cost_aggregate2(const uint4* pixL, const uint4* pixR, const AggRecords& recL,
+                                  const AggRecords& recR, int W, int H, int D, int iters,
+                                  const float* tabA, const float* tabC, const float* alpha,
+                                  const float* beta, int L1, float* outL, float* outR,
+                                  hipStream_t st) {
+    dco::AggArgs a{};
+    a.pixL = pixL;
+    a.pixR = pixR;
+    a.tabA = tabA;
+    a.tabC = tabC;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.W = W;
+    a.H = H;
+    a.D = D;
+    a.L1 = L1;
+    a.nstrips = (W + kStripOut - 1) / kStripOut;
+    a.ref = 0;
+    a.rec = recL;
+    a.out = outL;
+    return iters == 1 ? launch_pair<1>(a, recR, outR, st) : launch_pair<2>(a, recR, outR, st);
 }
 
 hipError_t launch_cost_aggregate(int ref, const uint4* pixL, const uint4* pixR,
