@@ -155,6 +155,12 @@ dco_status alloc_records(AggRecords* r, int W, int H);
 hipError_t launch_census_arms(const uint8_t* rgb, int W, int H, int cw, int ch, int L1, int tau1,
                               uint64_t* census, uint32_t* arms, uint32_t* rgb_packed, uint4* pix,
                               hipStream_t st);
+// Census + arms + packed pixels, then region counts + records, of both views
+// (the one-call path): two launches.
+hipError_t launch_front2(const uint8_t* rgbL, const uint8_t* rgbR, int W, int H, int cw, int ch,
+                         int L1, int tau1, int iters, uint32_t* armsL, uint32_t* armsR,
+                         uint4* pixL, uint4* pixR, const AggRecords& recL, const AggRecords& recR,
+                         hipStream_t st);
 hipError_t launch_geometry(const uint32_t* arms, int W, int H, int iters, const AggRecords& rec,
                            hipStream_t st);
 hipError_t launch_cost(int ref, const uint8_t* rgbL, const uint8_t* rgbR, const uint64_t* cenL,
