@@ -6,30 +6,30 @@
 //   E1 = row range sum of c       a1 = (column range sum of E1) / N1     (Eq. 2, stage 1)
 //   E2 = column range sum of a1   A2 = (row range sum of E2) / N2         (Eq. 2, stage 2)
 //   dhat = sum_d d softmax_d(-A2 / T),  lse = log sum_d exp(-A2 / T)
-// Every range sum adds at most 2 kLMax + 1 terms directly, in a fixed order,
-// so there is no cancellation between long prefix sums and the result is
-// bit-reproducible.
+// Row range sums add at most 2 kLMax + 1 terms directly; column range sums
+// are differences of FP64 running column sums (exact to the final FP32
+// rounding).  Every sum runs in a fixed order, so results are bit-reproducible.
 //
 // Backward, given g = dLoss/d dhat:
 //   G_A2  = g w (dhat - d) / T,   dLoss/dT = sum g w (d - dhat) A2 / T^2
 // then the adjoint of each range sum: an output that summed a range hands its
-// adjoint back to every pixel of that range.  Each adjoint is written as a
-// gather over the (at most 2 kLMax + 1) candidate pixels whose range can
-// cover a pixel, so there are no atomics and no float reductions of
-// unspecified order.  Finally
+// adjoint back to every pixel of that range.  Row adjoints are gathers over
+// the (at most 2 kLMax + 1) candidate pixels whose range can cover a pixel;
+// column adjoints are FP64 difference arrays streamed down each column by
+// one thread.  There are no atomics and no float reductions of unspecified
+// order.  Finally
 //   dLoss/dlambda_AD     = sum G_c alpha   d(1 - exp(-(s/3)/lambda_AD))/dlambda_AD
 //   dLoss/dlambda_census = sum G_c (1 - alpha) d(1 - exp(-h/lambda_census))/dlambda_census
 // with fixed-order two-level reductions.
 //
 // Layout: volumes are B x D x H x W float in handle scratch; arms, census
 // and packed RGB are per pair B x H x W.  Row passes run one workgroup per
-// image row with the row in LDS; column passes one workgroup per 64-column x
-// 64-row tile with a kLMax-row apron in LDS.
+// image row with the row in LDS; column passes one thread per column,
+// streaming down the rows with a ring of FP64 sums in LDS.
 #include "dco_internal.h"
 
 namespace {
 
-constexpr int kTileX = 64, kTileY = 64;
 
 struct SoftGeom {
     const uint32_t* arms;  // B x H x W packed arms of the left view
@@ -139,36 +139,124 @@ __global__ __launch_bounds__(256) void k_soft_h1(SoftGeom g, SoftImg im, float* 
 
 // Column pass: out(x, y) = scale(x, y) * sum of in(x, y') over y' in [y - u, y + dn]
 // of pixel (x, y).  One 64 x 64 tile per block with the kLMax-row aprons in LDS.
-__global__ __launch_bounds__(256) void k_soft_v(SoftGeom g, const float* __restrict__ in,
-                                                const float* __restrict__ scale,
-                                                float* __restrict__ out) {
-    __shared__ float tile[kTileY + 2 * kLMax][kTileX];
-    const int x0 = blockIdx.x * kTileX, y0 = (blockIdx.y % ((g.H + kTileY - 1) / kTileY)) * kTileY;
-    const int bd = blockIdx.y / ((g.H + kTileY - 1) / kTileY);  // b * D + d
-    const int b = bd / g.D;
+
+// Forward row pass 2: A2(x) = sum of E2 over [x - l, x + r] / N2.
+// Column passes, streamed down each column: one thread per column, kSoftCols
+// columns per workgroup, rows in order.  FP64 running sums in an LDS ring of
+// kSoftRing rows per column keep every range sum exact to FP32 rounding of
+// the final value, and each thread touches only its own column, so the result
+// does not depend on scheduling.
+constexpr int kSoftCols = 128;
+constexpr int kSoftRing = 2 * kLMax + 2;
+constexpr int kSoftPre = 8;  // rows loaded ahead
+
+// out(y) = (sum of in over the vertical range of pixel y) [/ scale(y)], with
+// the running column prefix P: out(y) = P(y + dn) - P(y - u - 1).
+template <bool kScale>
+__global__ __launch_bounds__(kSoftCols) void k_soft_vs(SoftGeom g, const float* __restrict__ in,
+                                                       const float* __restrict__ scale,
+                                                       float* __restrict__ out) {
+    __shared__ double ring[kSoftRing][kSoftCols];
+    const int t = threadIdx.x, x = blockIdx.x * kSoftCols + t;
+    const int bd = blockIdx.y, b = bd / g.D;
+    const bool ok = x < g.W;
+    const int xc = ok ? x : 0;
     const size_t P = (size_t)g.W * g.H;
-    const float* src = in + (size_t)bd * P;
-    for (int i = threadIdx.x; i < (kTileY + 2 * kLMax) * kTileX; i += 256) {
-        const int ty = i / kTileX, tx = i - ty * kTileX;
-        const int y = y0 - kLMax + ty, x = x0 + tx;
-        tile[ty][tx] = (y >= 0 && y < g.H && x < g.W) ? src[(size_t)y * g.W + x] : 0.0f;
-    }
-    __syncthreads();
-    const int tx = threadIdx.x & 63;
-    const int x = x0 + tx;
-    if (x >= g.W) return;
-    for (int ty = threadIdx.x >> 6; ty < kTileY; ty += 4) {
-        const int y = y0 + ty;
-        if (y >= g.H) break;
-        const size_t i = (size_t)y * g.W + x;
-        const uint32_t a = g.arms[b * P + i];
-        float s = 0.0f;
-        for (int k = ty + kLMax - arm(a, 2); k <= ty + kLMax + arm(a, 3); ++k) s += tile[k][tx];
-        out[(size_t)bd * P + i] = scale ? s / scale[b * P + i] : s;
+    const float* src = in + (size_t)bd * P + xc;
+    const uint32_t* arms = g.arms + (size_t)b * P + xc;
+    const float* sc = (kScale ? scale : in) + (size_t)b * P + xc;
+    float* dst = out + (size_t)bd * P + xc;
+    double acc = 0.0;
+    int slot = 0;  // ring slot of row y (y mod kSoftRing)
+    for (int y0 = 0; y0 < g.H + kLMax; y0 += kSoftPre) {
+        float v[kSoftPre];
+        uint32_t a[kSoftPre];
+        float s[kSoftPre];
+#pragma unroll
+        for (int k = 0; k < kSoftPre; ++k) {  // clamped rows: every load is unconditional
+            const int y = y0 + k, yo = y - kLMax;
+            const size_t yq = (size_t)min(y, g.H - 1), oq = (size_t)min(max(yo, 0), g.H - 1);
+            v[k] = src[yq * g.W];
+            a[k] = arms[oq * g.W];
+            s[k] = kScale ? sc[oq * g.W] : 1.0f;
+            v[k] = y < g.H ? v[k] : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < kSoftPre; ++k) {
+            const int y = y0 + k, yo = y - kLMax;
+            acc += (double)v[k];
+            ring[slot][t] = acc;
+            if (yo >= 0 && yo < g.H) {
+                const int u = arm(a[k], 2), dn = arm(a[k], 3);
+                // P(yo + dn) is kLMax - dn rows back, P(yo - u - 1) kLMax + u + 1
+                int sh = slot - (kLMax - dn), sl = slot - (kLMax + u + 1);
+                sh += sh < 0 ? kSoftRing : 0;
+                sl += sl < 0 ? kSoftRing : 0;
+                const double lo = yo - u - 1 >= 0 ? ring[sl][t] : 0.0;
+                const float r = (float)(ring[sh][t] - lo);
+                if (ok) dst[(size_t)yo * g.W] = kScale ? r / s[k] : r;
+            }
+            slot = slot + 1 == kSoftRing ? 0 : slot + 1;
+        }
     }
 }
 
-// Forward row pass 2: A2(x) = sum of E2 over [x - l, x + r] / N2.
+// Adjoint of k_soft_vs: out(y') = sum over pixels y whose vertical range
+// covers y' of in(y), [/ scale(y')].  Each y adds in(y) at row y - u and
+// subtracts it after row y + dn in a ring of differences; row y' is final
+// kLMax rows later and its running sum is the output.
+template <bool kScale>
+__global__ __launch_bounds__(kSoftCols) void k_soft_vsa(SoftGeom g, const float* __restrict__ in,
+                                                        const float* __restrict__ scale,
+                                                        float* __restrict__ out) {
+    __shared__ double ring[kSoftRing][kSoftCols];
+    const int t = threadIdx.x, x = blockIdx.x * kSoftCols + t;
+    const int bd = blockIdx.y, b = bd / g.D;
+    const bool ok = x < g.W;
+    const int xc = ok ? x : 0;
+    const size_t P = (size_t)g.W * g.H;
+    const float* src = in + (size_t)bd * P + xc;
+    const uint32_t* arms = g.arms + (size_t)b * P + xc;
+    const float* sc = (kScale ? scale : in) + (size_t)b * P + xc;
+    float* dst = out + (size_t)bd * P + xc;
+    for (int i = 0; i < kSoftRing; ++i) ring[i][t] = 0.0;
+    double run = 0.0;
+    int slot = 0;  // ring slot of row y
+    for (int y0 = 0; y0 < g.H + kLMax; y0 += kSoftPre) {
+        float v[kSoftPre];
+        uint32_t a[kSoftPre];
+        float s[kSoftPre];
+#pragma unroll
+        for (int k = 0; k < kSoftPre; ++k) {  // clamped rows: every load is unconditional
+            const int y = y0 + k, yo = y - kLMax;
+            const size_t yq = (size_t)min(y, g.H - 1), oq = (size_t)min(max(yo, 0), g.H - 1);
+            v[k] = src[yq * g.W];
+            a[k] = arms[yq * g.W];
+            s[k] = kScale ? sc[oq * g.W] : 1.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < kSoftPre; ++k) {
+            const int y = y0 + k, yo = y - kLMax;
+            if (y < g.H) {  // uniform
+                const int u = arm(a[k], 2), dn = arm(a[k], 3);
+                int sa = slot - u, se = slot + dn + 1;
+                sa += sa < 0 ? kSoftRing : 0;
+                se -= se >= kSoftRing ? kSoftRing : 0;
+                ring[sa][t] += (double)v[k];
+                ring[se][t] -= (double)v[k];
+            }
+            if (yo >= 0) {  // row yo is final: its slot is kLMax rows back
+                int so = slot - kLMax;
+                so += so < 0 ? kSoftRing : 0;
+                run += ring[so][t];
+                ring[so][t] = 0.0;  // reused for row yo + kSoftRing
+                if (ok && yo < g.H) dst[(size_t)yo * g.W] = kScale ? (float)run / s[k] : (float)run;
+            }
+            slot = slot + 1 == kSoftRing ? 0 : slot + 1;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_soft_h2(SoftGeom g, const float* __restrict__ E2,
                                                  float* __restrict__ A2) {
     __shared__ float row[2048];
@@ -270,40 +358,6 @@ __global__ __launch_bounds__(256) void k_soft_h_adj(SoftGeom g, const float* __r
 
 // Adjoint of a column range sum, then an optional per-pixel scale:
 // out(x, y') = scale(x, y') * sum over y with y' in [y - u(y), y + dn(y)] of in(x, y).
-__global__ __launch_bounds__(256) void k_soft_v_adj(SoftGeom g, const float* __restrict__ in,
-                                                    const float* __restrict__ scale,
-                                                    float* __restrict__ out) {
-    __shared__ float tile[kTileY + 2 * kLMax][kTileX];
-    __shared__ uint32_t atile[kTileY + 2 * kLMax][kTileX];
-    const int nty = (g.H + kTileY - 1) / kTileY;
-    const int x0 = blockIdx.x * kTileX, y0 = (blockIdx.y % nty) * kTileY;
-    const int bd = blockIdx.y / nty;
-    const int b = bd / g.D;
-    const size_t P = (size_t)g.W * g.H;
-    for (int i = threadIdx.x; i < (kTileY + 2 * kLMax) * kTileX; i += 256) {
-        const int ty = i / kTileX, tx = i - ty * kTileX;
-        const int y = y0 - kLMax + ty, x = x0 + tx;
-        const bool ok = y >= 0 && y < g.H && x < g.W;
-        tile[ty][tx] = ok ? in[(size_t)bd * P + (size_t)y * g.W + x] : 0.0f;
-        atile[ty][tx] = ok ? g.arms[b * P + (size_t)y * g.W + x] : 0u;
-    }
-    __syncthreads();
-    const int tx = threadIdx.x & 63;
-    const int x = x0 + tx;
-    if (x >= g.W) return;
-    for (int ty = threadIdx.x >> 6; ty < kTileY; ty += 4) {
-        const int yp = y0 + ty;
-        if (yp >= g.H) break;
-        float s = 0.0f;
-        for (int k = ty; k <= ty + 2 * kLMax; ++k) {  // candidate rows yp - kLMax .. yp + kLMax
-            const int y = y0 - kLMax + k;
-            const uint32_t a = atile[k][tx];
-            if (yp >= y - arm(a, 2) && yp <= y + arm(a, 3)) s += tile[k][tx];
-        }
-        const size_t i = (size_t)yp * g.W + x;
-        out[(size_t)bd * P + i] = scale ? s / scale[b * P + i] : s;
-    }
-}
 
 // Last adjoint (row direction, onto the raw costs) fused with the lambda
 // derivatives: per-block partial sums of G_c dc/dlambda_AD and G_c dc/dlambda_c.
@@ -397,12 +451,11 @@ hipError_t soft_aggregate(const SoftBuffers& s, int B, int W, int H, int D, floa
                           float* t2, hipStream_t st) {
     SoftGeom g{s.arms, s.n1, s.n2, B, W, H, D};
     SoftImg im{s.rgbL, s.rgbR, s.cenL, s.cenR, s.alpha, s.tab};
-    const int nty = (H + kTileY - 1) / kTileY;
     hipLaunchKernelGGL(k_soft_h1, dim3(H, D, B), dim3(256), 0, st, g, im, t1);             // E1
-    hipLaunchKernelGGL(k_soft_v, dim3((W + kTileX - 1) / kTileX, nty * B * D), dim3(256), 0, st,
-                       g, t1, s.n1, t2);                                                     // a1
-    hipLaunchKernelGGL(k_soft_v, dim3((W + kTileX - 1) / kTileX, nty * B * D), dim3(256), 0, st,
-                       g, t2, (const float*)nullptr, t1);                                    // E2
+    const dim3 gv((W + kSoftCols - 1) / kSoftCols, B * D);
+    hipLaunchKernelGGL(k_soft_vs<true>, gv, dim3(kSoftCols), 0, st, g, t1, s.n1, t2);      // a1
+    hipLaunchKernelGGL(k_soft_vs<false>, gv, dim3(kSoftCols), 0, st, g, t2,
+                       (const float*)nullptr, t1);                                           // E2
     hipLaunchKernelGGL(k_soft_h2, dim3(H, D, B), dim3(256), 0, st, g, t1, A2);             // A2
     return hipGetLastError();
 }
@@ -425,14 +478,13 @@ hipError_t soft_backward(const SoftBuffers& s, int B, int W, int H, int D, const
     SoftImg im{s.rgbL, s.rgbR, s.cenL, s.cenR, s.alpha, s.tab};
     const size_t P = (size_t)W * H;
     const unsigned nb = (unsigned)((P + 255) / 256);
-    const int nty = (H + kTileY - 1) / kTileY;
     hipLaunchKernelGGL(k_soft_seed, dim3(nb, B), dim3(256), 0, st, g, A2, theta, dhat, lse, gdhat,
                        t1, partT);                                              // G_A2 / N2
     hipLaunchKernelGGL(k_soft_h_adj, dim3(H, D, B), dim3(256), 0, st, g, t1, t2);   // G_E2
-    hipLaunchKernelGGL(k_soft_v_adj, dim3((W + kTileX - 1) / kTileX, nty * B * D), dim3(256), 0,
-                       st, g, t2, s.n1, t1);                                    // G_a1 / N1
-    hipLaunchKernelGGL(k_soft_v_adj, dim3((W + kTileX - 1) / kTileX, nty * B * D), dim3(256), 0,
-                       st, g, t1, (const float*)nullptr, t2);                   // G_E1
+    const dim3 gv((W + kSoftCols - 1) / kSoftCols, B * D);
+    hipLaunchKernelGGL(k_soft_vsa<true>, gv, dim3(kSoftCols), 0, st, g, t2, s.n1, t1);  // G_a1/N1
+    hipLaunchKernelGGL(k_soft_vsa<false>, gv, dim3(kSoftCols), 0, st, g, t1,
+                       (const float*)nullptr, t2);                                    // G_E1
     hipLaunchKernelGGL(k_soft_h1_adj_grad, dim3(H, D, B), dim3(256), 0, st, g, im, t2, partAC);
     hipLaunchKernelGGL(k_soft_reduce, dim3(1), dim3(256), 0, st, partAC, (size_t)B * D * H,
                        partT, (size_t)B * nb, grad);
