@@ -115,32 +115,172 @@ struct SoftImg {
     const float* tab;      // k_soft_tables output
 };
 
-// Forward row pass 1: E1(x) = sum of c over [x - l, x + r], one row per block.
-__global__ __launch_bounds__(256) void k_soft_h1(SoftGeom g, SoftImg im, float* __restrict__ E1) {
-    __shared__ float row[2048];
-    const int y = blockIdx.x, d = blockIdx.y, b = blockIdx.z, W = g.W;
-    const size_t P = (size_t)W * g.H;
-    const uint32_t* arms = g.arms + b * P;
-    for (int x = threadIdx.x; x < W; x += blockDim.x) {
-        float c;
-        cost_row<false>(im.rgbL + b * P, im.rgbR + b * P, im.cenL + b * P, im.cenR + b * P, arms,
-                        im.alpha, im.tab, W, y, d, x, &c, nullptr, nullptr);
-        row[x] = c;
+// Row passes: one wavefront per image row, kRowWaves wavefronts per
+// workgroup, each with its own LDS slice (no workgroup barriers) and
+// kRowsPerWave rows in turn.  Row ids run over (b, d, y) with y fastest.
+constexpr int kRowWaves = 4;
+constexpr int kRowsPerWave = 4;
+
+__device__ inline void row_of(int rid, int D, int H, int& b, int& d, int& y) {
+    y = rid % H;
+    const int bd = rid / H;
+    d = bd % D;
+    b = bd / D;
+}
+
+// FP64 inclusive prefix of the wavefront's row (W <= 2048): P[0] = 0,
+// P[x + 1] = row[0] + ... + row[x].  Lane L sums its contiguous run of
+// ceil(W / 64) values, the run totals are scanned across the wavefront, and
+// the runs are written with their offsets; fixed order, bit-reproducible.
+__device__ inline void wave_row_prefix(const float* row, double* P, int W) {
+    const int lane = threadIdx.x & 63, c = (W + 63) / 64, x0 = lane * c;
+    double acc = 0.0;
+    for (int k = 0; k < c; ++k)
+        if (x0 + k < W) acc += (double)row[x0 + k];
+    double inc = acc;
+    for (int off = 1; off < 64; off <<= 1) {
+        const double n = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += n;
     }
-    __syncthreads();
-    float* out = E1 + ((size_t)b * g.D + d) * P + (size_t)y * W;
-    for (int x = threadIdx.x; x < W; x += blockDim.x) {
-        const uint32_t a = arms[(size_t)y * W + x];
-        float s = 0.0f;
-        for (int xx = x - arm(a, 0); xx <= x + arm(a, 1); ++xx) s += row[xx];
-        out[x] = s;
+    double run = inc - acc;
+    if (lane == 0) P[0] = 0.0;
+    for (int k = 0; k < c; ++k)
+        if (x0 + k < W) {
+            run += (double)row[x0 + k];
+            P[x0 + k + 1] = run;
+        }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Adjoint of a row range sum at x': the pixels x whose horizontal range
+// covers x' are x' itself, x' + k with l(x' + k) >= k and x' - k with
+// r(x' - k) >= k (k = 1 .. kLMax); added in a fixed order.  lr holds the
+// arms of the row as bytes (l, r); row and lr are zero-padded by kLMax.
+__device__ inline float row_adjoint(const float* rowp, const uchar2* lrp, int xp) {
+    float s = rowp[xp];
+#pragma unroll
+    for (int k = 1; k <= kLMax; ++k) {
+        s += lrp[xp + k].x >= k ? rowp[xp + k] : 0.0f;
+        s += lrp[xp - k].y >= k ? rowp[xp - k] : 0.0f;
+    }
+    return s;
+}
+
+// Bytes of dynamic LDS per wavefront: forward (row + FP64 prefix) and
+// adjoint (padded row + padded arms).
+inline size_t row_lds_fwd(int W) { return ((size_t)W * 4 + 15) / 16 * 16 + (size_t)(W + 1) * 8; }
+inline size_t row_lds_adj(int W) {
+    return ((size_t)(W + 2 * kLMax) * 4 + 15) / 16 * 16 + (size_t)(W + 2 * kLMax) * 2;
+}
+
+// Lets a kernel take `bytes` of dynamic LDS (above the default limit for
+// wide rows).
+inline hipError_t allow_lds(const void* kernel, size_t bytes) {
+    return bytes > 48 * 1024 ? hipFuncSetAttribute(kernel,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   (int)bytes)
+                             : hipSuccess;
+}
+
+// Forward row passes.  kCost: E1(x) = sum of the raw cost c over
+// [x - l, x + r] (Eq. 1 computed here); else A2(x) = (sum of E2 over the
+// range) / N2(x).
+template <bool kCost>
+__global__ __launch_bounds__(64 * kRowWaves) void k_soft_hrow(SoftGeom g, SoftImg im,
+                                                              const float* __restrict__ in,
+                                                              float* __restrict__ out,
+                                                              size_t lds_wave) {
+    extern __shared__ __align__(16) unsigned char dyn[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, W = g.W;
+    unsigned char* mine = dyn + w * lds_wave;
+    float* row = reinterpret_cast<float*>(mine);
+    double* Pf = reinterpret_cast<double*>(mine + ((size_t)W * 4 + 15) / 16 * 16);
+    const size_t P = (size_t)W * g.H;
+    const int nrows = g.B * g.D * g.H;
+    const int r0 = (blockIdx.x * kRowWaves + w) * kRowsPerWave;
+    for (int rid = r0; rid < min(nrows, r0 + kRowsPerWave); ++rid) {
+        int b, d, y;
+        row_of(rid, g.D, g.H, b, d, y);
+        const size_t base = ((size_t)b * g.D + d) * P + (size_t)y * W;
+        const uint32_t* arms = g.arms + b * P + (size_t)y * W;
+        for (int x = lane; x < W; x += 64) {
+            float c;
+            if (kCost)
+                cost_row<false>(im.rgbL + b * P, im.rgbR + b * P, im.cenL + b * P,
+                                im.cenR + b * P, g.arms + b * P, im.alpha, im.tab, W, y, d, x, &c,
+                                nullptr, nullptr);
+            else
+                c = in[base + x];
+            row[x] = c;
+        }
+        __builtin_amdgcn_wave_barrier();
+        wave_row_prefix(row, Pf, W);
+        for (int x = lane; x < W; x += 64) {
+            const uint32_t a = arms[x];
+            const float v = (float)(Pf[x + arm(a, 1) + 1] - Pf[x - arm(a, 0)]);
+            out[base + x] = kCost ? v : v / g.n2[b * P + (size_t)y * W + x];
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
-// Column pass: out(x, y) = scale(x, y) * sum of in(x, y') over y' in [y - u, y + dn]
-// of pixel (x, y).  One 64 x 64 tile per block with the kLMax-row aprons in LDS.
+// Adjoint row passes.  kGrad: the adjoint of E1's row sums (G_c), dotted
+// with dc/dlambda_AD and dc/dlambda_census into one FP64 pair per row;
+// else out = the adjoint of A2's row sums (G_E2).
+template <bool kGrad>
+__global__ __launch_bounds__(64 * kRowWaves) void k_soft_hrow_adj(SoftGeom g, SoftImg im,
+                                                                  const float* __restrict__ in,
+                                                                  float* __restrict__ out,
+                                                                  double* __restrict__ part,
+                                                                  size_t lds_wave) {
+    extern __shared__ __align__(16) unsigned char dyn[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, W = g.W;
+    unsigned char* mine = dyn + w * lds_wave;
+    float* row = reinterpret_cast<float*>(mine);
+    uchar2* lr = reinterpret_cast<uchar2*>(mine + ((size_t)(W + 2 * kLMax) * 4 + 15) / 16 * 16);
+    const size_t P = (size_t)W * g.H;
+    const int nrows = g.B * g.D * g.H;
+    const int r0 = (blockIdx.x * kRowWaves + w) * kRowsPerWave;
+    for (int rid = r0; rid < min(nrows, r0 + kRowsPerWave); ++rid) {
+        int b, d, y;
+        row_of(rid, g.D, g.H, b, d, y);
+        const size_t base = ((size_t)b * g.D + d) * P + (size_t)y * W;
+        const uint32_t* arms = g.arms + b * P + (size_t)y * W;
+        for (int x = lane - kLMax; x < W + kLMax; x += 64) {
+            const bool in_row = x >= 0 && x < W;
+            const uint32_t a = in_row ? arms[x] : 0u;
+            row[x + kLMax] = in_row ? in[base + x] : 0.0f;
+            lr[x + kLMax] = make_uchar2((unsigned char)arm(a, 0), (unsigned char)arm(a, 1));
+        }
+        __builtin_amdgcn_wave_barrier();
+        double sa = 0.0, sc = 0.0;
+        for (int xp = lane; xp < W; xp += 64) {
+            const float s = row_adjoint(row + kLMax, lr + kLMax, xp);
+            if (kGrad) {
+                float c, dca, dcc;
+                cost_row<true>(im.rgbL + b * P, im.rgbR + b * P, im.cenL + b * P,
+                               im.cenR + b * P, g.arms + b * P, im.alpha, im.tab, W, y, d, xp, &c,
+                               &dca, &dcc);
+                sa += (double)(s * dca);
+                sc += (double)(s * dcc);
+            } else {
+                out[base + xp] = s;
+            }
+        }
+        if (kGrad) {  // fixed-order wavefront reduction
+            for (int off = 32; off > 0; off >>= 1) {
+                sa += __shfl_down(sa, off, 64);
+                sc += __shfl_down(sc, off, 64);
+            }
+            if (lane == 0) {
+                part[2 * (size_t)rid] = sa;
+                part[2 * (size_t)rid + 1] = sc;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
 
-// Forward row pass 2: A2(x) = sum of E2 over [x - l, x + r] / N2.
 // Column passes, streamed down each column: one thread per column, kSoftCols
 // columns per workgroup, rows in order.  FP64 running sums in an LDS ring of
 // kSoftRing rows per column keep every range sum exact to FP32 rounding of
@@ -257,22 +397,6 @@ __global__ __launch_bounds__(kSoftCols) void k_soft_vsa(SoftGeom g, const float*
     }
 }
 
-__global__ __launch_bounds__(256) void k_soft_h2(SoftGeom g, const float* __restrict__ E2,
-                                                 float* __restrict__ A2) {
-    __shared__ float row[2048];
-    const int y = blockIdx.x, d = blockIdx.y, b = blockIdx.z, W = g.W;
-    const size_t P = (size_t)W * g.H;
-    const size_t base = ((size_t)b * g.D + d) * P + (size_t)y * W;
-    for (int x = threadIdx.x; x < W; x += blockDim.x) row[x] = E2[base + x];
-    __syncthreads();
-    for (int x = threadIdx.x; x < W; x += blockDim.x) {
-        const size_t i = (size_t)y * W + x;
-        const uint32_t a = g.arms[b * P + i];
-        float s = 0.0f;
-        for (int xx = x - arm(a, 0); xx <= x + arm(a, 1); ++xx) s += row[xx];
-        A2[base + x] = s / g.n2[b * P + i];
-    }
-}
 
 // Soft-argmin over d per pixel: dhat and lse (log-sum-exp of -A2/T).
 __global__ __launch_bounds__(256) void k_soft_argmin(SoftGeom g, const float* __restrict__ A2,
@@ -334,77 +458,12 @@ __global__ __launch_bounds__(256) void k_soft_seed(SoftGeom g, const float* __re
 
 // Adjoint of a row range sum: out(x') = sum over x with x' in [x - l(x), x + r(x)]
 // of in(x).  The candidates are x in [x' - kLMax, x' + kLMax].
-__global__ __launch_bounds__(256) void k_soft_h_adj(SoftGeom g, const float* __restrict__ in,
-                                                    float* __restrict__ out) {
-    __shared__ float row[2048];
-    __shared__ uint32_t arow[2048];
-    const int y = blockIdx.x, d = blockIdx.y, b = blockIdx.z, W = g.W;
-    const size_t P = (size_t)W * g.H;
-    const size_t base = ((size_t)b * g.D + d) * P + (size_t)y * W;
-    for (int x = threadIdx.x; x < W; x += blockDim.x) {
-        row[x] = in[base + x];
-        arow[x] = g.arms[b * P + (size_t)y * W + x];
-    }
-    __syncthreads();
-    for (int xp = threadIdx.x; xp < W; xp += blockDim.x) {
-        float s = 0.0f;
-        for (int x = max(0, xp - kLMax); x <= min(W - 1, xp + kLMax); ++x) {
-            const uint32_t a = arow[x];
-            if (xp >= x - arm(a, 0) && xp <= x + arm(a, 1)) s += row[x];
-        }
-        out[base + xp] = s;
-    }
-}
 
 // Adjoint of a column range sum, then an optional per-pixel scale:
 // out(x, y') = scale(x, y') * sum over y with y' in [y - u(y), y + dn(y)] of in(x, y).
 
 // Last adjoint (row direction, onto the raw costs) fused with the lambda
 // derivatives: per-block partial sums of G_c dc/dlambda_AD and G_c dc/dlambda_c.
-__global__ __launch_bounds__(256) void k_soft_h1_adj_grad(SoftGeom g, SoftImg im,
-                                                          const float* __restrict__ GE1,
-                                                          double* __restrict__ part) {
-    __shared__ float row[2048];
-    __shared__ uint32_t arow[2048];
-    __shared__ double red[2][256];
-    const int y = blockIdx.x, d = blockIdx.y, b = blockIdx.z, W = g.W;
-    const size_t P = (size_t)W * g.H;
-    const size_t base = ((size_t)b * g.D + d) * P + (size_t)y * W;
-    const uint32_t* arms = g.arms + b * P;
-    for (int x = threadIdx.x; x < W; x += blockDim.x) {
-        row[x] = GE1[base + x];
-        arow[x] = arms[(size_t)y * W + x];
-    }
-    __syncthreads();
-    double sa = 0.0, sc = 0.0;
-    for (int xp = threadIdx.x; xp < W; xp += blockDim.x) {
-        float s = 0.0f;
-        for (int x = max(0, xp - kLMax); x <= min(W - 1, xp + kLMax); ++x) {
-            const uint32_t a = arow[x];
-            if (xp >= x - arm(a, 0) && xp <= x + arm(a, 1)) s += row[x];
-        }
-        float c, dca, dcc;
-        cost_row<true>(im.rgbL + b * P, im.rgbR + b * P, im.cenL + b * P, im.cenR + b * P, arms,
-                       im.alpha, im.tab, W, y, d, xp, &c, &dca, &dcc);
-        sa += (double)(s * dca);
-        sc += (double)(s * dcc);
-    }
-    red[0][threadIdx.x] = sa;
-    red[1][threadIdx.x] = sc;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + s];
-            red[1][threadIdx.x] += red[1][threadIdx.x + s];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const size_t blk = ((size_t)b * g.D + d) * g.H + y;
-        part[2 * blk] = red[0][0];
-        part[2 * blk + 1] = red[1][0];
-    }
-}
 
 // Final fixed-order reduction of the partial sums into grad_theta (float).
 __global__ void k_soft_reduce(const double* __restrict__ partAC, size_t nAC,
@@ -451,12 +510,21 @@ hipError_t soft_aggregate(const SoftBuffers& s, int B, int W, int H, int D, floa
                           float* t2, hipStream_t st) {
     SoftGeom g{s.arms, s.n1, s.n2, B, W, H, D};
     SoftImg im{s.rgbL, s.rgbR, s.cenL, s.cenR, s.alpha, s.tab};
-    hipLaunchKernelGGL(k_soft_h1, dim3(H, D, B), dim3(256), 0, st, g, im, t1);             // E1
+    const int nrows = B * D * H;
+    const dim3 gr((nrows + kRowWaves * kRowsPerWave - 1) / (kRowWaves * kRowsPerWave));
+    const size_t lf = row_lds_fwd(W);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_soft_hrow<true>), kRowWaves * lf);
+    if (e == hipSuccess)
+        e = allow_lds(reinterpret_cast<const void*>(&k_soft_hrow<false>), kRowWaves * lf);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_soft_hrow<true>, gr, dim3(64 * kRowWaves), kRowWaves * lf, st, g, im,
+                       (const float*)nullptr, t1, lf);                                       // E1
     const dim3 gv((W + kSoftCols - 1) / kSoftCols, B * D);
     hipLaunchKernelGGL(k_soft_vs<true>, gv, dim3(kSoftCols), 0, st, g, t1, s.n1, t2);      // a1
     hipLaunchKernelGGL(k_soft_vs<false>, gv, dim3(kSoftCols), 0, st, g, t2,
                        (const float*)nullptr, t1);                                           // E2
-    hipLaunchKernelGGL(k_soft_h2, dim3(H, D, B), dim3(256), 0, st, g, t1, A2);             // A2
+    hipLaunchKernelGGL(k_soft_hrow<false>, gr, dim3(64 * kRowWaves), kRowWaves * lf, st, g, im, t1,
+                       A2, lf);                                                              // A2
     return hipGetLastError();
 }
 
@@ -480,12 +548,21 @@ hipError_t soft_backward(const SoftBuffers& s, int B, int W, int H, int D, const
     const unsigned nb = (unsigned)((P + 255) / 256);
     hipLaunchKernelGGL(k_soft_seed, dim3(nb, B), dim3(256), 0, st, g, A2, theta, dhat, lse, gdhat,
                        t1, partT);                                              // G_A2 / N2
-    hipLaunchKernelGGL(k_soft_h_adj, dim3(H, D, B), dim3(256), 0, st, g, t1, t2);   // G_E2
+    const int nrows = B * D * H;
+    const dim3 gr((nrows + kRowWaves * kRowsPerWave - 1) / (kRowWaves * kRowsPerWave));
+    const size_t la = row_lds_adj(W);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_soft_hrow_adj<false>), kRowWaves * la);
+    if (e == hipSuccess)
+        e = allow_lds(reinterpret_cast<const void*>(&k_soft_hrow_adj<true>), kRowWaves * la);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_soft_hrow_adj<false>, gr, dim3(64 * kRowWaves), kRowWaves * la, st, g, im,
+                       t1, t2, (double*)nullptr, la);                         // G_E2
     const dim3 gv((W + kSoftCols - 1) / kSoftCols, B * D);
     hipLaunchKernelGGL(k_soft_vsa<true>, gv, dim3(kSoftCols), 0, st, g, t2, s.n1, t1);  // G_a1/N1
     hipLaunchKernelGGL(k_soft_vsa<false>, gv, dim3(kSoftCols), 0, st, g, t1,
                        (const float*)nullptr, t2);                                    // G_E1
-    hipLaunchKernelGGL(k_soft_h1_adj_grad, dim3(H, D, B), dim3(256), 0, st, g, im, t2, partAC);
+    hipLaunchKernelGGL(k_soft_hrow_adj<true>, gr, dim3(64 * kRowWaves), kRowWaves * la, st, g, im,
+                       t2, (float*)nullptr, partAC, la);                      // G_c . dc/dlambda
     hipLaunchKernelGGL(k_soft_reduce, dim3(1), dim3(256), 0, st, partAC, (size_t)B * D * H,
                        partT, (size_t)B * nb, grad);
     return hipGetLastError();
