@@ -442,7 +442,7 @@ static dco_status soft_reserve(dco_stereo* h, int B) {
     DCO_TRY(dev_alloc(&f.tab, 1792));
     for (int k = 0; k < 3; ++k) DCO_TRY(dev_alloc(&f.vol[k], V));
     DCO_TRY(dev_alloc(&f.partAC, 2 * (size_t)B * h->D * h->H));
-    DCO_TRY(dev_alloc(&f.partT, (size_t)B * nb));
+    DCO_TRY(dev_alloc(&f.partT, (size_t)B * nb + 3 * 256));  // + the reduction's block totals
     f.cap = B;
     return DCO_OK;
 }

@@ -63,7 +63,8 @@ struct SoftScratch {
     float* tab;            // Eq. 1 tables and derivatives for the current theta
     float* vol[3];
     double* partAC;        // per-row partial sums of the lambda gradients
-    double* partT;         // per-block partial sums of the temperature gradient
+    double* partT;         // per-block partial sums of the temperature gradient, then
+                           // 3 x 256 block totals of the final reduction
 };
 
 // Read-only view of the soft-path inputs handed to the kernels.

@@ -466,16 +466,12 @@ __global__ __launch_bounds__(256) void k_soft_seed(SoftGeom g, const float* __re
 // derivatives: per-block partial sums of G_c dc/dlambda_AD and G_c dc/dlambda_c.
 
 // Final fixed-order reduction of the partial sums into grad_theta (float).
-__global__ void k_soft_reduce(const double* __restrict__ partAC, size_t nAC,
-                              const double* __restrict__ partT, size_t nT,
-                              float* __restrict__ grad) {
-    __shared__ double red[3][256];
-    double a = 0.0, c = 0.0, t = 0.0;
-    for (size_t i = threadIdx.x; i < nAC; i += 256) {
-        a += partAC[2 * i];
-        c += partAC[2 * i + 1];
-    }
-    for (size_t i = threadIdx.x; i < nT; i += 256) t += partT[i];
+// Two-level fixed-order reduction of the gradient partial sums: block k of
+// kRedBlocks sums a contiguous chunk of the per-row lambda partials and of
+// the per-block temperature partials; then one block sums the block totals.
+constexpr int kRedBlocks = 256;
+
+__device__ inline void tree3(double (*red)[256], double a, double c, double t) {
     red[0][threadIdx.x] = a;
     red[1][threadIdx.x] = c;
     red[2][threadIdx.x] = t;
@@ -485,11 +481,34 @@ __global__ void k_soft_reduce(const double* __restrict__ partAC, size_t nAC,
             for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        grad[0] = (float)red[0][0];
-        grad[1] = (float)red[1][0];
-        grad[2] = (float)red[2][0];
+}
+
+__global__ __launch_bounds__(256) void k_soft_reduce1(const double* __restrict__ partAC,
+                                                      size_t nAC,
+                                                      const double* __restrict__ partT, size_t nT,
+                                                      double* __restrict__ blk) {
+    __shared__ double red[3][256];
+    const size_t ca = (nAC + kRedBlocks - 1) / kRedBlocks, ct = (nT + kRedBlocks - 1) / kRedBlocks;
+    const size_t a0 = blockIdx.x * ca, a1 = a0 + ca < nAC ? a0 + ca : nAC;
+    const size_t t0 = blockIdx.x * ct, t1 = t0 + ct < nT ? t0 + ct : nT;
+    double a = 0.0, c = 0.0, t = 0.0;
+    for (size_t i = a0 + threadIdx.x; i < a1; i += 256) {
+        a += partAC[2 * i];
+        c += partAC[2 * i + 1];
     }
+    for (size_t i = t0 + threadIdx.x; i < t1; i += 256) t += partT[i];
+    tree3(red, a, c, t);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) blk[3 * blockIdx.x + k] = red[k][0];
+}
+
+__global__ __launch_bounds__(256) void k_soft_reduce2(const double* __restrict__ blk,
+                                                      float* __restrict__ grad) {
+    __shared__ double red[3][256];
+    const int t = threadIdx.x;
+    tree3(red, blk[3 * t], blk[3 * t + 1], blk[3 * t + 2]);
+    if (t == 0)
+        for (int k = 0; k < 3; ++k) grad[k] = (float)red[k][0];
 }
 
 }  // namespace
@@ -563,7 +582,9 @@ hipError_t soft_backward(const SoftBuffers& s, int B, int W, int H, int D, const
                        (const float*)nullptr, t2);                                    // G_E1
     hipLaunchKernelGGL(k_soft_hrow_adj<true>, gr, dim3(64 * kRowWaves), kRowWaves * la, st, g, im,
                        t2, (float*)nullptr, partAC, la);                      // G_c . dc/dlambda
-    hipLaunchKernelGGL(k_soft_reduce, dim3(1), dim3(256), 0, st, partAC, (size_t)B * D * H,
-                       partT, (size_t)B * nb, grad);
+    double* blk = partT + (size_t)B * nb;  // kRedBlocks x 3 after the block partials
+    hipLaunchKernelGGL(k_soft_reduce1, dim3(kRedBlocks), dim3(256), 0, st, partAC,
+                       (size_t)B * D * H, partT, (size_t)B * nb, blk);
+    hipLaunchKernelGGL(k_soft_reduce2, dim3(1), dim3(256), 0, st, blk, grad);
     return hipGetLastError();
 }
