@@ -453,16 +453,9 @@ static dco_status soft_front(dco_stereo* h, int B, const uint8_t* L, const uint8
                              const float* theta, SoftBuffers* sb) {
     SoftScratch& f = h->soft;
     const dco_params& p = h->p;
-    const size_t P = (size_t)h->W * h->H;
-    for (int b = 0; b < B; ++b) {
-        DCO_HIP_CHECK(launch_census_arms(L + 3 * P * b, h->W, h->H, p.census_w, p.census_h,
-                                         p.arm_L1, p.arm_tau1, f.cen[0] + P * b, f.arms + P * b,
-                                         f.rgbp[0] + P * b, nullptr, h->stream));
-        DCO_HIP_CHECK(launch_census_arms(R + 3 * P * b, h->W, h->H, p.census_w, p.census_h,
-                                         p.arm_L1, p.arm_tau1, f.cen[1] + P * b,
-                                         f.arms_r + P * b, f.rgbp[1] + P * b, nullptr,
-                                         h->stream));
-    }
+    DCO_HIP_CHECK(launch_census_pairs(L, R, B, h->W, h->H, p.census_w, p.census_h, p.arm_L1,
+                                      p.arm_tau1, f.cen[0], f.cen[1], f.arms, f.arms_r,
+                                      f.rgbp[0], f.rgbp[1], h->stream));
     DCO_HIP_CHECK(soft_prepare(theta, f.tab, f.arms, B, h->W, h->H, h->D, f.n1, f.n2, h->stream));
     *sb = SoftBuffers{f.arms, f.n1, f.n2, f.rgbp[0], f.rgbp[1], f.cen[0], f.cen[1], h->alpha, f.tab};
     DCO_HIP_CHECK(soft_aggregate(*sb, B, h->W, h->H, h->D, f.vol[0], f.vol[1], f.vol[2], h->stream));

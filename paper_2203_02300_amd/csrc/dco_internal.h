@@ -156,6 +156,12 @@ dco_status alloc_records(AggRecords* r, int W, int H);
 hipError_t launch_census_arms(const uint8_t* rgb, int W, int H, int cw, int ch, int L1, int tau1,
                               uint64_t* census, uint32_t* arms, uint32_t* rgb_packed, uint4* pix,
                               hipStream_t st);
+// Census, arms and packed RGB of both views of B pairs (HWC images of 3 W H
+// bytes each, outputs of W H entries each, pair-major) in one launch.
+hipError_t launch_census_pairs(const uint8_t* rgbL, const uint8_t* rgbR, int B, int W, int H,
+                               int cw, int ch, int L1, int tau1, uint64_t* cenL, uint64_t* cenR,
+                               uint32_t* armsL, uint32_t* armsR, uint32_t* rgbpL, uint32_t* rgbpR,
+                               hipStream_t st);
 // Census + arms + packed pixels, then region counts + records, of both views
 // (the one-call path): two launches.
 hipError_t launch_front2(const uint8_t* rgbL, const uint8_t* rgbR, int W, int H, int cw, int ch,

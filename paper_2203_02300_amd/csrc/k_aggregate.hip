@@ -22,8 +22,10 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_agg_stream(dco::AggArgs A)
 
 // Blocks of XCD x in the two-view launch: its nx items (a contiguous,
 // strip-major run), the last m of them split into a top and a bottom half so
-// that the final round of workgroups is not left part-empty.  s8 = resident
-// workgroups per XCD.
+// that the final round of workgroups is not left part-empty.  The top halves
+// of the m items run before their bottom halves: workgroups resident together
+// then walk the same rows of one strip, which the XCD's L2 serves once.
+// s8 = resident workgroups per XCD.
 __host__ __device__ inline void pair_part(int N, int x, int s8, int H, int& start, int& nx,
                                           int& m) {
     const int per = N / 8, rem = N % 8;
@@ -56,8 +58,8 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_agg_pair(dco::AggArgs A0, 
     } else {
         const int j = i - (nx - m);
         if (j >= 2 * m) return;  // uniform: the whole workgroup leaves
-        item = start + nx - m + j / 2;
-        if (j & 1)
+        item = start + nx - m + (j < m ? j : j - m);  // all top halves, then bottoms
+        if (j >= m)
             y0 = A0.H / 2;
         else
             y1 = A0.H / 2;
