@@ -1,6 +1,7 @@
 """Benchmark of the gfx950 adaptive AD-census matcher.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extras]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
+                    [--extras staged,batched,soft] [--cpu-rows N]
 
 A step is one pass of the whole plain matcher (census and arms of both views,
 cost and two-stage aggregation of both views, WTA with sub-pixel refinement,
@@ -81,11 +82,14 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=240)
+    ap.add_argument("--cpu-rows", type=int, default=540)
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="staged,batched,soft",
+                    help="comma list of the extra measurements to run (staged, batched, soft)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of MiB mebibytes (counter calibration)")
     args = ap.parse_args()
+    want = set() if args.no_extras else {e for e in args.extras.split(",") if e}
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(pairs would shard across GPUs with no communication); run with --gpus 1",
@@ -152,14 +156,15 @@ def main():
                     ops_per_pd=ops_per_unit, units_per_launch=2 * V)
 
     extras = {"stage_ms": {n: round(t, 4) for n, t in zip(STAGES, per_call)}}
-    if not args.no_extras:
+    if "staged" in want:
         extras["staged"] = staged_extras(m, gL, gR, args.steps)
     del m
     torch.cuda.empty_cache()
-    if not args.no_extras:
+    if "batched" in want:
         log("bench: batched matcher (32 mixed pairs)")
         extras["batched"] = batched_extras(max(3, args.steps // 10))
         torch.cuda.empty_cache()
+    if "soft" in want:
         log("bench: differentiable soft-argmin (8 x 640x480, D=64)")
         extras["soft"] = soft_extras(max(3, args.steps // 10))
         torch.cuda.empty_cache()
