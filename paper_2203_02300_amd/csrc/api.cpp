@@ -121,10 +121,10 @@ static void free_handle_memory(dco_stereo* h) {
                     h->s.arms[1],    h->s.rec[0].b,   h->s.rec[0].c,
                     h->s.rec[1].b,   h->s.rec[1].c,
                     h->s.agg[0],     h->s.agg[1],     h->s.dint[0],
-                    h->s.dint[1],    h->s.delta,      h->soft.cen[0],  h->soft.cen[1],
-                    h->soft.arms,    h->soft.rgbp[0], h->soft.rgbp[1], h->soft.arms_r,
-                    h->soft.n1,      h->soft.n2,      h->soft.tab,     h->soft.vol[0],
-                    h->soft.vol[1],  h->soft.vol[2],  h->soft.partAC,  h->soft.partT};
+                    h->s.dint[1],    h->s.delta,      h->soft.pix[0],  h->soft.pix[1],
+                    h->soft.arms,    h->soft.arms_r,  h->soft.n1,      h->soft.n2,
+                    h->soft.tab,     h->soft.vol[0],  h->soft.vol[1],  h->soft.vol[2],
+                    h->soft.partAC,  h->soft.partT};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -417,7 +417,7 @@ extern "C" dco_status dco_stereo_last_disparities(dco_stereo* h, int16_t* dL, in
 // ---- differentiable soft-argmin form ----
 
 static void free_soft(SoftScratch& f) {
-    void* ptrs[] = {f.cen[0], f.cen[1], f.arms, f.rgbp[0], f.rgbp[1], f.arms_r, f.n1, f.n2,
+    void* ptrs[] = {f.pix[0], f.pix[1], f.arms,   f.arms_r, f.n1,     f.n2,
                     f.tab,    f.vol[0], f.vol[1], f.vol[2], f.partAC, f.partT};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -430,34 +430,31 @@ static dco_status soft_reserve(dco_stereo* h, int B) {
     (void)hipStreamSynchronize(h->stream);
     free_soft(f);
     const size_t P = (size_t)h->W * h->H, V = P * h->D * B;
-    const size_t nb = (P + 255) / 256;
-    DCO_TRY(dev_alloc(&f.cen[0], P * B));
-    DCO_TRY(dev_alloc(&f.cen[1], P * B));
+    DCO_TRY(dev_alloc(&f.pix[0], P * B));
+    DCO_TRY(dev_alloc(&f.pix[1], P * B));
     DCO_TRY(dev_alloc(&f.arms, P * B));
     DCO_TRY(dev_alloc(&f.arms_r, P * B));
-    DCO_TRY(dev_alloc(&f.rgbp[0], P * B));
-    DCO_TRY(dev_alloc(&f.rgbp[1], P * B));
     DCO_TRY(dev_alloc(&f.n1, P * B));
     DCO_TRY(dev_alloc(&f.n2, P * B));
     DCO_TRY(dev_alloc(&f.tab, 1792));
     for (int k = 0; k < 3; ++k) DCO_TRY(dev_alloc(&f.vol[k], V));
     DCO_TRY(dev_alloc(&f.partAC, 2 * (size_t)B * h->D * h->H));
-    DCO_TRY(dev_alloc(&f.partT, (size_t)B * nb + 3 * 256));  // + the reduction's block totals
+    DCO_TRY(dev_alloc(&f.partT, (size_t)B * h->D * h->H + 3 * 256));  // + the block totals
     f.cap = B;
     return DCO_OK;
 }
 
-// Census, arms and packed RGB of every pair, the Eq. 1 tables for theta,
+// Arms and packed pixels of every pair, the Eq. 1 tables for theta,
 // region counts, and the aggregated volume A2 (vol[0]).
 static dco_status soft_front(dco_stereo* h, int B, const uint8_t* L, const uint8_t* R,
                              const float* theta, SoftBuffers* sb) {
     SoftScratch& f = h->soft;
     const dco_params& p = h->p;
     DCO_HIP_CHECK(launch_census_pairs(L, R, B, h->W, h->H, p.census_w, p.census_h, p.arm_L1,
-                                      p.arm_tau1, f.cen[0], f.cen[1], f.arms, f.arms_r,
-                                      f.rgbp[0], f.rgbp[1], h->stream));
+                                      p.arm_tau1, f.arms, f.arms_r, f.pix[0], f.pix[1],
+                                      h->stream));
     DCO_HIP_CHECK(soft_prepare(theta, f.tab, f.arms, B, h->W, h->H, h->D, f.n1, f.n2, h->stream));
-    *sb = SoftBuffers{f.arms, f.n1, f.n2, f.rgbp[0], f.rgbp[1], f.cen[0], f.cen[1], h->alpha, f.tab};
+    *sb = SoftBuffers{f.arms, f.n1, f.n2, f.pix[0], f.pix[1], h->alpha, f.tab};
     DCO_HIP_CHECK(soft_aggregate(*sb, B, h->W, h->H, h->D, f.vol[0], f.vol[1], f.vol[2], h->stream));
     return DCO_OK;
 }

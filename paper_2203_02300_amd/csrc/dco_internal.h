@@ -54,16 +54,16 @@ struct dco_scratch {
 // B x D x H x W float volumes (grown on demand).
 struct SoftScratch {
     int cap;               // pairs the buffers hold
-    uint64_t* cen[2];      // census codes of left / right views
+    uint4* pix[2];         // packed pixels of left / right views (census lo, census
+                           // hi, RGB | 8 L_min << 24, 0)
     uint32_t* arms;        // arms of the left views
-    uint32_t* rgbp[2];     // packed RGB
     uint32_t* arms_r;      // arms of the right views (computed, unused)
     float* n1;             // region counts
     float* n2;
     float* tab;            // Eq. 1 tables and derivatives for the current theta
     float* vol[3];
     double* partAC;        // per-row partial sums of the lambda gradients
-    double* partT;         // per-block partial sums of the temperature gradient, then
+    double* partT;         // per-row partial sums of the temperature gradient, then
                            // 3 x 256 block totals of the final reduction
 };
 
@@ -72,10 +72,8 @@ struct SoftBuffers {
     const uint32_t* arms;
     const float* n1;
     const float* n2;
-    const uint32_t* rgbL;
-    const uint32_t* rgbR;
-    const uint64_t* cenL;
-    const uint64_t* cenR;
+    const uint4* pixL;
+    const uint4* pixR;
     const float* alpha;
     const float* tab;
 };
@@ -156,12 +154,11 @@ dco_status alloc_records(AggRecords* r, int W, int H);
 hipError_t launch_census_arms(const uint8_t* rgb, int W, int H, int cw, int ch, int L1, int tau1,
                               uint64_t* census, uint32_t* arms, uint32_t* rgb_packed, uint4* pix,
                               hipStream_t st);
-// Census, arms and packed RGB of both views of B pairs (HWC images of 3 W H
+// Arms and packed pixels of both views of B pairs (HWC images of 3 W H
 // bytes each, outputs of W H entries each, pair-major) in one launch.
 hipError_t launch_census_pairs(const uint8_t* rgbL, const uint8_t* rgbR, int B, int W, int H,
-                               int cw, int ch, int L1, int tau1, uint64_t* cenL, uint64_t* cenR,
-                               uint32_t* armsL, uint32_t* armsR, uint32_t* rgbpL, uint32_t* rgbpR,
-                               hipStream_t st);
+                               int cw, int ch, int L1, int tau1, uint32_t* armsL, uint32_t* armsR,
+                               uint4* pixL, uint4* pixR, hipStream_t st);
 // Census + arms + packed pixels, then region counts + records, of both views
 // (the one-call path): two launches.
 hipError_t launch_front2(const uint8_t* rgbL, const uint8_t* rgbR, int W, int H, int cw, int ch,

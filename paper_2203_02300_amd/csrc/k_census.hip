@@ -48,30 +48,27 @@ __global__ __launch_bounds__(256) void k_geometry2(const uint32_t* __restrict__ 
 }
 
 // Every view of a batch of pairs in one launch (blockIdx.z = 2 * pair + view),
-// for the soft path: census codes, arms of the left view, packed RGB.
+// for the soft path: arms and packed pixels.
 __global__ __launch_bounds__(256) void k_census_pairs(const uint8_t* __restrict__ rgbL,
                                                      const uint8_t* __restrict__ rgbR, int W,
                                                      int H, int cw, int ch, int L1, int tau1,
-                                                     uint64_t* __restrict__ cenL,
-                                                     uint64_t* __restrict__ cenR,
                                                      uint32_t* __restrict__ armsL,
                                                      uint32_t* __restrict__ armsR,
-                                                     uint32_t* __restrict__ rgbpL,
-                                                     uint32_t* __restrict__ rgbpR) {
+                                                     uint4* __restrict__ pixL,
+                                                     uint4* __restrict__ pixR) {
     __shared__ dco::CensusLds S;
     const bool r = (blockIdx.z & 1) != 0;
     const size_t P = (size_t)W * H, o = P * (blockIdx.z >> 1);
-    dco::census_tile((r ? rgbR : rgbL) + 3 * o, W, H, cw, ch, L1, tau1, (r ? cenR : cenL) + o,
-                     (r ? armsR : armsL) + o, (r ? rgbpR : rgbpL) + o, nullptr,
+    dco::census_tile((r ? rgbR : rgbL) + 3 * o, W, H, cw, ch, L1, tau1, nullptr,
+                     (r ? armsR : armsL) + o, nullptr, (r ? pixR : pixL) + o,
                      blockIdx.x * dco::kCenTW, blockIdx.y * dco::kCenTH, S);
 }
 
 }  // namespace
 
 hipError_t launch_census_pairs(const uint8_t* rgbL, const uint8_t* rgbR, int B, int W, int H,
-                               int cw, int ch, int L1, int tau1, uint64_t* cenL, uint64_t* cenR,
-                               uint32_t* armsL, uint32_t* armsR, uint32_t* rgbpL, uint32_t* rgbpR,
-                               hipStream_t st) {
+                               int cw, int ch, int L1, int tau1, uint32_t* armsL, uint32_t* armsR,
+                               uint4* pixL, uint4* pixR, hipStream_t st) {
     const size_t P = (size_t)W * H;
     constexpr int kMaxPairs = 16384;  // keeps gridDim.z = 2 * pairs within the launch limit
     for (int b0 = 0; b0 < B; b0 += kMaxPairs) {
@@ -79,8 +76,7 @@ hipError_t launch_census_pairs(const uint8_t* rgbL, const uint8_t* rgbR, int B, 
         const size_t o = P * b0;
         dim3 g((W + dco::kCenTW - 1) / dco::kCenTW, (H + dco::kCenTH - 1) / dco::kCenTH, 2 * nb);
         hipLaunchKernelGGL(k_census_pairs, g, dim3(256), 0, st, rgbL + 3 * o, rgbR + 3 * o, W, H,
-                           cw, ch, L1, tau1, cenL + o, cenR + o, armsL + o, armsR + o, rgbpL + o,
-                           rgbpR + o);
+                           cw, ch, L1, tau1, armsL + o, armsR + o, pixL + o, pixR + o);
     }
     return hipGetLastError();
 }

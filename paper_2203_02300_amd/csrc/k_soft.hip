@@ -6,26 +6,28 @@
 //   E1 = row range sum of c       a1 = (column range sum of E1) / N1     (Eq. 2, stage 1)
 //   E2 = column range sum of a1   A2 = (row range sum of E2) / N2         (Eq. 2, stage 2)
 //   dhat = sum_d d softmax_d(-A2 / T),  lse = log sum_d exp(-A2 / T)
-// Row range sums add at most 2 kLMax + 1 terms directly; column range sums
-// are differences of FP64 running column sums (exact to the final FP32
-// rounding).  Every sum runs in a fixed order, so results are bit-reproducible.
+// Every range sum is a difference of two FP64 prefix sums (along the row, or
+// running down the column), so it is within one FP32 rounding of the exact
+// sum of its FP32 terms.  Every sum runs in a fixed order, so results are
+// bit-reproducible.
 //
 // Backward, given g = dLoss/d dhat:
 //   G_A2  = g w (dhat - d) / T,   dLoss/dT = sum g w (d - dhat) A2 / T^2
 // then the adjoint of each range sum: an output that summed a range hands its
-// adjoint back to every pixel of that range.  Row adjoints are gathers over
-// the (at most 2 kLMax + 1) candidate pixels whose range can cover a pixel;
-// column adjoints are FP64 difference arrays streamed down each column by
-// one thread.  There are no atomics and no float reductions of unspecified
-// order.  Finally
-//   dLoss/dlambda_AD     = sum G_c alpha   d(1 - exp(-(s/3)/lambda_AD))/dlambda_AD
-//   dLoss/dlambda_census = sum G_c (1 - alpha) d(1 - exp(-h/lambda_census))/dlambda_census
-// with fixed-order two-level reductions.
+// adjoint back to every pixel of that range.  The first row adjoint is a
+// gather over the (at most 2 kLMax + 1) candidate pixels whose range can
+// cover a pixel; column adjoints are FP64 difference arrays streamed down each
+// column by one thread.  The last row adjoint is never formed: with
+// E1 = H c,  sum_p (H^T G)(p) dc/dlambda(p) = sum_x G(x) (H dc/dlambda)(x),
+// so the row range sums of the two cost derivatives are dotted with G:
+//   dLoss/dlambda_AD     = sum G_E1 . H (alpha d(1 - exp(-(s/3)/lambda_AD))/dlambda_AD)
+//   dLoss/dlambda_census = sum G_E1 . H ((1 - alpha) d(1 - exp(-h/lambda_census))/dlambda_census)
+// with fixed-order two-level reductions.  There are no atomics.
 //
-// Layout: volumes are B x D x H x W float in handle scratch; arms, census
-// and packed RGB are per pair B x H x W.  Row passes run one workgroup per
-// image row with the row in LDS; column passes one thread per column,
-// streaming down the rows with a ring of FP64 sums in LDS.
+// Layout: volumes are B x D x H x W float in handle scratch; arms and the
+// packed pixels (census, RGB, L_min) are per pair B x H x W.  Row passes run
+// one wavefront per image row with its FP64 prefix in LDS; column passes one
+// thread per column, streaming down the rows with a ring of FP64 sums in LDS.
 #include "dco_internal.h"
 
 namespace {
@@ -81,45 +83,50 @@ __global__ void k_soft_counts(SoftGeom g, float* __restrict__ n1, float* __restr
     n2[i] = (float)s2;
 }
 
-// Raw costs c (and, with kDeriv, the two lambda-derivative factors packed as
-// dc/dlambda_AD and dc/dlambda_c) of one image row for one (pair, d).
+// Eq. 1 tables of the current theta in LDS: the k_soft_tables layout, then
+// alpha_L for L = 0 .. kLMax.
+constexpr int kTabFloats = 1792;
+constexpr size_t kTabLds = (kTabFloats + 32) * sizeof(float);
+
+struct SoftImg {
+    const uint4* pixL;   // B x H x W packed pixels: census lo, census hi,
+    const uint4* pixR;   //   RGB | 8 L_min << 24, 0
+    const float* alpha;  // alpha_L, L = 0..kLMax
+    const float* tab;    // k_soft_tables output
+};
+
+__device__ inline void load_tables(const SoftImg& im, float* lds) {
+    for (int i = threadIdx.x; i < kTabFloats; i += blockDim.x) lds[i] = im.tab[i];
+    if (threadIdx.x <= kLMax) lds[kTabFloats + threadIdx.x] = im.alpha[threadIdx.x];
+    __syncthreads();
+}
+
+// Raw cost c of Eq. 1 for reference pixel a and partner pixel b (and, with
+// kDeriv, its lambda_AD and lambda_census derivatives); c = 1 and zero
+// derivatives when the partner lies outside the image.
 template <bool kDeriv>
-__device__ inline void cost_row(const uint32_t* rgbL, const uint32_t* rgbR, const uint64_t* cenL,
-                                const uint64_t* cenR, const uint32_t* arms, const float* alpha,
-                                const float* tab, int W, int y, int d, int x, float* c,
-                                float* dca, float* dcc) {
-    const size_t i = (size_t)y * W + x;
-    if (x - d < 0) {
-        *c = 1.0f;
-        if (kDeriv) *dca = 0.0f, *dcc = 0.0f;
-        return;
-    }
-    const uint32_t s = __builtin_amdgcn_sad_u8(rgbL[i], rgbR[i - d], 0u);
-    const int h = __popcll(cenL[i] ^ cenR[i - d]);
-    const uint32_t a = arms[i];
-    const int lmin = min(min(arm(a, 0), arm(a, 1)), min(arm(a, 2), arm(a, 3)));
-    const float al = alpha[lmin];
-    *c = al * tab[s] + (1.0f - al) * tab[1536 + h];
+__device__ inline void cost_px(uint4 a, uint4 b, bool inside, const float* tab, float& c,
+                               float& dca, float& dcc) {
+    const uint32_t s = __builtin_amdgcn_sad_u8(a.z << 8, b.z << 8, 0u);  // L_min shifted out
+    const int h = __popcll(((uint64_t)a.y << 32 | a.x) ^ ((uint64_t)b.y << 32 | b.x));
+    const float al = tab[kTabFloats + (a.z >> 27)];
+    const float v = al * tab[s] + (1.0f - al) * tab[1536 + h];
+    c = inside ? v : 1.0f;
     if (kDeriv) {
-        *dca = al * tab[768 + s];
-        *dcc = (1.0f - al) * tab[1664 + h];
+        const float va = al * tab[768 + s], vc = (1.0f - al) * tab[1664 + h];
+        dca = inside ? va : 0.0f;
+        dcc = inside ? vc : 0.0f;
     }
 }
 
-struct SoftImg {
-    const uint32_t* rgbL;  // B x H x W packed RGB
-    const uint32_t* rgbR;
-    const uint64_t* cenL;  // B x H x W census
-    const uint64_t* cenR;
-    const float* alpha;    // alpha_L, L = 0..kLMax
-    const float* tab;      // k_soft_tables output
-};
-
 // Row passes: one wavefront per image row, kRowWaves wavefronts per
-// workgroup, each with its own LDS slice (no workgroup barriers) and
-// kRowsPerWave rows in turn.  Row ids run over (b, d, y) with y fastest.
+// workgroup, each with its own LDS slice (no workgroup barriers after the
+// table load) and kRowsPerWave rows in turn.  Row ids run over (b, d, y)
+// with y fastest.  Lane `lane` handles columns lane + 64 k; loads are issued
+// kRowBatch columns at a time with clamped (always valid) addresses.
 constexpr int kRowWaves = 4;
 constexpr int kRowsPerWave = 4;
+constexpr int kRowBatch = 8;
 
 __device__ inline void row_of(int rid, int D, int H, int& b, int& d, int& y) {
     y = rid % H;
@@ -128,27 +135,86 @@ __device__ inline void row_of(int rid, int D, int H, int& b, int& d, int& y) {
     b = bd / D;
 }
 
-// FP64 inclusive prefix of the wavefront's row (W <= 2048): P[0] = 0,
-// P[x + 1] = row[0] + ... + row[x].  Lane L sums its contiguous run of
-// ceil(W / 64) values, the run totals are scanned across the wavefront, and
-// the runs are written with their offsets; fixed order, bit-reproducible.
-__device__ inline void wave_row_prefix(const float* row, double* P, int W) {
-    const int lane = threadIdx.x & 63, c = (W + 63) / 64, x0 = lane * c;
-    double acc = 0.0;
-    for (int k = 0; k < c; ++k)
-        if (x0 + k < W) acc += (double)row[x0 + k];
-    double inc = acc;
-    for (int off = 1; off < 64; off <<= 1) {
-        const double n = __shfl_up(inc, off, 64);
-        if (lane >= off) inc += n;
+template <unsigned Ctrl, unsigned RowMask>
+__device__ inline double dpp_f64(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, Ctrl, RowMask,
+                                                              0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), Ctrl,
+                                                              RowMask, 0xf, false);
+    return __builtin_bit_cast(double, (uint64_t)hi << 32 | lo);
+}
+
+__device__ inline double readlane_f64(double v, int l) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, (uint64_t)hi << 32 | lo);
+}
+
+// FP64 inclusive scan across the wavefront (lane L gets v(0) + ... + v(L)):
+// DPP row shifts 1, 2, 4, 8, then the row broadcasts of lanes 15 and 31.
+__device__ inline double wave_scan_f64(double v) {
+    v += dpp_f64<0x111, 0xf>(v);
+    v += dpp_f64<0x112, 0xf>(v);
+    v += dpp_f64<0x114, 0xf>(v);
+    v += dpp_f64<0x118, 0xf>(v);
+    v += dpp_f64<0x142, 0xa>(v);
+    v += dpp_f64<0x143, 0xc>(v);
+    return v;
+}
+
+// FP64 prefixes of the wavefront's row (W <= 2048): P[0] = 0 and
+// P[x + 1] = v(0) + ... + v(x), where v is (kCost) the raw cost of Eq. 1 of
+// row y for disparity d, or (kDeriv) its lambda_AD derivative, with the
+// lambda_census derivative prefixed into P2, or else the row of `src`.  The
+// columns go in 64-wide chunks: a wavefront scan per chunk plus the total of
+// the chunks before it; fixed order, bit-reproducible.
+template <bool kCost, bool kDeriv>
+__device__ inline void prefix_row(const uint4* pl, const uint4* pr, const float* src, int W, int d,
+                                  const float* tab, double* P, double* P2) {
+    const int lane = threadIdx.x & 63;
+    double carry = 0.0, carry2 = 0.0;
+    if (lane == 0) {
+        P[0] = 0.0;
+        if (kDeriv) P2[0] = 0.0;
     }
-    double run = inc - acc;
-    if (lane == 0) P[0] = 0.0;
-    for (int k = 0; k < c; ++k)
-        if (x0 + k < W) {
-            run += (double)row[x0 + k];
-            P[x0 + k + 1] = run;
+    for (int x0 = 0; x0 < W; x0 += 64 * kRowBatch) {
+        float v[kRowBatch], v2[kRowBatch];
+        if (kCost) {
+            uint4 a[kRowBatch], b[kRowBatch];
+#pragma unroll
+            for (int j = 0; j < kRowBatch; ++j) {
+                const int xc = min(x0 + 64 * j + lane, W - 1);
+                a[j] = pl[xc];
+                b[j] = pr[max(xc - d, 0)];
+            }
+#pragma unroll
+            for (int j = 0; j < kRowBatch; ++j) {
+                const int x = x0 + 64 * j + lane;
+                float c, dca, dcc;
+                cost_px<kDeriv>(a[j], b[j], x - d >= 0, tab, c, dca, dcc);
+                v[j] = kDeriv ? dca : c;
+                v2[j] = dcc;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kRowBatch; ++j) v[j] = src[min(x0 + 64 * j + lane, W - 1)];
         }
+#pragma unroll
+        for (int j = 0; j < kRowBatch; ++j) {
+            if (x0 + 64 * j >= W) break;  // uniform
+            const int x = x0 + 64 * j + lane;
+            const double inc = wave_scan_f64(x < W ? (double)v[j] : 0.0);
+            if (x < W) P[x + 1] = carry + inc;
+            carry += readlane_f64(inc, 63);
+            if (kDeriv) {
+                const double inc2 = wave_scan_f64(x < W ? (double)v2[j] : 0.0);
+                if (x < W) P2[x + 1] = carry2 + inc2;
+                carry2 += readlane_f64(inc2, 63);
+            }
+        }
+    }
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -166,11 +232,14 @@ __device__ inline float row_adjoint(const float* rowp, const uchar2* lrp, int xp
     return s;
 }
 
-// Bytes of dynamic LDS per wavefront: forward (row + FP64 prefix) and
-// adjoint (padded row + padded arms).
-inline size_t row_lds_fwd(int W) { return ((size_t)W * 4 + 15) / 16 * 16 + (size_t)(W + 1) * 8; }
+// Bytes of dynamic LDS per wavefront: forward (one FP64 prefix), gradient
+// (two) and adjoint (padded row + padded arms).
+__host__ __device__ inline size_t row_bytes(int W) { return ((size_t)W * 4 + 15) / 16 * 16; }
+__host__ __device__ inline size_t prefix_bytes(int W) { return ((size_t)(W + 1) * 8 + 15) / 16 * 16; }
+inline size_t row_lds_fwd(int W) { return prefix_bytes(W); }
+inline size_t row_lds_grad(int W) { return 2 * prefix_bytes(W); }
 inline size_t row_lds_adj(int W) {
-    return ((size_t)(W + 2 * kLMax) * 4 + 15) / 16 * 16 + (size_t)(W + 2 * kLMax) * 2;
+    return row_bytes(W + 2 * kLMax) + (size_t)(W + 2 * kLMax) * 2;
 }
 
 // Lets a kernel take `bytes` of dynamic LDS (above the default limit for
@@ -192,9 +261,9 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hrow(SoftGeom g, SoftIm
                                                               size_t lds_wave) {
     extern __shared__ __align__(16) unsigned char dyn[];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, W = g.W;
-    unsigned char* mine = dyn + w * lds_wave;
-    float* row = reinterpret_cast<float*>(mine);
-    double* Pf = reinterpret_cast<double*>(mine + ((size_t)W * 4 + 15) / 16 * 16);
+    float* tab = reinterpret_cast<float*>(dyn);
+    double* Pf = reinterpret_cast<double*>(dyn + (kCost ? kTabLds : 0) + w * lds_wave);
+    if (kCost) load_tables(im, tab);
     const size_t P = (size_t)W * g.H;
     const int nrows = g.B * g.D * g.H;
     const int r0 = (blockIdx.x * kRowWaves + w) * kRowsPerWave;
@@ -202,42 +271,46 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hrow(SoftGeom g, SoftIm
         int b, d, y;
         row_of(rid, g.D, g.H, b, d, y);
         const size_t base = ((size_t)b * g.D + d) * P + (size_t)y * W;
-        const uint32_t* arms = g.arms + b * P + (size_t)y * W;
-        for (int x = lane; x < W; x += 64) {
-            float c;
-            if (kCost)
-                cost_row<false>(im.rgbL + b * P, im.rgbR + b * P, im.cenL + b * P,
-                                im.cenR + b * P, g.arms + b * P, im.alpha, im.tab, W, y, d, x, &c,
-                                nullptr, nullptr);
-            else
-                c = in[base + x];
-            row[x] = c;
-        }
-        __builtin_amdgcn_wave_barrier();
-        wave_row_prefix(row, Pf, W);
-        for (int x = lane; x < W; x += 64) {
-            const uint32_t a = arms[x];
-            const float v = (float)(Pf[x + arm(a, 1) + 1] - Pf[x - arm(a, 0)]);
-            out[base + x] = kCost ? v : v / g.n2[b * P + (size_t)y * W + x];
+        const size_t pix = b * P + (size_t)y * W;
+        prefix_row<kCost, false>(im.pixL + pix, im.pixR + pix, in + base, W, d, tab, Pf, nullptr);
+        for (int x0 = 0; x0 < W; x0 += 64 * kRowBatch) {
+            uint32_t a[kRowBatch];
+            float n[kRowBatch];
+#pragma unroll
+            for (int j = 0; j < kRowBatch; ++j) {
+                const int xc = min(x0 + 64 * j + lane, W - 1);
+                a[j] = g.arms[pix + xc];
+                n[j] = kCost ? 1.0f : g.n2[pix + xc];
+            }
+#pragma unroll
+            for (int j = 0; j < kRowBatch; ++j) {
+                const int x = x0 + 64 * j + lane;
+                if (x < W) {
+                    const float v = (float)(Pf[x + arm(a[j], 1) + 1] - Pf[x - arm(a[j], 0)]);
+                    out[base + x] = kCost ? v : v / n[j];
+                }
+            }
         }
         __builtin_amdgcn_wave_barrier();
     }
 }
 
-// Adjoint row passes.  kGrad: the adjoint of E1's row sums (G_c), dotted
-// with dc/dlambda_AD and dc/dlambda_census into one FP64 pair per row;
-// else out = the adjoint of A2's row sums (G_E2).
-template <bool kGrad>
-__global__ __launch_bounds__(64 * kRowWaves) void k_soft_hrow_adj(SoftGeom g, SoftImg im,
-                                                                  const float* __restrict__ in,
-                                                                  float* __restrict__ out,
-                                                                  double* __restrict__ part,
-                                                                  size_t lds_wave) {
+// Gradient row pass.  With G = dLoss/dE1 and E1 = H c (H the row range-sum
+// operator), dLoss/dlambda = sum_p (H^T G)(p) dc/dlambda(p)
+//                          = sum_x G(x) (H dc/dlambda)(x):
+// the range sums of the two cost derivatives, dotted with G, give one FP64
+// pair per row (no adjoint volume is formed).
+__global__ __launch_bounds__(64 * kRowWaves) void k_soft_hgrad(SoftGeom g, SoftImg im,
+                                                               const float* __restrict__ G,
+                                                               double* __restrict__ part,
+                                                               size_t lds_wave) {
     extern __shared__ __align__(16) unsigned char dyn[];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, W = g.W;
-    unsigned char* mine = dyn + w * lds_wave;
-    float* row = reinterpret_cast<float*>(mine);
-    uchar2* lr = reinterpret_cast<uchar2*>(mine + ((size_t)(W + 2 * kLMax) * 4 + 15) / 16 * 16);
+    float* tab = reinterpret_cast<float*>(dyn);
+    unsigned char* mine = dyn + kTabLds + w * lds_wave;
+    double* Pa = reinterpret_cast<double*>(mine);
+    double* Pc = reinterpret_cast<double*>(mine + prefix_bytes(W));
+    load_tables(im, tab);
     const size_t P = (size_t)W * g.H;
     const int nrows = g.B * g.D * g.H;
     const int r0 = (blockIdx.x * kRowWaves + w) * kRowsPerWave;
@@ -245,38 +318,100 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hrow_adj(SoftGeom g, So
         int b, d, y;
         row_of(rid, g.D, g.H, b, d, y);
         const size_t base = ((size_t)b * g.D + d) * P + (size_t)y * W;
-        const uint32_t* arms = g.arms + b * P + (size_t)y * W;
-        for (int x = lane - kLMax; x < W + kLMax; x += 64) {
-            const bool in_row = x >= 0 && x < W;
-            const uint32_t a = in_row ? arms[x] : 0u;
-            row[x + kLMax] = in_row ? in[base + x] : 0.0f;
-            lr[x + kLMax] = make_uchar2((unsigned char)arm(a, 0), (unsigned char)arm(a, 1));
+        const size_t pix = b * P + (size_t)y * W;
+        prefix_row<true, true>(im.pixL + pix, im.pixR + pix, nullptr, W, d, tab, Pa, Pc);
+        double sa = 0.0, sc = 0.0;
+        for (int x0 = 0; x0 < W; x0 += 64 * kRowBatch) {
+            uint32_t a[kRowBatch];
+            float gv[kRowBatch];
+#pragma unroll
+            for (int j = 0; j < kRowBatch; ++j) {
+                const int xc = min(x0 + 64 * j + lane, W - 1);
+                a[j] = g.arms[pix + xc];
+                gv[j] = G[base + xc];
+            }
+#pragma unroll
+            for (int j = 0; j < kRowBatch; ++j) {
+                const int x = x0 + 64 * j + lane;
+                if (x < W) {
+                    const int hi = x + arm(a[j], 1) + 1, lo = x - arm(a[j], 0);
+                    sa += (double)gv[j] * (Pa[hi] - Pa[lo]);
+                    sc += (double)gv[j] * (Pc[hi] - Pc[lo]);
+                }
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {  // fixed-order wavefront reduction
+            sa += __shfl_down(sa, off, 64);
+            sc += __shfl_down(sc, off, 64);
+        }
+        if (lane == 0) {
+            part[2 * (size_t)rid] = sa;
+            part[2 * (size_t)rid + 1] = sc;
+        }
+        __builtin_amdgcn_wave_barrier();  // Pa, Pc are rewritten for the next row
+    }
+}
+
+// Backward seed and adjoint row pass.  Per pixel and disparity, with
+// w = softmax weight and g = dLoss/d dhat:
+//   G_A2 / N2 = g w (dhat - d) / (T N2),   dLoss/dT term = g w (d - dhat) A2 / T^2;
+// out = the adjoint of A2's row range sums applied to G_A2 / N2 (G_E2), and
+// the temperature terms of the row summed into one FP64 value per row.
+__global__ __launch_bounds__(64 * kRowWaves) void k_soft_seed_adj(
+    SoftGeom g, const float* __restrict__ A2, const float* __restrict__ theta,
+    const float* __restrict__ dhat, const float* __restrict__ lse,
+    const float* __restrict__ gdhat, float* __restrict__ out, double* __restrict__ partT,
+    size_t lds_wave) {
+    extern __shared__ __align__(16) unsigned char dyn[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, W = g.W;
+    unsigned char* mine = dyn + w * lds_wave;
+    float* row = reinterpret_cast<float*>(mine);
+    uchar2* lr = reinterpret_cast<uchar2*>(mine + row_bytes(W + 2 * kLMax));
+    const float T = theta[2], invT = 1.0f / T;
+    const size_t P = (size_t)W * g.H;
+    const int nrows = g.B * g.D * g.H;
+    const int r0 = (blockIdx.x * kRowWaves + w) * kRowsPerWave;
+    const int Wp = W + 2 * kLMax;
+    for (int rid = r0; rid < min(nrows, r0 + kRowsPerWave); ++rid) {
+        int b, d, y;
+        row_of(rid, g.D, g.H, b, d, y);
+        const size_t base = ((size_t)b * g.D + d) * P + (size_t)y * W;
+        const size_t pix = b * P + (size_t)y * W;
+        double acc = 0.0;
+        for (int x0 = 0; x0 < Wp; x0 += 64 * kRowBatch) {  // padded index x + kLMax
+            float a2[kRowBatch], gp[kRowBatch], dh[kRowBatch], l[kRowBatch], n2[kRowBatch];
+            uint32_t a[kRowBatch];
+#pragma unroll
+            for (int j = 0; j < kRowBatch; ++j) {
+                const size_t xc = (size_t)min(max(x0 + 64 * j + lane - kLMax, 0), W - 1);
+                a2[j] = A2[base + xc];
+                gp[j] = gdhat[pix + xc];
+                dh[j] = dhat[pix + xc];
+                l[j] = lse[pix + xc];
+                n2[j] = g.n2[pix + xc];
+                a[j] = g.arms[pix + xc];
+            }
+#pragma unroll
+            for (int j = 0; j < kRowBatch; ++j) {
+                const int i = x0 + 64 * j + lane, x = i - kLMax;
+                const bool in_row = x >= 0 && x < W;
+                const float wgt = expf(-a2[j] * invT - l[j]);
+                const float G = gp[j] * wgt * (dh[j] - (float)d) * invT / n2[j];
+                if (in_row)
+                    acc += (double)(gp[j] * wgt * ((float)d - dh[j]) * a2[j]) *
+                           (double)(invT * invT);
+                if (i < Wp) {
+                    row[i] = in_row ? G : 0.0f;
+                    lr[i] = in_row ? make_uchar2((unsigned char)arm(a[j], 0),
+                                                 (unsigned char)arm(a[j], 1))
+                                   : make_uchar2(0, 0);
+                }
+            }
         }
         __builtin_amdgcn_wave_barrier();
-        double sa = 0.0, sc = 0.0;
-        for (int xp = lane; xp < W; xp += 64) {
-            const float s = row_adjoint(row + kLMax, lr + kLMax, xp);
-            if (kGrad) {
-                float c, dca, dcc;
-                cost_row<true>(im.rgbL + b * P, im.rgbR + b * P, im.cenL + b * P,
-                               im.cenR + b * P, g.arms + b * P, im.alpha, im.tab, W, y, d, xp, &c,
-                               &dca, &dcc);
-                sa += (double)(s * dca);
-                sc += (double)(s * dcc);
-            } else {
-                out[base + xp] = s;
-            }
-        }
-        if (kGrad) {  // fixed-order wavefront reduction
-            for (int off = 32; off > 0; off >>= 1) {
-                sa += __shfl_down(sa, off, 64);
-                sc += __shfl_down(sc, off, 64);
-            }
-            if (lane == 0) {
-                part[2 * (size_t)rid] = sa;
-                part[2 * (size_t)rid + 1] = sc;
-            }
-        }
+        for (int x = lane; x < W; x += 64) out[base + x] = row_adjoint(row + kLMax, lr + kLMax, x);
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+        if (lane == 0) partT[rid] = acc;
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -288,7 +423,28 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hrow_adj(SoftGeom g, So
 // does not depend on scheduling.
 constexpr int kSoftCols = 128;
 constexpr int kSoftRing = 2 * kLMax + 2;
-constexpr int kSoftPre = 8;  // rows loaded ahead
+constexpr int kSoftPre = 8;  // rows per load batch (one batch ahead)
+
+// kSoftPre rows of a column pass's per-row inputs, loaded one batch ahead of
+// the rows being processed (clamped rows: every load is unconditional).
+struct ColBatch {
+    float v[kSoftPre];     // input of row y
+    uint32_t a[kSoftPre];  // arms of row y (adjoint) or of row y - kLMax (forward)
+    float s[kSoftPre];     // scale of row y - kLMax
+};
+
+template <bool kScale, bool kAdj>
+__device__ inline void col_load(const float* src, const uint32_t* arms, const float* sc, int W,
+                                int H, int y0, ColBatch& c) {
+#pragma unroll
+    for (int k = 0; k < kSoftPre; ++k) {
+        const int y = y0 + k, yo = y - kLMax;
+        const size_t yq = (size_t)min(y, H - 1), oq = (size_t)min(max(yo, 0), H - 1);
+        c.v[k] = src[yq * W];
+        c.a[k] = arms[(kAdj ? yq : oq) * W];
+        c.s[k] = kScale ? sc[oq * W] : 1.0f;
+    }
+}
 
 // out(y) = (sum of in over the vertical range of pixel y) [/ scale(y)], with
 // the running column prefix P: out(y) = P(y + dn) - P(y - u - 1).
@@ -306,38 +462,32 @@ __global__ __launch_bounds__(kSoftCols) void k_soft_vs(SoftGeom g, const float* 
     const uint32_t* arms = g.arms + (size_t)b * P + xc;
     const float* sc = (kScale ? scale : in) + (size_t)b * P + xc;
     float* dst = out + (size_t)bd * P + xc;
+    const int rows = g.H + kLMax;
     double acc = 0.0;
     int slot = 0;  // ring slot of row y (y mod kSoftRing)
-    for (int y0 = 0; y0 < g.H + kLMax; y0 += kSoftPre) {
-        float v[kSoftPre];
-        uint32_t a[kSoftPre];
-        float s[kSoftPre];
-#pragma unroll
-        for (int k = 0; k < kSoftPre; ++k) {  // clamped rows: every load is unconditional
-            const int y = y0 + k, yo = y - kLMax;
-            const size_t yq = (size_t)min(y, g.H - 1), oq = (size_t)min(max(yo, 0), g.H - 1);
-            v[k] = src[yq * g.W];
-            a[k] = arms[oq * g.W];
-            s[k] = kScale ? sc[oq * g.W] : 1.0f;
-            v[k] = y < g.H ? v[k] : 0.0f;
-        }
+    ColBatch cur, nxt;
+    col_load<kScale, false>(src, arms, sc, g.W, g.H, 0, cur);
+    for (int y0 = 0; y0 < rows; y0 += kSoftPre) {
+        if (y0 + kSoftPre < rows)  // uniform: the next batch is in flight meanwhile
+            col_load<kScale, false>(src, arms, sc, g.W, g.H, y0 + kSoftPre, nxt);
 #pragma unroll
         for (int k = 0; k < kSoftPre; ++k) {
             const int y = y0 + k, yo = y - kLMax;
-            acc += (double)v[k];
+            acc += y < g.H ? (double)cur.v[k] : 0.0;
             ring[slot][t] = acc;
             if (yo >= 0 && yo < g.H) {
-                const int u = arm(a[k], 2), dn = arm(a[k], 3);
+                const int u = arm(cur.a[k], 2), dn = arm(cur.a[k], 3);
                 // P(yo + dn) is kLMax - dn rows back, P(yo - u - 1) kLMax + u + 1
                 int sh = slot - (kLMax - dn), sl = slot - (kLMax + u + 1);
                 sh += sh < 0 ? kSoftRing : 0;
                 sl += sl < 0 ? kSoftRing : 0;
                 const double lo = yo - u - 1 >= 0 ? ring[sl][t] : 0.0;
                 const float r = (float)(ring[sh][t] - lo);
-                if (ok) dst[(size_t)yo * g.W] = kScale ? r / s[k] : r;
+                if (ok) dst[(size_t)yo * g.W] = kScale ? r / cur.s[k] : r;
             }
             slot = slot + 1 == kSoftRing ? 0 : slot + 1;
         }
+        cur = nxt;
     }
 }
 
@@ -360,40 +510,36 @@ __global__ __launch_bounds__(kSoftCols) void k_soft_vsa(SoftGeom g, const float*
     const float* sc = (kScale ? scale : in) + (size_t)b * P + xc;
     float* dst = out + (size_t)bd * P + xc;
     for (int i = 0; i < kSoftRing; ++i) ring[i][t] = 0.0;
+    const int rows = g.H + kLMax;
     double run = 0.0;
     int slot = 0;  // ring slot of row y
-    for (int y0 = 0; y0 < g.H + kLMax; y0 += kSoftPre) {
-        float v[kSoftPre];
-        uint32_t a[kSoftPre];
-        float s[kSoftPre];
-#pragma unroll
-        for (int k = 0; k < kSoftPre; ++k) {  // clamped rows: every load is unconditional
-            const int y = y0 + k, yo = y - kLMax;
-            const size_t yq = (size_t)min(y, g.H - 1), oq = (size_t)min(max(yo, 0), g.H - 1);
-            v[k] = src[yq * g.W];
-            a[k] = arms[yq * g.W];
-            s[k] = kScale ? sc[oq * g.W] : 1.0f;
-        }
+    ColBatch cur, nxt;
+    col_load<kScale, true>(src, arms, sc, g.W, g.H, 0, cur);
+    for (int y0 = 0; y0 < rows; y0 += kSoftPre) {
+        if (y0 + kSoftPre < rows)  // uniform: the next batch is in flight meanwhile
+            col_load<kScale, true>(src, arms, sc, g.W, g.H, y0 + kSoftPre, nxt);
 #pragma unroll
         for (int k = 0; k < kSoftPre; ++k) {
             const int y = y0 + k, yo = y - kLMax;
             if (y < g.H) {  // uniform
-                const int u = arm(a[k], 2), dn = arm(a[k], 3);
+                const int u = arm(cur.a[k], 2), dn = arm(cur.a[k], 3);
                 int sa = slot - u, se = slot + dn + 1;
                 sa += sa < 0 ? kSoftRing : 0;
                 se -= se >= kSoftRing ? kSoftRing : 0;
-                ring[sa][t] += (double)v[k];
-                ring[se][t] -= (double)v[k];
+                ring[sa][t] += (double)cur.v[k];
+                ring[se][t] -= (double)cur.v[k];
             }
             if (yo >= 0) {  // row yo is final: its slot is kLMax rows back
                 int so = slot - kLMax;
                 so += so < 0 ? kSoftRing : 0;
                 run += ring[so][t];
                 ring[so][t] = 0.0;  // reused for row yo + kSoftRing
-                if (ok && yo < g.H) dst[(size_t)yo * g.W] = kScale ? (float)run / s[k] : (float)run;
+                if (ok && yo < g.H)
+                    dst[(size_t)yo * g.W] = kScale ? (float)run / cur.s[k] : (float)run;
             }
             slot = slot + 1 == kSoftRing ? 0 : slot + 1;
         }
+        cur = nxt;
     }
 }
 
@@ -419,41 +565,6 @@ __global__ __launch_bounds__(256) void k_soft_argmin(SoftGeom g, const float* __
     }
     dhat[(size_t)b * P + i] = zd / z;
     lse[(size_t)b * P + i] = m + logf(z);
-}
-
-// Backward seed: G(p,d) = g w (dhat - d) / (T N2), per-block partial sums of
-// the T-gradient terms g w (d - dhat) A2 / T^2 (one partial per block).
-__global__ __launch_bounds__(256) void k_soft_seed(SoftGeom g, const float* __restrict__ A2,
-                                                   const float* __restrict__ theta,
-                                                   const float* __restrict__ dhat,
-                                                   const float* __restrict__ lse,
-                                                   const float* __restrict__ gdhat,
-                                                   float* __restrict__ G,
-                                                   double* __restrict__ partT) {
-    __shared__ double red[256];
-    const size_t P = (size_t)g.W * g.H;
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    const int b = blockIdx.y;
-    const float T = theta[2], invT = 1.0f / T;
-    double acc = 0.0;
-    if (i < P) {
-        const size_t pi = (size_t)b * P + i;
-        const float gp = gdhat[pi], dh = dhat[pi], l = lse[pi], n2 = g.n2[pi];
-        for (int d = 0; d < g.D; ++d) {
-            const size_t vi = ((size_t)b * g.D + d) * P + i;
-            const float a2 = A2[vi];
-            const float w = expf(-a2 * invT - l);
-            G[vi] = gp * w * (dh - (float)d) * invT / n2;
-            acc += (double)(gp * w * ((float)d - dh) * a2) * (double)(invT * invT);
-        }
-    }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partT[(size_t)b * gridDim.x + blockIdx.x] = red[0];
 }
 
 // Adjoint of a row range sum: out(x') = sum over x with x' in [x - l(x), x + r(x)]
@@ -528,16 +639,17 @@ hipError_t soft_prepare(const float* theta, float* tab, const uint32_t* arms, in
 hipError_t soft_aggregate(const SoftBuffers& s, int B, int W, int H, int D, float* A2, float* t1,
                           float* t2, hipStream_t st) {
     SoftGeom g{s.arms, s.n1, s.n2, B, W, H, D};
-    SoftImg im{s.rgbL, s.rgbR, s.cenL, s.cenR, s.alpha, s.tab};
+    SoftImg im{s.pixL, s.pixR, s.alpha, s.tab};
     const int nrows = B * D * H;
     const dim3 gr((nrows + kRowWaves * kRowsPerWave - 1) / (kRowWaves * kRowsPerWave));
     const size_t lf = row_lds_fwd(W);
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_soft_hrow<true>), kRowWaves * lf);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_soft_hrow<true>),
+                             kTabLds + kRowWaves * lf);
     if (e == hipSuccess)
         e = allow_lds(reinterpret_cast<const void*>(&k_soft_hrow<false>), kRowWaves * lf);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_soft_hrow<true>, gr, dim3(64 * kRowWaves), kRowWaves * lf, st, g, im,
-                       (const float*)nullptr, t1, lf);                                       // E1
+    hipLaunchKernelGGL(k_soft_hrow<true>, gr, dim3(64 * kRowWaves), kTabLds + kRowWaves * lf, st, g,
+                       im, (const float*)nullptr, t1, lf);                                   // E1
     const dim3 gv((W + kSoftCols - 1) / kSoftCols, B * D);
     hipLaunchKernelGGL(k_soft_vs<true>, gv, dim3(kSoftCols), 0, st, g, t1, s.n1, t2);      // a1
     hipLaunchKernelGGL(k_soft_vs<false>, gv, dim3(kSoftCols), 0, st, g, t2,
@@ -562,29 +674,25 @@ hipError_t soft_backward(const SoftBuffers& s, int B, int W, int H, int D, const
                          const float* gdhat, float* t1, float* t2, double* partAC,
                          double* partT, float* grad, hipStream_t st) {
     SoftGeom g{s.arms, s.n1, s.n2, B, W, H, D};
-    SoftImg im{s.rgbL, s.rgbR, s.cenL, s.cenR, s.alpha, s.tab};
-    const size_t P = (size_t)W * H;
-    const unsigned nb = (unsigned)((P + 255) / 256);
-    hipLaunchKernelGGL(k_soft_seed, dim3(nb, B), dim3(256), 0, st, g, A2, theta, dhat, lse, gdhat,
-                       t1, partT);                                              // G_A2 / N2
+    SoftImg im{s.pixL, s.pixR, s.alpha, s.tab};
     const int nrows = B * D * H;
     const dim3 gr((nrows + kRowWaves * kRowsPerWave - 1) / (kRowWaves * kRowsPerWave));
-    const size_t la = row_lds_adj(W);
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_soft_hrow_adj<false>), kRowWaves * la);
+    const size_t la = row_lds_adj(W), lg = row_lds_grad(W);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_soft_seed_adj), kRowWaves * la);
     if (e == hipSuccess)
-        e = allow_lds(reinterpret_cast<const void*>(&k_soft_hrow_adj<true>), kRowWaves * la);
+        e = allow_lds(reinterpret_cast<const void*>(&k_soft_hgrad), kTabLds + kRowWaves * lg);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_soft_hrow_adj<false>, gr, dim3(64 * kRowWaves), kRowWaves * la, st, g, im,
-                       t1, t2, (double*)nullptr, la);                         // G_E2
+    hipLaunchKernelGGL(k_soft_seed_adj, gr, dim3(64 * kRowWaves), kRowWaves * la, st, g, A2, theta,
+                       dhat, lse, gdhat, t2, partT, la);                 // G_E2, T-gradient terms
     const dim3 gv((W + kSoftCols - 1) / kSoftCols, B * D);
     hipLaunchKernelGGL(k_soft_vsa<true>, gv, dim3(kSoftCols), 0, st, g, t2, s.n1, t1);  // G_a1/N1
     hipLaunchKernelGGL(k_soft_vsa<false>, gv, dim3(kSoftCols), 0, st, g, t1,
                        (const float*)nullptr, t2);                                    // G_E1
-    hipLaunchKernelGGL(k_soft_hrow_adj<true>, gr, dim3(64 * kRowWaves), kRowWaves * la, st, g, im,
-                       t2, (float*)nullptr, partAC, la);                      // G_c . dc/dlambda
-    double* blk = partT + (size_t)B * nb;  // kRedBlocks x 3 after the block partials
+    hipLaunchKernelGGL(k_soft_hgrad, gr, dim3(64 * kRowWaves), kTabLds + kRowWaves * lg, st, g,
+                       im, t2, partAC, lg);                                // G_E1 . H dc/dlambda
+    double* blk = partT + (size_t)nrows;  // kRedBlocks x 3 after the row partials
     hipLaunchKernelGGL(k_soft_reduce1, dim3(kRedBlocks), dim3(256), 0, st, partAC,
-                       (size_t)B * D * H, partT, (size_t)B * nb, blk);
+                       (size_t)nrows, partT, (size_t)nrows, blk);
     hipLaunchKernelGGL(k_soft_reduce2, dim3(1), dim3(256), 0, st, blk, grad);
     return hipGetLastError();
 }
