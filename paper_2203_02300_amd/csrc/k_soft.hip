@@ -544,7 +544,11 @@ __global__ __launch_bounds__(kSoftCols) void k_soft_vsa(SoftGeom g, const float*
 }
 
 
-// Soft-argmin over d per pixel: dhat and lse (log-sum-exp of -A2/T).
+// Soft-argmin over d per pixel: dhat and lse (log-sum-exp of -A2/T), in one
+// pass over the slices: kArgBatch slices are loaded at a time and the running
+// sums are rescaled whenever the running maximum grows.
+constexpr int kArgBatch = 16;
+
 __global__ __launch_bounds__(256) void k_soft_argmin(SoftGeom g, const float* __restrict__ A2,
                                                      const float* __restrict__ theta,
                                                      float* __restrict__ dhat,
@@ -555,13 +559,26 @@ __global__ __launch_bounds__(256) void k_soft_argmin(SoftGeom g, const float* __
     if (i >= P) return;
     const float invT = 1.0f / theta[2];
     const float* a = A2 + (size_t)b * g.D * P + i;
-    float m = -a[0] * invT;
-    for (int d = 1; d < g.D; ++d) m = fmaxf(m, -a[(size_t)d * P] * invT);
-    float z = 0.0f, zd = 0.0f;
-    for (int d = 0; d < g.D; ++d) {
-        const float e = expf(-a[(size_t)d * P] * invT - m);
-        z += e;
-        zd += (float)d * e;
+    float m = -INFINITY, z = 0.0f, zd = 0.0f;
+    for (int d0 = 0; d0 < g.D; d0 += kArgBatch) {
+        float v[kArgBatch];
+#pragma unroll
+        for (int j = 0; j < kArgBatch; ++j) v[j] = -a[(size_t)min(d0 + j, g.D - 1) * P] * invT;
+        float mb = m;
+#pragma unroll
+        for (int j = 0; j < kArgBatch; ++j) mb = d0 + j < g.D ? fmaxf(mb, v[j]) : mb;
+        const float sc = expf(m - mb);  // 0 on the first batch (m = -inf)
+        z *= sc;
+        zd *= sc;
+#pragma unroll
+        for (int j = 0; j < kArgBatch; ++j) {
+            if (d0 + j < g.D) {
+                const float e = expf(v[j] - mb);
+                z += e;
+                zd += (float)(d0 + j) * e;
+            }
+        }
+        m = mb;
     }
     dhat[(size_t)b * P + i] = zd / z;
     lse[(size_t)b * P + i] = m + logf(z);
