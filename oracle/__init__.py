@@ -22,7 +22,7 @@ _SO = os.path.join(_HERE, "libdco_oracle.so")
 _lib = None
 
 DEFAULTS = dict(cw=9, ch=7, L1=17, tau1=20, gamma=1.0, eps=0.8, lam_ad=10.0, lam_c=40.0,
-                iters=2, maxdiff=0, subpixel=1)
+                iters=2, maxdiff=0, subpixel=1, vote_iters=0)
 
 
 def build(force: bool = True) -> str:
@@ -52,7 +52,9 @@ def lib():
             "orc_aggregate": [P, P, i, i, i, i, P],
             "orc_wta": [P, i, i, i, P, P],
             "orc_lrcheck": [P, P, P, i, i, i, i, P, P],
-            "orc_match": [P, P, i, i, i, i, i, i, i, f, f, f, f, i, i, i, P, P, P, P],
+            "orc_match": [P, P, i, i, i, i, i, i, i, f, f, f, f, i, i, i, i, P, P, P, P],
+            "orc_vote": [P, P, P, i, i, i, i, P],
+            "orc_vote_finish": [P, P, i, i, i, i, P, P],
             "orc_soft_forward": [P, P, P, P, P, i, i, i, dbl, dbl, dbl, dbl, dbl, P, P],
             "orc_soft_grad": [P, P, P, P, P, i, i, i, dbl, dbl, dbl, dbl, dbl, P, P],
         }
@@ -149,8 +151,10 @@ def lrcheck(dL, deltaL, dR, maxdiff=0, subpixel=1):
 
 
 def match(L, R, D, cw=9, ch=7, L1=17, tau1=20, gamma=1.0, eps=0.8, lam_ad=10.0, lam_c=40.0,
-          iters=2, maxdiff=0, subpixel=1):
-    """Full plain matcher: returns (disp, valid, dL, dR)."""
+          iters=2, maxdiff=0, subpixel=1, vote_iters=0):
+    """Full plain matcher: returns (disp, valid, dL, dR).  With vote_iters > 0
+    the LR-valid left disparities go through the Eq. 4 vote (dL stays the
+    WTA map)."""
     L = _c(L, np.uint8)
     R = _c(R, np.uint8)
     H, W = L.shape[:2]
@@ -159,8 +163,30 @@ def match(L, R, D, cw=9, ch=7, L1=17, tau1=20, gamma=1.0, eps=0.8, lam_ad=10.0, 
     dL = np.empty((H, W), np.int16)
     dR = np.empty((H, W), np.int16)
     lib().orc_match(_p(L), _p(R), W, H, D, cw, ch, L1, tau1, gamma, eps, lam_ad, lam_c, iters,
-                    maxdiff, subpixel, _p(disp), _p(valid), _p(dL), _p(dR))
+                    maxdiff, subpixel, vote_iters, _p(disp), _p(valid), _p(dL), _p(dR))
     return disp, valid, dL, dR
+
+
+def vote(d, valid, arms, D, iters):
+    """Eq. 4 region vote: returns the H x W int16 map (-1 where invalid)."""
+    d = _c(d, np.int16)
+    valid = _c(valid, np.uint8)
+    arms = _c(arms, np.uint8)
+    H, W = d.shape
+    out = np.empty((H, W), np.int16)
+    lib().orc_vote(_p(d), _p(valid), _p(arms), W, H, D, iters, _p(out))
+    return out
+
+
+def vote_finish(agg, dv, subpixel=1):
+    """Disparity output of a voted map: (disp, valid)."""
+    agg = _c(agg, np.float32)
+    dv = _c(dv, np.int16)
+    D, H, W = agg.shape
+    disp = np.empty((H, W), np.float32)
+    valid = np.empty((H, W), np.uint8)
+    lib().orc_vote_finish(_p(agg), _p(dv), W, H, D, subpixel, _p(disp), _p(valid))
+    return disp, valid
 
 
 def stages(L, R, D, cw=9, ch=7, L1=17, tau1=20, gamma=1.0, eps=0.8, lam_ad=10.0, lam_c=40.0,

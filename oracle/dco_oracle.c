@@ -223,6 +223,24 @@ void orc_aggregate(const int32_t* q, const uint8_t* arms, int W, int H, int D, i
  * costs m = A(d*-1), c = A(d*), p = A(d*+1):
  *   num = m - p;  den = (m - c) + (p - c);  delta = num / (2 den)
  * clamped to [-0.5, 0.5]; delta = 0 when d* is 0 or D-1 or den <= 0. */
+static float parabola_at(const float* agg, size_t P, size_t i, int D, int d) {
+    float del = 0.0f;
+    if (d > 0 && d < D - 1) {
+        float m = agg[(size_t)(d - 1) * P + i];
+        float c = agg[(size_t)d * P + i];
+        float p = agg[(size_t)(d + 1) * P + i];
+        float num = m - p;
+        float den = (m - c) + (p - c);
+        if (den > 0.0f) {
+            float two_den = 2.0f * den;
+            del = num / two_den;
+            if (del > 0.5f) del = 0.5f;
+            if (del < -0.5f) del = -0.5f;
+        }
+    }
+    return del;
+}
+
 void orc_wta(const float* agg, int W, int H, int D, int16_t* dint, float* delta) {
     size_t P = (size_t)W * H;
     for (size_t i = 0; i < P; ++i) {
@@ -233,22 +251,8 @@ void orc_wta(const float* agg, int W, int H, int D, int16_t* dint, float* delta)
                 bv = agg[(size_t)d * P + i];
                 best = d;
             }
-        float del = 0.0f;
-        if (best > 0 && best < D - 1) {
-            float m = agg[(size_t)(best - 1) * P + i];
-            float c = bv;
-            float p = agg[(size_t)(best + 1) * P + i];
-            float num = m - p;
-            float den = (m - c) + (p - c);
-            if (den > 0.0f) {
-                float two_den = 2.0f * den;
-                del = num / two_den;
-                if (del > 0.5f) del = 0.5f;
-                if (del < -0.5f) del = -0.5f;
-            }
-        }
         dint[i] = (int16_t)best;
-        delta[i] = del;
+        delta[i] = parabola_at(agg, P, i, D, best);
     }
 }
 
@@ -270,12 +274,78 @@ void orc_lrcheck(const int16_t* dL, const float* deltaL, const int16_t* dR, int 
         }
 }
 
+/* Disparity refinement by region vote, Eq. 4 (Sec. 4.3).
+ * READING (region): N_p is p's stage-1 cross region: for each y' in
+ *   [y - u(p), y + dn(p)], the pixels x' in [x - l(x, y'), x + r(x, y')].
+ * READING (votes): only valid pixels vote, each with its integer disparity;
+ *   a value outside [0, D) counts as invalid.  An invalid pixel is not
+ *   changed and stays invalid (-1 in the output).
+ * READING (choice): the disparity with the most votes in N_p; among equal
+ *   counts the smallest.  A valid p lies in its own region and votes, so it
+ *   always has a winner.
+ * READING (iterations): `iters` passes; each pass reads only the previous
+ *   pass's map, so every pixel of a pass sees the same input.
+ * din: H x W int16; valid: H x W uint8; arms: H x W x 4; dout: H x W int16. */
+void orc_vote(const int16_t* din, const uint8_t* valid, const uint8_t* arms, int W, int H, int D,
+              int iters, int16_t* dout) {
+    size_t P = (size_t)W * H;
+    int16_t* cur = (int16_t*)malloc(2 * P);
+    int16_t* nxt = (int16_t*)malloc(2 * P);
+    int* hist = (int*)malloc(sizeof(int) * (size_t)D);
+#define ARM(x, y, k) ((int)arms[4 * ((size_t)(y) * W + (x)) + (k)])
+    for (size_t i = 0; i < P; ++i)
+        cur[i] = (int16_t)(valid[i] && din[i] >= 0 && din[i] < D ? din[i] : -1);
+    for (int it = 0; it < iters; ++it) {
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                size_t i = (size_t)y * W + x;
+                if (cur[i] < 0) {
+                    nxt[i] = -1;
+                    continue;
+                }
+                memset(hist, 0, sizeof(int) * (size_t)D);
+                for (int yy = y - ARM(x, y, 2); yy <= y + ARM(x, y, 3); ++yy)
+                    for (int xx = x - ARM(x, yy, 0); xx <= x + ARM(x, yy, 1); ++xx) {
+                        int v = cur[(size_t)yy * W + xx];
+                        if (v >= 0) hist[v]++;
+                    }
+                int best = 0;
+                for (int d = 1; d < D; ++d)
+                    if (hist[d] > hist[best]) best = d;
+                nxt[i] = (int16_t)best;
+            }
+        int16_t* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+#undef ARM
+    memcpy(dout, cur, 2 * P);
+    free(cur);
+    free(nxt);
+    free(hist);
+}
+
+/* Output of the voted map: where dv >= 0, disp = dv plus the parabola offset
+ * at dv from the aggregated costs (the sub-pixel READING of orc_wta; 0 when
+ * subpixel = 0) and valid = 1; elsewhere disp = 0 and valid = 0. */
+void orc_vote_finish(const float* agg, const int16_t* dv, int W, int H, int D, int subpixel,
+                     float* disp, uint8_t* valid) {
+    size_t P = (size_t)W * H;
+    for (size_t i = 0; i < P; ++i) {
+        int ok = dv[i] >= 0;
+        valid[i] = (uint8_t)ok;
+        disp[i] = ok ? (float)dv[i] + (subpixel ? parabola_at(agg, P, i, D, dv[i]) : 0.0f) : 0.0f;
+    }
+}
+
 /* The whole plain matcher: grey, census and arms of both views, the cost and
- * aggregated volumes of both views, WTA of both, LR check. */
+ * aggregated volumes of both views, WTA of both, LR check, and, when
+ * vote_iters > 0, the Eq. 4 vote on the LR-valid left disparities with the
+ * sub-pixel offset taken again at the voted disparity. */
 void orc_match(const uint8_t* rgbL, const uint8_t* rgbR, int W, int H, int D, int cw, int ch,
                int L1, int tau1, float gamma, float eps, float lam_ad, float lam_c, int iters,
-               int maxdiff, int subpixel, float* disp, uint8_t* valid, int16_t* dL_out,
-               int16_t* dR_out) {
+               int maxdiff, int subpixel, int vote_iters, float* disp, uint8_t* valid,
+               int16_t* dL_out, int16_t* dR_out) {
     size_t P = (size_t)W * H, V = P * D;
     uint8_t* Y = (uint8_t*)malloc(P);
     uint64_t* cL = (uint64_t*)malloc(8 * P);
@@ -297,10 +367,22 @@ void orc_match(const uint8_t* rgbL, const uint8_t* rgbR, int W, int H, int D, in
     orc_cost(0, rgbL, rgbR, cL, cR, aL, W, H, D, L1, gamma, eps, lam_ad, lam_c, q);
     orc_aggregate(q, aL, W, H, D, iters, agg);
     orc_wta(agg, W, H, D, dL, delL);
+    float* aggL = NULL;
+    if (vote_iters > 0) {  /* the vote's sub-pixel step needs the left costs */
+        aggL = (float*)malloc(4 * V);
+        memcpy(aggL, agg, 4 * V);
+    }
     orc_cost(1, rgbL, rgbR, cL, cR, aR, W, H, D, L1, gamma, eps, lam_ad, lam_c, q);
     orc_aggregate(q, aR, W, H, D, iters, agg);
     orc_wta(agg, W, H, D, dR, delR);
     orc_lrcheck(dL, delL, dR, W, H, maxdiff, subpixel, disp, valid);
+    if (vote_iters > 0) {
+        int16_t* dv = (int16_t*)malloc(2 * P);
+        orc_vote(dL, valid, aL, W, H, D, vote_iters, dv);
+        orc_vote_finish(aggL, dv, W, H, D, subpixel, disp, valid);
+        free(dv);
+        free(aggL);
+    }
     if (dL_out) memcpy(dL_out, dL, 2 * P);
     if (dR_out) memcpy(dR_out, dR, 2 * P);
     free(Y); free(cL); free(cR); free(aL); free(aR); free(q); free(agg);
