@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 # 4 cycles (16 lanes per cycle each): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 METRIC = "Mpix·disp/s and ms/frame at 1280x720 D=128 vs oracle; batched & fwd+bwd vs plain"
-STAGES = ("census+arms+counts", "cost+aggregate L+R", "wta", "lrcheck")
+STAGES = ("census+arms+counts", "cost+aggregate L+R", "wta", "lrcheck", "vote")
 
 
 TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
@@ -84,8 +84,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=540)
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="staged,batched,soft",
-                    help="comma list of the extra measurements to run (staged, batched, soft)")
+    ap.add_argument("--extras", default="staged,vote,batched,soft",
+                    help="comma list of the extra measurements to run "
+                         "(staged, vote, batched, soft)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of MiB mebibytes (counter calibration)")
     args = ap.parse_args()
@@ -158,6 +159,9 @@ def main():
     extras = {"stage_ms": {n: round(t, 4) for n, t in zip(STAGES, per_call)}}
     if "staged" in want:
         extras["staged"] = staged_extras(m, gL, gR, args.steps)
+    if "vote" in want:
+        log("bench: one-call match with two Eq. 4 vote passes")
+        extras["vote"] = vote_extras(gL, gR, disp, valid, args.steps)
     del m
     torch.cuda.empty_cache()
     if "batched" in want:
@@ -268,6 +272,33 @@ def soft_extras(n):
                 Mpix_disp_s=round(units / (ms_fb / 1e3) / 1e6, 1),
                 plain_ms=round(ms_plain, 3), ratio_to_plain=round(ms_fb / ms_plain, 3),
                 loss=round(loss, 4), grad_theta=[round(g, 6) for g in grad])
+
+
+def vote_extras(gL, gR, disp0, valid0, steps):
+    """The one-call match with two passes of the Eq. 4 region vote on the
+    same pair: ms per frame, the vote stage's HIP-event time, and how many
+    valid pixels the vote changed."""
+    import torch
+    from paper_2203_02300_amd import StereoMatcher
+    from paper_2203_02300_amd._lib import check, lib
+    H, W = gL.shape[:2]
+    m = StereoMatcher(W, H, 128, vote_iters=2)
+    disp = torch.empty_like(disp0)
+    valid = torch.empty_like(valid0)
+    ms = _time(lambda: m.match(gL, gR, disp, valid), steps)
+    check(lib().dco_stereo_profile(m._h, 1))
+    for _ in range(steps):
+        m.match(gL, gR, disp, valid)
+    torch.cuda.synchronize()
+    check(lib().dco_stereo_profile(m._h, 0))
+    st = (C.c_float * len(STAGES))()
+    calls = C.c_int()
+    check(lib().dco_stereo_stage_times(m._h, st, len(STAGES), C.byref(calls)))
+    m.close()
+    changed = int(((disp != disp0) & (valid == 1)).sum())
+    return dict(passes=2, ms_per_frame=round(ms, 4), vote_stage_ms=round(st[4] / calls.value, 4),
+                Mpix_disp_s=round(W * H * 128 / (ms / 1e3) / 1e6, 1),
+                valid_pixels=int(valid.sum()), changed_pixels=changed)
 
 
 def staged_extras(m, gL, gR, steps):

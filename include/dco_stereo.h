@@ -64,6 +64,9 @@ typedef struct {
     int agg_iters;            /* 2 = two-stage aggregation; 1 = Eq. 2 once */
     int lr_max_diff;          /* >= 0: LR tolerance in whole disparities */
     int subpixel;             /* 1 = parabola refinement, 0 = integer output */
+    int vote_iters;           /* 0 <= n <= 64: passes of the Eq. 4 region vote that
+                                 dco_stereo_match applies after the LR check
+                                 (default 0 = none); n > 0 needs D <= 448 */
 } dco_params;
 
 /* Fill *out with the defaults above.  DCO_ERR_ARG if out is NULL. */
@@ -143,6 +146,27 @@ dco_status dco_wta_lrcheck(dco_stereo* h, const float* aggL, const float* aggR, 
 dco_status dco_stereo_match(dco_stereo* h, const uint8_t* rgbL, const uint8_t* rgbR, float* disp,
                             uint8_t* valid);
 
+/* Disparity refinement by region vote (Eq. 4, Sec. 4.3), `iters` passes.
+ * In each pass every valid pixel p takes the disparity with the most votes
+ * in its stage-1 cross region N_p: for each y' in [y - u(p), y + dn(p)] the
+ * pixels x' in [x - l(x, y'), x + r(x, y')].  Only valid pixels vote, with
+ * their integer disparity; equal counts go to the smallest disparity; a
+ * pass reads only the previous pass's map.  Then, where the voted map dv is
+ * valid: disp = dv + the parabola offset of dco_wta_lrcheck taken at dv on
+ * aggL (0 if subpixel = 0), valid_out = 1; elsewhere disp = 0, valid_out = 0.
+ * A pixel with valid = 0 or dL outside [0, D) is invalid and stays so.
+ * dco_stereo_match with vote_iters = n gives the same result as
+ * dco_wta_lrcheck followed by this call with iters = n.
+ * armsL: H x W x 4 uint8 left arms as from dco_census (4-byte aligned; arms
+ * are clipped to 17); aggL: D x H x W float; dL: H x W int16; valid: H x W
+ * uint8; disp: H x W float (out); valid_out: H x W uint8 (out, may alias
+ * valid); dvote: H x W int16 (out, optional: the voted map, -1 where
+ * invalid).  Needs 0 <= iters <= 64 and D <= 448 (one 16-bit counter per
+ * disparity per pixel of a tile in LDS). */
+dco_status dco_vote_refine(dco_stereo* h, const uint8_t* armsL, const float* aggL,
+                           const int16_t* dL, const uint8_t* valid, int iters, float* disp,
+                           uint8_t* valid_out, int16_t* dvote);
+
 /* Integer disparities of both views from the last dco_stereo_match on this
  * handle (H x W int16 each, device, out; either may be NULL). */
 dco_status dco_stereo_last_disparities(dco_stereo* h, int16_t* dL, int16_t* dR);
@@ -155,8 +179,9 @@ dco_status dco_stereo_last_disparities(dco_stereo* h, int16_t* dL, int16_t* dR);
  * stage s < n, ms[s] = total milliseconds over the recorded calls, and
  * *calls = the number of recorded calls.  Stages: 0 census + arms + region
  * counts of both views, 1 cost + aggregation of both views (one launch),
- * 2 WTA of both views, 3 LR check.  ms: host array of n floats. */
-#define DCO_NUM_STAGES 4
+ * 2 WTA of both views, 3 LR check, 4 Eq. 4 vote and its sub-pixel output
+ * (0 ms when vote_iters = 0).  ms: host array of n floats. */
+#define DCO_NUM_STAGES 5
 dco_status dco_stereo_profile(dco_stereo* h, int enable);
 dco_status dco_stereo_stage_times(dco_stereo* h, float* ms, int n, int* calls);
 

@@ -17,8 +17,8 @@ EXPORTS = (
     "dco_census", "dco_cost_volume", "dco_aggregate", "dco_wta_lrcheck", "dco_stereo_match",
     "dco_stereo_last_disparities", "dco_stereo_profile", "dco_stereo_stage_times",
     "dco_batch_create", "dco_batch_destroy", "dco_batch_match",
-    "dco_batch_tile", "dco_soft_forward", "dco_soft_backward", "dco_status_string",
-    "dco_last_error",
+    "dco_batch_tile", "dco_soft_forward", "dco_soft_backward", "dco_vote_refine",
+    "dco_status_string", "dco_last_error",
 )
 
 DCO_OK = 0
@@ -39,6 +39,7 @@ class Params(C.Structure):
         ("lambda_ad", C.c_float), ("lambda_census", C.c_float),
         ("gamma_L", C.c_float), ("eps", C.c_float),
         ("agg_iters", C.c_int), ("lr_max_diff", C.c_int), ("subpixel", C.c_int),
+        ("vote_iters", C.c_int),
     ]
 
 
@@ -74,6 +75,7 @@ def lib():
         "dco_batch_tile": (st, [P, i, P, P, P]),
         "dco_soft_forward": (st, [P, i, P, P, P, P, P]),
         "dco_soft_backward": (st, [P, i, P, P, P, P, P, P, P]),
+        "dco_vote_refine": (st, [P, P, P, P, P, i, P, P, P]),
         "dco_status_string": (C.c_char_p, [st]),
         "dco_last_error": (C.c_char_p, []),
     }

@@ -141,6 +141,20 @@ class StereoMatcher:
         check(lib().dco_stereo_match(self._h, _ptr(L), _ptr(R), _ptr(disp), _ptr(valid)))
         return disp, valid
 
+    def vote_refine(self, armsL, aggL, dL, valid, iters):
+        """Eq. 4 region vote on the left integer map: returns (disp, valid, dvote)."""
+        _need(armsL, "armsL", torch.uint8, (self.H, self.W, 4))
+        _need(aggL, "aggL", torch.float32, (self.D, self.H, self.W))
+        _need(dL, "dL", torch.int16, (self.H, self.W))
+        _need(valid, "valid", torch.uint8, (self.H, self.W))
+        self._begin()
+        disp = self._empty((self.H, self.W), torch.float32)
+        vout = self._empty((self.H, self.W), torch.uint8)
+        dvote = self._empty((self.H, self.W), torch.int16)
+        check(lib().dco_vote_refine(self._h, _ptr(armsL), _ptr(aggL), _ptr(dL), _ptr(valid),
+                                    int(iters), _ptr(disp), _ptr(vout), _ptr(dvote)))
+        return disp, vout, dvote
+
     def last_disparities(self):
         """Integer (dL, dR) of the last ``match`` call."""
         self._begin()

@@ -50,6 +50,7 @@ extern "C" dco_status dco_default_params(dco_params* out) {
     out->agg_iters = 2;
     out->lr_max_diff = 0;
     out->subpixel = 1;
+    out->vote_iters = 0;
     return DCO_OK;
 }
 
@@ -81,6 +82,10 @@ dco_status check_params(const dco_params& p) {
         dco_set_error("lr_max_diff must be >= 0 and subpixel 0 or 1");
         return DCO_ERR_ARG;
     }
+    if (p.vote_iters < 0 || p.vote_iters > kVoteMaxIters) {
+        dco_set_error("vote_iters must be in [0, %d] (got %d)", kVoteMaxIters, p.vote_iters);
+        return DCO_ERR_ARG;
+    }
     return DCO_OK;
 }
 
@@ -90,6 +95,10 @@ dco_status check_shape(int W, int H, int D, const dco_params& p) {
         dco_set_error("shape W=%d H=%d D=%d: need 1 <= D < W, W >= census_w, H >= census_h, "
                       "W, H <= 16384 and W*H*D < 2^31",
                       W, H, D);
+        return DCO_ERR_SHAPE;
+    }
+    if (p.vote_iters > 0 && D > kVoteMaxD) {
+        dco_set_error("the Eq. 4 vote needs D <= %d (got %d)", kVoteMaxD, D);
         return DCO_ERR_SHAPE;
     }
     return DCO_OK;
@@ -121,7 +130,8 @@ static void free_handle_memory(dco_stereo* h) {
                     h->s.arms[1],    h->s.rec[0].b,   h->s.rec[0].c,
                     h->s.rec[1].b,   h->s.rec[1].c,
                     h->s.agg[0],     h->s.agg[1],     h->s.dint[0],
-                    h->s.dint[1],    h->s.delta,      h->soft.pix[0],  h->soft.pix[1],
+                    h->s.dint[1],    h->s.delta,      h->s.vote[0],    h->s.vote[1],
+                    h->soft.pix[0],  h->soft.pix[1],
                     h->soft.arms,    h->soft.arms_r,  h->soft.n1,      h->soft.n2,
                     h->soft.tab,     h->soft.vol[0],  h->soft.vol[1],  h->soft.vol[2],
                     h->soft.partAC,  h->soft.partT};
@@ -154,6 +164,8 @@ static dco_status alloc_scratch(dco_stereo* h) {
         DCO_TRY(dev_alloc(&s.dint[v], P));
     }
     DCO_TRY(dev_alloc(&s.delta, P));
+    DCO_TRY(dev_alloc(&s.vote[0], P));
+    DCO_TRY(dev_alloc(&s.vote[1], P));
     h->scratch_ready = true;
     return DCO_OK;
 }
@@ -401,6 +413,50 @@ extern "C" dco_status dco_stereo_match(dco_stereo* h, const uint8_t* rgbL, const
     DCO_HIP_CHECK(launch_lrcheck(s.dint[0], s.delta, s.dint[1], h->W, h->H, p.lr_max_diff, disp,
                                  valid, h->stream));
     DCO_TRY(prof_mark(h));
+    DCO_TRY(prof_mark(h));
+    if (p.vote_iters > 0) {
+        const int16_t* dv = nullptr;
+        DCO_HIP_CHECK(launch_vote(s.dint[0], valid, s.arms[0], h->W, h->H, h->D, p.vote_iters,
+                                  s.vote[0], s.vote[1], &dv, h->stream));
+        DCO_HIP_CHECK(launch_vote_finish(dv, nullptr, s.agg[0], h->W, h->H, h->D, p.subpixel, disp,
+                                         valid, nullptr, h->stream));
+    }
+    DCO_TRY(prof_mark(h));
+    return DCO_OK;
+}
+
+extern "C" dco_status dco_vote_refine(dco_stereo* h, const uint8_t* armsL, const float* aggL,
+                                      const int16_t* dL, const uint8_t* valid, int iters,
+                                      float* disp, uint8_t* valid_out, int16_t* dvote) {
+    DCO_TRY(need(h, "handle"));
+    DCO_TRY(need(armsL, "armsL"));
+    DCO_TRY(need(aggL, "aggL"));
+    DCO_TRY(need(dL, "dL"));
+    DCO_TRY(need(valid, "valid"));
+    DCO_TRY(need(disp, "disp"));
+    DCO_TRY(need(valid_out, "valid_out"));
+    DCO_TRY(need_align(armsL, 4, "armsL"));
+    if (iters < 0 || iters > kVoteMaxIters) {
+        dco_set_error("iters must be in [0, %d] (got %d)", kVoteMaxIters, iters);
+        return DCO_ERR_ARG;
+    }
+    if (iters > 0 && h->D > kVoteMaxD) {
+        dco_set_error("the Eq. 4 vote needs D <= %d (got %d)", kVoteMaxD, h->D);
+        return DCO_ERR_SHAPE;
+    }
+    if (!h->scratch_ready) {
+        dco_set_error("handle has no scratch");
+        return DCO_ERR_STATE;
+    }
+    const int16_t* dv = dL;
+    const uint8_t* mask = valid;
+    if (iters > 0) {
+        DCO_HIP_CHECK(launch_vote(dL, valid, reinterpret_cast<const uint32_t*>(armsL), h->W, h->H,
+                                  h->D, iters, h->s.vote[0], h->s.vote[1], &dv, h->stream));
+        mask = nullptr;
+    }
+    DCO_HIP_CHECK(launch_vote_finish(dv, mask, aggL, h->W, h->H, h->D, h->p.subpixel, disp,
+                                     valid_out, dvote, h->stream));
     return DCO_OK;
 }
 

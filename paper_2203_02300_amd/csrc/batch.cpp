@@ -404,6 +404,11 @@ extern "C" dco_status dco_batch_create(dco_batch** out, int n, const int* W, con
     else
         dco_default_params(&prm);
     DCO_TRY(check_params(prm));
+    if (prm.vote_iters != 0) {
+        dco_set_error("dco_batch_create: the batched matcher has no Eq. 4 vote (vote_iters must "
+                      "be 0; use dco_vote_refine per pair)");
+        return DCO_ERR_ARG;
+    }
     for (int i = 0; i < n; ++i) DCO_TRY(check_shape(W[i], H[i], D[i], prm));
     hipStream_t st = (hipStream_t)stream;
     // tile choice per size class: cache, else measure

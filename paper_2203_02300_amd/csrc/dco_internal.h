@@ -14,6 +14,8 @@
 // Largest arm length the kernels are built for.  The aggregation halo is
 // 2 * kLMax columns/rows on each side of an output pixel.
 constexpr int kLMax = 17;
+constexpr int kVoteMaxD = 448;     // Eq. 4 vote: 16-bit counters of D bins x 64 pixels in LDS
+constexpr int kVoteMaxIters = 64;
 // Threads of a streaming-aggregation workgroup = input columns of a strip.
 constexpr int kStripThreads = 256;
 // Output columns of one strip.
@@ -48,6 +50,7 @@ struct dco_scratch {
     float* agg[2];      // aggregated volumes of both views (D x H x W)
     int16_t* dint[2];
     float* delta;
+    int16_t* vote[2];   // ping-pong maps of the Eq. 4 vote passes
 };
 
 // Soft-path scratch of a handle: per-pair maps of B pairs and three
@@ -154,6 +157,18 @@ dco_status alloc_records(AggRecords* r, int W, int H);
 hipError_t launch_census_arms(const uint8_t* rgb, int W, int H, int cw, int ch, int L1, int tau1,
                               uint64_t* census, uint32_t* arms, uint32_t* rgb_packed, uint4* pix,
                               hipStream_t st);
+// Eq. 4 vote: `iters` passes (>= 1) over the left integer map dL (pixels
+// with valid = 0 or a value outside [0, D) do not vote), ping-ponging between
+// buf0 and buf1 (H x W int16 each); *result points at the final map (-1 where
+// invalid).  Then the output step: disp / valid from a voted map (valid_in
+// null) or from dL and its mask (no pass).
+size_t vote_lds_bytes(int D);
+hipError_t launch_vote(const int16_t* dL, const uint8_t* valid, const uint32_t* arms, int W, int H,
+                       int D, int iters, int16_t* buf0, int16_t* buf1, const int16_t** result,
+                       hipStream_t st);
+hipError_t launch_vote_finish(const int16_t* dv, const uint8_t* valid_in, const float* agg, int W,
+                              int H, int D, int subpixel, float* disp, uint8_t* valid,
+                              int16_t* dv_out, hipStream_t st);
 // Arms and packed pixels of both views of B pairs (HWC images of 3 W H
 // bytes each, outputs of W H entries each, pair-major) in one launch.
 hipError_t launch_census_pairs(const uint8_t* rgbL, const uint8_t* rgbR, int B, int W, int H,

@@ -44,6 +44,7 @@ def test_default_params(L):
     assert (p.census_w, p.census_h, p.arm_L1, p.arm_tau1) == (9, 7, 17, 20)
     assert (p.lambda_ad, p.lambda_census, p.gamma_L) == (10.0, 40.0, 1.0)
     assert abs(p.eps - 0.8) < 1e-7 and p.agg_iters == 2 and p.subpixel == 1
+    assert p.vote_iters == 0
     assert L.dco_default_params(None) == -1
 
 
@@ -69,7 +70,8 @@ def test_bad_shapes_rejected(L, W, H, D):
                                 dict(arm_L1=18), dict(arm_L1=-1), dict(arm_tau1=0),
                                 dict(lambda_ad=0.0), dict(lambda_census=-1.0),
                                 dict(eps=float("nan")), dict(agg_iters=3),
-                                dict(lr_max_diff=-1), dict(subpixel=2)])
+                                dict(lr_max_diff=-1), dict(subpixel=2), dict(vote_iters=-1),
+                                dict(vote_iters=65)])
 def test_bad_params_rejected(L, kw):
     st, h = create(L, 64, 48, 16, **kw)
     assert st == -1 and not h.value
@@ -82,8 +84,15 @@ def test_null_arguments_rejected(L):
     assert L.dco_aggregate(None, None, None, None) == -1
     assert L.dco_wta_lrcheck(None, None, None, None, None, None, None) == -1
     assert L.dco_stereo_match(None, None, None, None, None) == -1
+    assert L.dco_vote_refine(None, None, None, None, None, 1, None, None, None) == -1
     assert L.dco_stereo_set_stream(None, None) == -1
     L.dco_stereo_destroy(None)
+
+
+def test_vote_needs_a_bounded_disparity_range(L):
+    # the vote's per-pixel counters live in LDS: D <= 448 when it is on
+    st, h = create(L, 640, 48, 449, vote_iters=2)
+    assert st == -2 and not h.value and b"vote" in L.dco_last_error()
 
 
 def test_status_strings(L):
