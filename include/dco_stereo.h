@@ -66,7 +66,7 @@ typedef struct {
     int subpixel;             /* 1 = parabola refinement, 0 = integer output */
     int vote_iters;           /* 0 <= n <= 64: passes of the Eq. 4 region vote that
                                  dco_stereo_match applies after the LR check
-                                 (default 0 = none); n > 0 needs D <= 448 */
+                                 (default 0 = none) */
 } dco_params;
 
 /* Fill *out with the defaults above.  DCO_ERR_ARG if out is NULL. */
@@ -161,8 +161,7 @@ dco_status dco_stereo_match(dco_stereo* h, const uint8_t* rgbL, const uint8_t* r
  * are clipped to 17); aggL: D x H x W float; dL: H x W int16; valid: H x W
  * uint8; disp: H x W float (out); valid_out: H x W uint8 (out, may alias
  * valid); dvote: H x W int16 (out, optional: the voted map, -1 where
- * invalid).  Needs 0 <= iters <= 64 and D <= 448 (one 16-bit counter per
- * disparity per pixel of a tile in LDS). */
+ * invalid).  Needs 0 <= iters <= 64. */
 dco_status dco_vote_refine(dco_stereo* h, const uint8_t* armsL, const float* aggL,
                            const int16_t* dL, const uint8_t* valid, int iters, float* disp,
                            uint8_t* valid_out, int16_t* dvote);

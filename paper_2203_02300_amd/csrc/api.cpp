@@ -97,10 +97,6 @@ dco_status check_shape(int W, int H, int D, const dco_params& p) {
                       W, H, D);
         return DCO_ERR_SHAPE;
     }
-    if (p.vote_iters > 0 && D > kVoteMaxD) {
-        dco_set_error("the Eq. 4 vote needs D <= %d (got %d)", kVoteMaxD, D);
-        return DCO_ERR_SHAPE;
-    }
     return DCO_OK;
 }
 
@@ -439,10 +435,6 @@ extern "C" dco_status dco_vote_refine(dco_stereo* h, const uint8_t* armsL, const
     if (iters < 0 || iters > kVoteMaxIters) {
         dco_set_error("iters must be in [0, %d] (got %d)", kVoteMaxIters, iters);
         return DCO_ERR_ARG;
-    }
-    if (iters > 0 && h->D > kVoteMaxD) {
-        dco_set_error("the Eq. 4 vote needs D <= %d (got %d)", kVoteMaxD, h->D);
-        return DCO_ERR_SHAPE;
     }
     if (!h->scratch_ready) {
         dco_set_error("handle has no scratch");

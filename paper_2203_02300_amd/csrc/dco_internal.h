@@ -14,7 +14,6 @@
 // Largest arm length the kernels are built for.  The aggregation halo is
 // 2 * kLMax columns/rows on each side of an output pixel.
 constexpr int kLMax = 17;
-constexpr int kVoteMaxD = 448;     // Eq. 4 vote: 16-bit counters of D bins x 64 pixels in LDS
 constexpr int kVoteMaxIters = 64;
 // Threads of a streaming-aggregation workgroup = input columns of a strip.
 constexpr int kStripThreads = 256;
@@ -162,7 +161,6 @@ hipError_t launch_census_arms(const uint8_t* rgb, int W, int H, int cw, int ch, 
 // buf0 and buf1 (H x W int16 each); *result points at the final map (-1 where
 // invalid).  Then the output step: disp / valid from a voted map (valid_in
 // null) or from dL and its mask (no pass).
-size_t vote_lds_bytes(int D);
 hipError_t launch_vote(const int16_t* dL, const uint8_t* valid, const uint32_t* arms, int W, int H,
                        int D, int iters, int16_t* buf0, int16_t* buf1, const int16_t** result,
                        hipStream_t st);

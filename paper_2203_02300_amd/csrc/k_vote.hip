@@ -8,12 +8,17 @@
 //
 // Layout: one wavefront per 8 x 8 pixel tile.  The tile's votes plus a kLMax
 // apron on every side (42 x 42 int16) and the horizontal arms of the tile
-// columns over the apron rows go to LDS; every lane then counts its own
-// region into its own D counters (16-bit, lane-interleaved so that the 64
-// lanes' counters of one disparity are 128 contiguous bytes: no bank
-// conflicts whatever the disparities).  Runs of equal votes along a segment
-// are added as one count.  All counts are integers, so the result does not
-// depend on the order of the additions.
+// columns over the apron rows go to LDS, and each staged row is run-length
+// coded once (runs of equal votes: start column, value, and the run of each
+// column).  Every lane then counts its own region into its own counters: a
+// segment adds, for each run it meets, the overlap length to the run's
+// value.  Counters cover a window of kVBins disparities at a time (16-bit,
+// lane-interleaved so that the 64 lanes' counters of one disparity are 128
+// contiguous bytes: no bank conflicts whatever the disparities); the windows
+// step from the smallest to the largest vote staged for the tile, and the
+// running maximum keeps the smallest disparity among equal counts.  All
+// counts are integers, so the result does not depend on the order of the
+// additions.
 #include "dco_device.h"
 
 namespace {
@@ -22,10 +27,26 @@ constexpr int kVT = 8;                // tile side
 constexpr int kVR = kVT + 2 * kLMax;  // staged side
 constexpr int kVStride = kVR + 2;
 
+constexpr int kVBins = 64;  // disparities per counter window
+constexpr int kVStage = (kVR * kVR + 63) / 64;
+
 struct VoteLds {
-    int16_t d[kVR][kVStride];      // votes of the staged region (-1: none)
-    uint8_t l[kVR][kVT], r[kVR][kVT];  // horizontal arms of the tile columns
+    __align__(16) uint16_t hist[kVBins * 64];  // counters of one window, [bin][lane]
+    int16_t d[kVR][kVStride];                  // votes of the staged region (-1: none)
+    int16_t rv[kVR][kVR];                      // value of run k of each staged row
+    uint8_t rs[kVR][kVR + 2];                  // run of each column
+    uint8_t st[kVR][kVR + 2];                  // start column of run k; st[nruns] = kVR
+    uint8_t l[kVR][kVT], r[kVR][kVT];          // horizontal arms of the tile columns
 };
+
+__device__ inline int wave_min(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline int wave_max(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
 
 // din: H x W int16; valid (first pass only, else null): H x W uint8; a vote
 // outside [0, D) counts as invalid.  dout: H x W int16, -1 where invalid.
@@ -33,65 +54,98 @@ __global__ __launch_bounds__(64) void k_vote(const int16_t* __restrict__ din,
                                              const uint8_t* __restrict__ valid,
                                              const uint32_t* __restrict__ arms, int W, int H,
                                              int D, int16_t* __restrict__ dout) {
-    __shared__ VoteLds S;
-    extern __shared__ __align__(16) uint16_t hist[];  // [D][64]
+    __shared__ __align__(16) VoteLds S;
     const int lane = threadIdx.x, tx = lane & (kVT - 1), ty = lane / kVT;
     const int x0 = blockIdx.x * kVT, y0 = blockIdx.y * kVT;
-    for (int i = lane; i < kVR * kVR; i += 64) {
-        const int ry = i / kVR, rx = i - ry * kVR;
-        const int x = x0 - kLMax + rx, y = y0 - kLMax + ry;
-        int v = -1;
-        if (x >= 0 && x < W && y >= 0 && y < H) {
-            const size_t q = (size_t)y * W + x;
-            const int dv = din[q];
-            if ((valid == nullptr || valid[q]) && dv >= 0 && dv < D) v = dv;
+    int vlo, vhi;
+    {   // stage the votes: every load issued before any is used (clamped addresses)
+        int dv[kVStage];
+        bool ok[kVStage];
+#pragma unroll
+        for (int t = 0; t < kVStage; ++t) {
+            const int i = min(lane + 64 * t, kVR * kVR - 1);
+            const int ry = i / kVR, rx = i - ry * kVR;
+            const int x = x0 - kLMax + rx, y = y0 - kLMax + ry;
+            ok[t] = x >= 0 && x < W && y >= 0 && y < H;
+            const size_t q = (size_t)min(max(y, 0), H - 1) * W + min(max(x, 0), W - 1);
+            dv[t] = din[q];
+            if (valid) ok[t] = ok[t] && valid[q] != 0;
         }
-        S.d[ry][rx] = (int16_t)v;
+        int lo = D, hi = -1;
+#pragma unroll
+        for (int t = 0; t < kVStage; ++t) {
+            const int i = lane + 64 * t;
+            const int v = ok[t] && dv[t] >= 0 && dv[t] < D ? dv[t] : -1;
+            if (i < kVR * kVR) {
+                const int ry = i / kVR;
+                S.d[ry][i - ry * kVR] = (int16_t)v;
+                if (v >= 0) {
+                    lo = min(lo, v);
+                    hi = max(hi, v);
+                }
+            }
+        }
+        vlo = __builtin_amdgcn_readfirstlane(wave_min(lo));  // the tile's vote range
+        vhi = __builtin_amdgcn_readfirstlane(wave_max(hi));  // (empty when vhi < vlo)
     }
     for (int i = lane; i < kVR * kVT; i += 64) {
         const int ry = i / kVT, cx = i - ry * kVT;
         const int x = x0 + cx, y = y0 - kLMax + ry;
         const uint32_t a = x < W && y >= 0 && y < H ? arms[(size_t)y * W + x] : 0u;
-        S.l[ry][cx] = (uint8_t)(a & 0xff);
-        S.r[ry][cx] = (uint8_t)((a >> 8) & 0xff);
+        S.l[ry][cx] = (uint8_t)min(a & 0xff, (uint32_t)kLMax);
+        S.r[ry][cx] = (uint8_t)min((a >> 8) & 0xff, (uint32_t)kLMax);
     }
-    for (int i = lane; i < D * 8; i += 64) reinterpret_cast<uint4*>(hist)[i] = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+    if (lane < kVR) {  // run-length code staged row `lane`
+        int n = 0, prev = 0;
+        for (int c = 0; c < kVR; ++c) {
+            const int v = S.d[lane][c];
+            if (c == 0 || v != prev) {
+                S.st[lane][n] = (uint8_t)c;
+                S.rv[lane][n] = (int16_t)v;
+                ++n;
+                prev = v;
+            }
+            S.rs[lane][c] = (uint8_t)(n - 1);
+        }
+        S.st[lane][n] = (uint8_t)kVR;
+    }
     __syncthreads();
 
     const int x = x0 + tx, y = y0 + ty;
     const bool in = x < W && y < H;
     const int mine = S.d[ty + kLMax][tx + kLMax];
     const uint32_t a = in ? arms[(size_t)y * W + x] : 0u;
-    const int u = (a >> 16) & 0xff, dn = a >> 24;
-    int cur = -1, run = 0;
-    for (int k = -kLMax; k <= kLMax; ++k) {
-        const bool rowin = mine >= 0 && k >= -u && k <= dn;
-        if (!__any(rowin)) continue;  // uniform
-        const int ry = ty + kLMax + k;
-        const int lo = rowin ? -(int)S.l[ry][tx] : 1, hi = rowin ? (int)S.r[ry][tx] : 0;
-        const int16_t* row = &S.d[ry][tx + kLMax];
-#pragma unroll
-        for (int j = -kLMax; j <= kLMax; ++j) {
-            const int v = row[j];
-            const bool take = j >= lo && j <= hi && v >= 0;
-            if (take && v != cur) {
-                if (run > 0) hist[cur * 64 + lane] += (uint16_t)run;
-                cur = v;
-                run = 0;
-            }
-            run += take ? 1 : 0;
-        }
-    }
-    if (run > 0) hist[cur * 64 + lane] += (uint16_t)run;
+    const int u = min((int)((a >> 16) & 0xff), kLMax), dn = min((int)(a >> 24), kLMax);
     int best = 0, bc = -1;
-    if (mine >= 0)
-        for (int d = 0; d < D; ++d) {
-            const int c = hist[d * 64 + lane];
-            if (c > bc) {
-                bc = c;
-                best = d;
+    for (int base = vlo; base <= vhi; base += kVBins) {  // uniform
+        for (int i = lane; i < kVBins * 64 / 8; i += 64)
+            reinterpret_cast<uint4*>(S.hist)[i] = make_uint4(0, 0, 0, 0);
+        __syncthreads();
+        if (mine >= 0) {
+            for (int k = -u; k <= dn; ++k) {
+                const int ry = ty + kLMax + k;
+                const int lo = tx + kLMax - S.l[ry][tx], hi = tx + kLMax + S.r[ry][tx];
+                const int k1 = S.rs[ry][hi];
+                for (int j = S.rs[ry][lo]; j <= k1; ++j) {
+                    const int b = S.rv[ry][j] - base;
+                    if (b >= 0 && b < kVBins) {
+                        const int s0 = max((int)S.st[ry][j], lo);
+                        const int s1 = min((int)S.st[ry][j + 1] - 1, hi);
+                        S.hist[b * 64 + lane] += (uint16_t)(s1 - s0 + 1);
+                    }
+                }
+            }
+            for (int b = 0; b < kVBins; ++b) {
+                const int c = S.hist[b * 64 + lane];
+                if (c > bc) {
+                    bc = c;
+                    best = base + b;
+                }
             }
         }
+        __syncthreads();
+    }
     if (in) dout[(size_t)y * W + x] = (int16_t)(mine >= 0 ? best : -1);
 }
 
@@ -122,8 +176,6 @@ __global__ __launch_bounds__(256) void k_vote_finish(const int16_t* dv, const ui
 
 }  // namespace
 
-size_t vote_lds_bytes(int D) { return (size_t)D * 64 * sizeof(uint16_t); }
-
 hipError_t launch_vote(const int16_t* dL, const uint8_t* valid, const uint32_t* arms, int W, int H,
                        int D, int iters, int16_t* buf0, int16_t* buf1, const int16_t** result,
                        hipStream_t st) {
@@ -133,8 +185,7 @@ hipError_t launch_vote(const int16_t* dL, const uint8_t* valid, const uint32_t* 
     int16_t* bufs[2] = {buf0, buf1};
     for (int it = 0; it < iters; ++it) {
         int16_t* dst = bufs[it & 1];
-        hipLaunchKernelGGL(k_vote, grid, dim3(64), vote_lds_bytes(D), st, src, mask, arms, W, H,
-                           D, dst);
+        hipLaunchKernelGGL(k_vote, grid, dim3(64), 0, st, src, mask, arms, W, H, D, dst);
         src = dst;
         mask = nullptr;
     }

@@ -89,12 +89,6 @@ def test_null_arguments_rejected(L):
     L.dco_stereo_destroy(None)
 
 
-def test_vote_needs_a_bounded_disparity_range(L):
-    # the vote's per-pixel counters live in LDS: D <= 448 when it is on
-    st, h = create(L, 640, 48, 449, vote_iters=2)
-    assert st == -2 and not h.value and b"vote" in L.dco_last_error()
-
-
 def test_status_strings(L):
     assert L.dco_status_string(0) == b"ok"
     assert L.dco_status_string(-4) == b"out of device memory"
