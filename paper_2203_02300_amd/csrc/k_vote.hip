@@ -88,16 +88,32 @@ __global__ __launch_bounds__(64) void k_vote(const int16_t* __restrict__ din,
         vlo = __builtin_amdgcn_readfirstlane(wave_min(lo));  // the tile's vote range
         vhi = __builtin_amdgcn_readfirstlane(wave_max(hi));  // (empty when vhi < vlo)
     }
-    for (int i = lane; i < kVR * kVT; i += 64) {
-        const int ry = i / kVT, cx = i - ry * kVT;
-        const int x = x0 + cx, y = y0 - kLMax + ry;
-        const uint32_t a = x < W && y >= 0 && y < H ? arms[(size_t)y * W + x] : 0u;
-        S.l[ry][cx] = (uint8_t)min(a & 0xff, (uint32_t)kLMax);
-        S.r[ry][cx] = (uint8_t)min((a >> 8) & 0xff, (uint32_t)kLMax);
+    {   // horizontal arms of the tile columns (loads issued together, clamped)
+        constexpr int kN = (kVR * kVT + 63) / 64;
+        uint32_t av[kN];
+#pragma unroll
+        for (int t = 0; t < kN; ++t) {
+            const int i = min(lane + 64 * t, kVR * kVT - 1);
+            const int ry = i / kVT, cx = i - ry * kVT;
+            const int x = min(x0 + cx, W - 1), y = min(max(y0 - kLMax + ry, 0), H - 1);
+            av[t] = arms[(size_t)y * W + x];
+        }
+#pragma unroll
+        for (int t = 0; t < kN; ++t) {
+            const int i = lane + 64 * t;
+            const int ry = i / kVT, cx = i - ry * kVT;
+            const int x = x0 + cx, y = y0 - kLMax + ry;
+            const uint32_t a = x < W && y >= 0 && y < H ? av[t] : 0u;
+            if (i < kVR * kVT) {
+                S.l[ry][cx] = (uint8_t)min(a & 0xff, (uint32_t)kLMax);
+                S.r[ry][cx] = (uint8_t)min((a >> 8) & 0xff, (uint32_t)kLMax);
+            }
+        }
     }
     __syncthreads();
     if (lane < kVR) {  // run-length code staged row `lane`
         int n = 0, prev = 0;
+#pragma unroll 6
         for (int c = 0; c < kVR; ++c) {
             const int v = S.d[lane][c];
             if (c == 0 || v != prev) {
