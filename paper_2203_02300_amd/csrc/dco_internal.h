@@ -11,35 +11,9 @@
 
 #include "../../include/dco_stereo.h"
 
-// Largest arm length the kernels are built for.  The aggregation halo is
-// 2 * kLMax columns/rows on each side of an output pixel.
-constexpr int kLMax = 17;
-constexpr int kVoteMaxIters = 64;
-// Threads of a streaming-aggregation workgroup = input columns of a strip.
-constexpr int kStripThreads = 256;
-// Output columns of one strip.
-constexpr int kStripOut = kStripThreads - 4 * kLMax;
+#include "dco_layout.h"
 
-// Packed per-pixel records of one view for the aggregation kernels, written
-// by k_geometry.  Both arrays hold 4-word entries (the fourth is unused: one
-// 16-byte load per pixel is cheaper than a 12-byte one), Wp per row; column x
-// sits at x + apron, and the apron columns are zero.  With hw(p) = 4 (r + 1) | 4 l << 8
-// (horizontal arms as byte offsets) and ring offsets rb(p) = the byte offsets
-// of prefix rows y + dn and y - u - 1 in a ring (16 bits each):
-//   b row r (H + kLMax + 1 rows; the last is zero), read at stream row r:
-//     two stages: m, rb1, hw(x, r) | (N1/2 | sh << 10) << 16    of pixel (x, r - kLMax)
-//                 for its stage-1 rounding floor((S1 + N1/2) / N1) = ((S1 + N1/2) m) >> sh
-//     one stage:  RN(1/N1) 2^-20, rb1, hw(x, r) | N1 << 16
-//     (hw of row r is 0 from row H on; the rest is 0 above row kLMax)
-//   c row y (H + 1 rows; row H is zero), two stages only:
-//     rb2, RN(1/N2) 2^-20, hw | N2 << 16                         of pixel (x, y)
-struct AggRecords {
-    uint32_t* b;
-    uint32_t* c;
-    int Wp, apron;
-};
-constexpr int kRecApronL = 2 * kLMax;        // left apron of the records
-constexpr int kRecApronR = kStripThreads;    // right apron (covers a strip's overhang)
+constexpr int kVoteMaxIters = 64;  // passes of one Eq. 4 vote call
 
 // Scratch owned by a matcher handle for the one-call path.
 struct dco_scratch {
