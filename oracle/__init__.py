@@ -55,6 +55,8 @@ def lib():
             "orc_match": [P, P, i, i, i, i, i, i, i, f, f, f, f, i, i, i, i, P, P, P, P],
             "orc_vote": [P, P, P, i, i, i, i, P],
             "orc_vote_finish": [P, P, i, i, i, i, P, P],
+            "orc_downscale2": [P, i, i, P],
+            "orc_depth_half": [P, P, i, i, f, P, P],
             "orc_soft_forward": [P, P, P, P, P, i, i, i, dbl, dbl, dbl, dbl, dbl, P, P],
             "orc_soft_grad": [P, P, P, P, P, i, i, i, dbl, dbl, dbl, dbl, dbl, P, P],
         }
@@ -165,6 +167,36 @@ def match(L, R, D, cw=9, ch=7, L1=17, tau1=20, gamma=1.0, eps=0.8, lam_ad=10.0, 
     lib().orc_match(_p(L), _p(R), W, H, D, cw, ch, L1, tau1, gamma, eps, lam_ad, lam_c, iters,
                     maxdiff, subpixel, vote_iters, _p(disp), _p(valid), _p(dL), _p(dR))
     return disp, valid, dL, dR
+
+
+def downscale2(rgb):
+    """2 x 2 block mean (rounded half up) of an H x W x 3 image."""
+    rgb = _c(rgb, np.uint8)
+    H, W = rgb.shape[:2]
+    out = np.empty((H // 2, W // 2, 3), np.uint8)
+    lib().orc_downscale2(_p(rgb), W, H, _p(out))
+    return out
+
+
+def depth_half(disp, valid, fB):
+    """(full-scale disparity, depth) of a quarter-size match."""
+    disp = _c(disp, np.float32)
+    valid = _c(valid, np.uint8)
+    H, W = disp.shape
+    dfull = np.empty((H, W), np.float32)
+    depth = np.empty((H, W), np.float32)
+    lib().orc_depth_half(_p(disp), _p(valid), W, H, fB, _p(dfull), _p(depth))
+    return dfull, depth
+
+
+def match_half(L, R, D, fB, **kw):
+    """The quarter-size front end: reduce both images, match with D
+    quarter-size disparities, double the disparity and convert to depth.
+    Returns (dfull, depth, valid) on the (H / 2) x (W / 2) grid."""
+    l2, r2 = downscale2(L), downscale2(R)
+    disp, valid, _, _ = match(l2, r2, D, **kw)
+    dfull, depth = depth_half(disp, valid, fB)
+    return dfull, depth, valid
 
 
 def vote(d, valid, arms, D, iters):

@@ -338,6 +338,39 @@ void orc_vote_finish(const float* agg, const int16_t* dv, int W, int H, int D, i
     }
 }
 
+/* Quarter-size front end (Sec. 4.4: the disparity is computed on the image
+ * reduced to a quarter of its area, then doubled before depth conversion).
+ * READING (reduction): each output pixel is the mean of a 2 x 2 block, per
+ * channel, rounded half up: (a + b + c + d + 2) >> 2.  The output is
+ * (W / 2) x (H / 2); an odd last column or row is dropped.
+ * rgb: H x W x 3; out: (H / 2) x (W / 2) x 3. */
+void orc_downscale2(const uint8_t* rgb, int W, int H, uint8_t* out) {
+    int w = W / 2, h = H / 2;
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x)
+            for (int c = 0; c < 3; ++c) {
+                int s = rgb[((2 * y) * W + 2 * x) * 3 + c] + rgb[((2 * y) * W + 2 * x + 1) * 3 + c] +
+                        rgb[((2 * y + 1) * W + 2 * x) * 3 + c] +
+                        rgb[((2 * y + 1) * W + 2 * x + 1) * 3 + c];
+                out[(y * w + x) * 3 + c] = (uint8_t)((s + 2) >> 2);
+            }
+}
+
+/* Full-scale disparity and depth of a quarter-size match (Sec. 4.4).
+ * READING: disparity doubled, dfull = 2 * disp (FP32, exact); depth is
+ * fB / dfull with fB = focal length x baseline of the rig (not given in the
+ * paper: a parameter), in FP32, where the pixel is valid and dfull > 0;
+ * elsewhere dfull = 0 and depth = 0 (0 = no depth, as in Eq. 14).
+ * All maps H x W of the quarter-size grid. */
+void orc_depth_half(const float* disp, const uint8_t* valid, int W, int H, float fB,
+                    float* dfull, float* depth) {
+    for (size_t i = 0; i < (size_t)W * H; ++i) {
+        float d2 = valid[i] ? 2.0f * disp[i] : 0.0f;
+        dfull[i] = d2;
+        depth[i] = d2 > 0.0f ? fB / d2 : 0.0f;
+    }
+}
+
 /* The whole plain matcher: grey, census and arms of both views, the cost and
  * aggregated volumes of both views, WTA of both, LR check, and, when
  * vote_iters > 0, the Eq. 4 vote on the LR-valid left disparities with the
