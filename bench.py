@@ -84,9 +84,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=540)
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="staged,vote,batched,soft",
+    ap.add_argument("--extras", default="staged,vote,half,batched,soft",
                     help="comma list of the extra measurements to run "
-                         "(staged, vote, batched, soft)")
+                         "(staged, vote, half, batched, soft)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of MiB mebibytes (counter calibration)")
     args = ap.parse_args()
@@ -162,6 +162,9 @@ def main():
     if "vote" in want:
         log("bench: one-call match with two Eq. 4 vote passes")
         extras["vote"] = vote_extras(gL, gR, disp, valid, args.steps)
+    if "half" in want:
+        log("bench: quarter-size front end (640x360, D=64, two vote passes, depth)")
+        extras["half"] = half_extras(gL, gR, args.steps)
     del m
     torch.cuda.empty_cache()
     if "batched" in want:
@@ -299,6 +302,23 @@ def vote_extras(gL, gR, disp0, valid0, steps):
     return dict(passes=2, ms_per_frame=round(ms, 4), vote_stage_ms=round(st[4] / calls.value, 4),
                 Mpix_disp_s=round(W * H * 128 / (ms / 1e3) / 1e6, 1),
                 valid_pixels=int(valid.sum()), changed_pixels=changed)
+
+
+def half_extras(gL, gR, steps):
+    """The paper's operating point: the 1280x720 pair reduced to 640x360,
+    matched with D = 64 and two Eq. 4 vote passes, disparity doubled and
+    converted to depth, all on the GPU: ms per frame."""
+    import torch
+    from paper_2203_02300_amd import StereoMatcher
+    H2, W2 = gL.shape[:2]
+    W, H, D = W2 // 2, H2 // 2, 64
+    m = StereoMatcher(W, H, D, vote_iters=2)
+    ms = _time(lambda: m.match_half(gL, gR, 1000.0), steps)
+    _, valid, _ = m.match_half(gL, gR, 1000.0)
+    torch.cuda.synchronize()
+    m.close()
+    return dict(full=f"{W2}x{H2}", reduced=f"{W}x{H}", D=D, vote_passes=2,
+                ms_per_frame=round(ms, 4), valid_frac=round(float(valid.float().mean()), 4))
 
 
 def staged_extras(m, gL, gR, steps):

@@ -146,6 +146,23 @@ dco_status dco_wta_lrcheck(dco_stereo* h, const float* aggL, const float* aggR, 
 dco_status dco_stereo_match(dco_stereo* h, const uint8_t* rgbL, const uint8_t* rgbR, float* disp,
                             uint8_t* valid);
 
+/* The quarter-size front end (Sec. 4.4): the disparity is computed on the
+ * pair reduced to half width and half height, then doubled and converted to
+ * depth.  The handle is created for the reduced size W x H (and the
+ * disparity range D of the reduced pair); the full images are W2 x H2 with
+ * W2 / 2 = W and H2 / 2 = H (an odd last column or row is dropped).
+ *   reduction: each reduced pixel and channel = (sum of its 2 x 2 block + 2) >> 2
+ *   then dco_stereo_match on the reduced pair (vote_iters applies)
+ *   disp2 = 2 x the reduced disparity where valid, else 0
+ *   depth = fB / disp2 where disp2 > 0, else 0 (0 = no depth, as in Eq. 14)
+ * fB = focal length (pixels of the full image) x baseline, in the unit wanted
+ * for depth; not used when depth is NULL.
+ * rgbL2, rgbR2: H2 x W2 x 3 uint8; disp2, depth: H x W float (out; depth
+ * optional); valid: H x W uint8 (out). */
+dco_status dco_stereo_match_half(dco_stereo* h, const uint8_t* rgbL2, const uint8_t* rgbR2,
+                                 int W2, int H2, float fB, float* disp2, uint8_t* valid,
+                                 float* depth);
+
 /* Disparity refinement by region vote (Eq. 4, Sec. 4.3), `iters` passes.
  * In each pass every valid pixel p takes the disparity with the most votes
  * in its stage-1 cross region N_p: for each y' in [y - u(p), y + dn(p)] the

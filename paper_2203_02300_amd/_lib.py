@@ -18,6 +18,7 @@ EXPORTS = (
     "dco_stereo_last_disparities", "dco_stereo_profile", "dco_stereo_stage_times",
     "dco_batch_create", "dco_batch_destroy", "dco_batch_match",
     "dco_batch_tile", "dco_soft_forward", "dco_soft_backward", "dco_vote_refine",
+    "dco_stereo_match_half",
     "dco_status_string", "dco_last_error",
 )
 
@@ -76,6 +77,7 @@ def lib():
         "dco_soft_forward": (st, [P, i, P, P, P, P, P]),
         "dco_soft_backward": (st, [P, i, P, P, P, P, P, P, P]),
         "dco_vote_refine": (st, [P, P, P, P, P, i, P, P, P]),
+        "dco_stereo_match_half": (st, [P, P, P, i, i, C.c_float, P, P, P]),
         "dco_status_string": (C.c_char_p, [st]),
         "dco_last_error": (C.c_char_p, []),
     }

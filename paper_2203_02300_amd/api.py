@@ -141,6 +141,21 @@ class StereoMatcher:
         check(lib().dco_stereo_match(self._h, _ptr(L), _ptr(R), _ptr(disp), _ptr(valid)))
         return disp, valid
 
+    def match_half(self, L2, R2, fB=0.0, want_depth=True):
+        """Quarter-size front end on full images of (2H or 2H+1) x (2W or
+        2W+1) x 3: returns (disp2, valid, depth) on this handle's W x H grid
+        (depth is None when not requested)."""
+        H2, W2 = L2.shape[:2]
+        _need(L2, "L2", torch.uint8, (H2, W2, 3))
+        _need(R2, "R2", torch.uint8, (H2, W2, 3))
+        self._begin()
+        disp = self._empty((self.H, self.W), torch.float32)
+        valid = self._empty((self.H, self.W), torch.uint8)
+        depth = self._empty((self.H, self.W), torch.float32) if want_depth else None
+        check(lib().dco_stereo_match_half(self._h, _ptr(L2), _ptr(R2), W2, H2, float(fB),
+                                          _ptr(disp), _ptr(valid), _ptr(depth)))
+        return disp, valid, depth
+
     def vote_refine(self, armsL, aggL, dL, valid, iters):
         """Eq. 4 region vote on the left integer map: returns (disp, valid, dvote)."""
         _need(armsL, "armsL", torch.uint8, (self.H, self.W, 4))

@@ -127,6 +127,7 @@ static void free_handle_memory(dco_stereo* h) {
                     h->s.rec[1].b,   h->s.rec[1].c,
                     h->s.agg[0],     h->s.agg[1],     h->s.dint[0],
                     h->s.dint[1],    h->s.delta,      h->s.vote[0],    h->s.vote[1],
+                    h->s.half[0],    h->s.half[1],
                     h->soft.pix[0],  h->soft.pix[1],
                     h->soft.arms,    h->soft.arms_r,  h->soft.n1,      h->soft.n2,
                     h->soft.tab,     h->soft.vol[0],  h->soft.vol[1],  h->soft.vol[2],
@@ -162,6 +163,8 @@ static dco_status alloc_scratch(dco_stereo* h) {
     DCO_TRY(dev_alloc(&s.delta, P));
     DCO_TRY(dev_alloc(&s.vote[0], P));
     DCO_TRY(dev_alloc(&s.vote[1], P));
+    DCO_TRY(dev_alloc(&s.half[0], 3 * P));
+    DCO_TRY(dev_alloc(&s.half[1], 3 * P));
     h->scratch_ready = true;
     return DCO_OK;
 }
@@ -418,6 +421,34 @@ extern "C" dco_status dco_stereo_match(dco_stereo* h, const uint8_t* rgbL, const
                                          valid, nullptr, h->stream));
     }
     DCO_TRY(prof_mark(h));
+    return DCO_OK;
+}
+
+extern "C" dco_status dco_stereo_match_half(dco_stereo* h, const uint8_t* rgbL2,
+                                            const uint8_t* rgbR2, int W2, int H2, float fB,
+                                            float* disp2, uint8_t* valid, float* depth) {
+    DCO_TRY(need(h, "handle"));
+    DCO_TRY(need(rgbL2, "rgbL2"));
+    DCO_TRY(need(rgbR2, "rgbR2"));
+    DCO_TRY(need(disp2, "disp2"));
+    DCO_TRY(need(valid, "valid"));
+    if (W2 / 2 != h->W || H2 / 2 != h->H || W2 < 0 || H2 < 0) {
+        dco_set_error("full images of %d x %d do not reduce to the handle's %d x %d", W2, H2, h->W,
+                      h->H);
+        return DCO_ERR_SHAPE;
+    }
+    if (depth && !pos_finite(fB)) {
+        dco_set_error("fB must be finite and > 0 when depth is requested");
+        return DCO_ERR_ARG;
+    }
+    if (!h->scratch_ready) {
+        dco_set_error("handle has no scratch");
+        return DCO_ERR_STATE;
+    }
+    DCO_HIP_CHECK(launch_downscale2(rgbL2, rgbR2, W2, h->W, h->H, h->s.half[0], h->s.half[1],
+                                    h->stream));
+    DCO_TRY(dco_stereo_match(h, h->s.half[0], h->s.half[1], disp2, valid));
+    DCO_HIP_CHECK(launch_depth_half(disp2, valid, h->W, h->H, fB, depth, h->stream));
     return DCO_OK;
 }
 

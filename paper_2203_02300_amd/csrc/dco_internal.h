@@ -24,6 +24,7 @@ struct dco_scratch {
     int16_t* dint[2];
     float* delta;
     int16_t* vote[2];   // ping-pong maps of the Eq. 4 vote passes
+    uint8_t* half[2];   // the reduced pair of dco_stereo_match_half (H x W x 3)
 };
 
 // Soft-path scratch of a handle: per-pair maps of B pairs and three
@@ -141,6 +142,13 @@ hipError_t launch_vote(const int16_t* dL, const uint8_t* valid, const uint32_t* 
 hipError_t launch_vote_finish(const int16_t* dv, const uint8_t* valid_in, const float* agg, int W,
                               int H, int D, int subpixel, float* disp, uint8_t* valid,
                               int16_t* dv_out, hipStream_t st);
+// Quarter-size front end: 2 x 2 block means of both full images (row length
+// W2 pixels) into W x H x 3 outputs; then disp = 2 disp where valid (else 0)
+// in place, and depth = fB / disp where > 0 (depth optional).
+hipError_t launch_downscale2(const uint8_t* rgbL, const uint8_t* rgbR, int W2, int W, int H,
+                             uint8_t* outL, uint8_t* outR, hipStream_t st);
+hipError_t launch_depth_half(float* disp, const uint8_t* valid, int W, int H, float fB,
+                             float* depth, hipStream_t st);
 // Arms and packed pixels of both views of B pairs (HWC images of 3 W H
 // bytes each, outputs of W H entries each, pair-major) in one launch.
 hipError_t launch_census_pairs(const uint8_t* rgbL, const uint8_t* rgbR, int B, int W, int H,

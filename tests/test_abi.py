@@ -85,6 +85,7 @@ def test_null_arguments_rejected(L):
     assert L.dco_wta_lrcheck(None, None, None, None, None, None, None) == -1
     assert L.dco_stereo_match(None, None, None, None, None) == -1
     assert L.dco_vote_refine(None, None, None, None, None, 1, None, None, None) == -1
+    assert L.dco_stereo_match_half(None, None, None, 2, 2, 1.0, None, None, None) == -1
     assert L.dco_stereo_set_stream(None, None) == -1
     L.dco_stereo_destroy(None)
 
