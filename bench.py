@@ -84,9 +84,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=540)
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="staged,vote,half,batched,soft",
+    ap.add_argument("--extras", default="staged,vote,half,densify,batched,soft",
                     help="comma list of the extra measurements to run "
-                         "(staged, vote, half, batched, soft)")
+                         "(staged, vote, half, densify, batched, soft)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of MiB mebibytes (counter calibration)")
     args = ap.parse_args()
@@ -165,6 +165,9 @@ def main():
     if "half" in want:
         log("bench: quarter-size front end (640x360, D=64, two vote passes, depth)")
         extras["half"] = half_extras(gL, gR, args.steps)
+    if "densify" in want:
+        log("bench: depth densification (Eq. 13-20) at 640x360 and 1280x720")
+        extras["densify"] = densify_extras(max(3, args.steps // 10))
     del m
     torch.cuda.empty_cache()
     if "batched" in want:
@@ -319,6 +322,30 @@ def half_extras(gL, gR, steps):
     m.close()
     return dict(full=f"{W2}x{H2}", reduced=f"{W}x{H}", D=D, vote_passes=2,
                 ms_per_frame=round(ms, 4), valid_frac=round(float(valid.float().mean()), 4))
+
+
+def densify_extras(n):
+    """Depth densification (Eq. 13-20) on seeded synthetic inputs at the
+    paper's reduced grid and at the full frame: ms per solve, iterations, and
+    the iteration kernels' HBM rate for their algorithmic bytes (per pixel
+    and iteration: 7 FP64 reads and 2 writes in the direction launch, 5 reads
+    and 2 writes in the update launch, neighbours counted once)."""
+    import torch
+    from paper_2203_02300_amd import Densifier, synth
+    out = {}
+    for W, H in ((640, 360), (1280, 720)):
+        d = synth.densify_inputs(W, H, 7)
+        t = {k: torch.from_numpy(d[k]).cuda() for k in ("Ds", "Dpre", "Bdp", "Mfuse", "MI")}
+        z = Densifier(W, H)
+        run = lambda: z.run(t["Ds"], t["Bdp"], t["Mfuse"], t["MI"], Dpre=t["Dpre"])
+        ms = _time(run, n)
+        it, rel = z.stats()
+        z.close()
+        bytes_iter = (9 + 7) * 8 * W * H
+        out[f"{W}x{H}"] = dict(ms_per_solve=round(ms, 3), iterations=it, rel_residual=rel,
+                               us_per_iteration=round(ms * 1e3 / max(it, 1), 2),
+                               GBs_iteration_bytes=round(bytes_iter * it / (ms / 1e3) / 1e9, 1))
+    return out
 
 
 def staged_extras(m, gL, gR, steps):

@@ -201,6 +201,48 @@ dco_status dco_stereo_last_disparities(dco_stereo* h, int16_t* dL, int16_t* dR);
 dco_status dco_stereo_profile(dco_stereo* h, int enable);
 dco_status dco_stereo_stage_times(dco_stereo* h, float* ms, int n, int* calls);
 
+/* ---- Depth densification (Sec. 6, Eq. 13-20) ---- */
+
+/* The dense depth D of an H x W grid minimises Eq. 20:
+ *   lambda_d  sum_p w_sparse(p) (D(p) - D_sparse(p))^2             (Eq. 13-14)
+ * + lambda_s  sum_p sum_{q in N4(p)} w_pq (D(p) - D(q))^2           (Eq. 15-17)
+ * + lambda_s2 sum_p w_stable(p) (D(p) - D_pre(p))^2                 (Eq. 18-19)
+ * with w_sparse = [D_sparse > 0], w_stable = [D_pre > 0], and w_pq = 0 when
+ * exactly one of p, q is on the depth contour B_dp, else
+ * max(1 - min(s_p, s_q), 0) with s = M_fuse M_I.  The normal equations are
+ * solved by Jacobi-preconditioned conjugate gradients in FP64 until
+ * |r| <= tol |b| or max_iters iterations; pixels whose region (joined by
+ * w_pq > 0 edges) holds no data or stability term get D = 0. */
+typedef struct {
+    float lambda_d, lambda_s, lambda_s2;  /* >= 0 (Sec. 7.2: 0.8, 1.2, 0.02) */
+    double tol;                           /* relative residual to stop at (default 1e-9) */
+    int max_iters;                        /* >= 0 (default 4000) */
+    int iters_per_launch;                 /* even, 2..1024: iterations per graph launch,
+                                             convergence is checked between launches
+                                             (default 16) */
+} dco_densify_params;
+typedef struct dco_densify dco_densify; /* opaque densification handle */
+
+dco_status dco_densify_default_params(dco_densify_params* out);
+
+/* Buffers for an H x W grid and the captured iteration graph (p may be
+ * NULL for the defaults; stream: the HIP stream the solves run on). */
+dco_status dco_densify_create(dco_densify** out, int W, int H, const dco_densify_params* p,
+                              void* stream);
+void dco_densify_destroy(dco_densify* h);
+
+/* One solve.  Ds (D_sparse, 0 = no data), Dpre (D_pre, 0 = none; NULL for
+ * none), Mfuse, MI: H x W float; Bdp: H x W uint8 (nonzero = on the depth
+ * contour); D: H x W float (out).  All device pointers.  Returns when the
+ * solve has converged or used max_iters iterations (the host reads the
+ * convergence flag after every launch of iters_per_launch iterations). */
+dco_status dco_densify_run(dco_densify* h, const float* Ds, const float* Dpre, const uint8_t* Bdp,
+                           const float* Mfuse, const float* MI, float* D);
+
+/* Iterations used by the last solve and its final |r| / |b| (host outputs,
+ * either may be NULL).  Synchronises the stream. */
+dco_status dco_densify_stats(dco_densify* h, int* iters, double* rel_residual);
+
 /* ---- Batched matcher: many pairs of uneven size and disparity range ---- */
 
 /* Create a batched matcher for n pairs of sizes W[i] x H[i], disparity

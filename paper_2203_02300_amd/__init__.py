@@ -10,13 +10,13 @@ scene generator can be used without a GPU.
 """
 
 __all__ = ["StereoMatcher", "BatchMatcher", "DcoSoftArgmin", "soft_argmin_disparity",
-           "default_params"]
+           "default_params", "Densifier"]
 
 
 import importlib
 
 _LAZY = {"StereoMatcher": "api", "default_params": "api", "BatchMatcher": "batch",
-         "DcoSoftArgmin": "soft", "soft_argmin_disparity": "soft"}
+         "DcoSoftArgmin": "soft", "soft_argmin_disparity": "soft", "Densifier": "densify"}
 
 
 def __getattr__(name):

@@ -18,7 +18,8 @@ EXPORTS = (
     "dco_stereo_last_disparities", "dco_stereo_profile", "dco_stereo_stage_times",
     "dco_batch_create", "dco_batch_destroy", "dco_batch_match",
     "dco_batch_tile", "dco_soft_forward", "dco_soft_backward", "dco_vote_refine",
-    "dco_stereo_match_half",
+    "dco_stereo_match_half", "dco_densify_default_params", "dco_densify_create",
+    "dco_densify_destroy", "dco_densify_run", "dco_densify_stats",
     "dco_status_string", "dco_last_error",
 )
 
@@ -41,6 +42,13 @@ class Params(C.Structure):
         ("gamma_L", C.c_float), ("eps", C.c_float),
         ("agg_iters", C.c_int), ("lr_max_diff", C.c_int), ("subpixel", C.c_int),
         ("vote_iters", C.c_int),
+    ]
+
+
+class DensifyParams(C.Structure):
+    _fields_ = [
+        ("lambda_d", C.c_float), ("lambda_s", C.c_float), ("lambda_s2", C.c_float),
+        ("tol", C.c_double), ("max_iters", C.c_int), ("iters_per_launch", C.c_int),
     ]
 
 
@@ -78,6 +86,11 @@ def lib():
         "dco_soft_backward": (st, [P, i, P, P, P, P, P, P, P]),
         "dco_vote_refine": (st, [P, P, P, P, P, i, P, P, P]),
         "dco_stereo_match_half": (st, [P, P, P, i, i, C.c_float, P, P, P]),
+        "dco_densify_default_params": (st, [C.POINTER(DensifyParams)]),
+        "dco_densify_create": (st, [C.POINTER(P), i, i, C.POINTER(DensifyParams), P]),
+        "dco_densify_destroy": (None, [P]),
+        "dco_densify_run": (st, [P, P, P, P, P, P, P]),
+        "dco_densify_stats": (st, [P, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
         "dco_status_string": (C.c_char_p, [st]),
         "dco_last_error": (C.c_char_p, []),
     }

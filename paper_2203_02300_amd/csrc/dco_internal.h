@@ -149,6 +149,21 @@ hipError_t launch_downscale2(const uint8_t* rgbL, const uint8_t* rgbR, int W2, i
                              uint8_t* outL, uint8_t* outR, hipStream_t st);
 hipError_t launch_depth_half(float* disp, const uint8_t* valid, int W, int H, float fB,
                              float* depth, hipStream_t st);
+// Depth densification (Eq. 13-20): device buffers of one grid (FP64 state,
+// nblk = densify_blocks(W, H) block partials per sum) and its launches.
+struct DensifyBufs {
+    double *cr, *cd, *diag, *invdiag;  // edge coefficients (p, p + x), (p, p + y); diagonal
+    double *x, *r, *q, *p[2];          // solution, residual, A p, search directions
+    double *rz[2], *rr[2], *pq, *bb;   // block partial sums
+    int* flags;                        // [0] converged, [1] iterations done
+};
+int densify_blocks(int W, int H);
+hipError_t launch_densify_setup(const DensifyBufs& b, const float* Ds, const float* Dpre,
+                                const uint8_t* Bdp, const float* Mfuse, const float* MI, int W,
+                                int H, double lam_d, double lam_s, double lam_s2, hipStream_t st);
+hipError_t launch_densify_iters(const DensifyBufs& b, int W, int H, double tol, int n,
+                                hipStream_t st);
+hipError_t launch_densify_out(const DensifyBufs& b, int W, int H, float* D, hipStream_t st);
 // Arms and packed pixels of both views of B pairs (HWC images of 3 W H
 // bytes each, outputs of W H entries each, pair-major) in one launch.
 hipError_t launch_census_pairs(const uint8_t* rgbL, const uint8_t* rgbR, int B, int W, int H,

@@ -383,3 +383,37 @@ def config_c5(n=8, seed0=200, W=640, H=480, D=64):
     """Differentiable: ``n`` C2-style pairs."""
     return [make_slanted_pair(W, H, D, seed0 + i, n_planes=6, dmin=4.0, dmax=D - 4.0,
                               noise_sigma=2.0, occl_strip_frac=0.03) for i in range(n)]
+
+
+def densify_inputs(W=640, H=360, seed=7, fB=1000.0, keep=0.7):
+    """Inputs of the depth densification (Eq. 13-20) from a slanted-plane
+    scene's ground truth: the sparse depth ``Ds`` (fB / disparity on a random
+    ``keep`` fraction of the pixels, 0 elsewhere), the previous frame's depth
+    ``Dpre`` (the ground truth scaled by 1 + N(0, 0.01) on half of the pixels,
+    0 elsewhere), the binary depth contour ``Bdp`` (pixels with a 4-neighbour
+    whose ground-truth disparity differs by more than 1), and the two maps
+    ``Mfuse`` and ``MI`` in [0, 1] (smooth value noise standing in for the
+    outputs of Sec. 5, which are not built here).  All H x W float32 except
+    ``Bdp`` (uint8)."""
+    scene = make_slanted_pair(W, H, 64, seed, n_planes=6, n_boxes=2, dmin=4.0, dmax=60.0,
+                              noise_sigma=0.0)
+    rng = np.random.default_rng(seed + 1000)
+    disp = scene["disp"].astype(np.float64)
+    depth = fB / np.maximum(disp, 1e-3)
+    Ds = np.where(rng.random((H, W)) < keep, depth, 0.0)
+    Dpre = np.where(rng.random((H, W)) < 0.5, depth * (1.0 + 0.01 * rng.normal(size=(H, W))), 0.0)
+    jump = np.zeros((H, W), bool)
+    dx = np.abs(np.diff(disp, axis=1)) > 1.0
+    dy = np.abs(np.diff(disp, axis=0)) > 1.0
+    jump[:, :-1] |= dx
+    jump[:, 1:] |= dx
+    jump[:-1, :] |= dy
+    jump[1:, :] |= dy
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    lat1, lat2 = _lattice(rng, H // 16 + 2, W // 16 + 2), _lattice(rng, H // 16 + 2, W // 16 + 2)
+    Mfuse = _value_noise(lat1, 16.0, xs, ys)
+    MI = _value_noise(lat2, 16.0, xs, ys)
+    return dict(Ds=Ds.astype(np.float32), Dpre=Dpre.astype(np.float32),
+                Bdp=jump.astype(np.uint8), Mfuse=np.clip(Mfuse, 0, 1).astype(np.float32),
+                MI=np.clip(MI, 0, 1).astype(np.float32), depth=depth.astype(np.float32),
+                W=W, H=H, seed=seed)

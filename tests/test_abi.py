@@ -86,6 +86,26 @@ def test_null_arguments_rejected(L):
     assert L.dco_stereo_match(None, None, None, None, None) == -1
     assert L.dco_vote_refine(None, None, None, None, None, 1, None, None, None) == -1
     assert L.dco_stereo_match_half(None, None, None, 2, 2, 1.0, None, None, None) == -1
+    assert L.dco_densify_run(None, None, None, None, None, None, None) == -1
+    assert L.dco_densify_create(None, 4, 4, None, None) == -1
+    L.dco_densify_destroy(None)
+
+
+def test_densify_defaults_and_bad_params(L):
+    p = _lib.DensifyParams()
+    assert L.dco_densify_default_params(C.byref(p)) == 0
+    assert abs(p.lambda_d - 0.8) < 1e-7 and abs(p.lambda_s - 1.2) < 1e-7
+    assert abs(p.lambda_s2 - 0.02) < 1e-9
+    assert p.iters_per_launch % 2 == 0 and p.max_iters > 0
+    for k, v in (("lambda_s", -1.0), ("tol", float("nan")), ("iters_per_launch", 3),
+                 ("max_iters", -1)):
+        q = _lib.DensifyParams()
+        L.dco_densify_default_params(C.byref(q))
+        setattr(q, k, v)
+        h = C.c_void_p()
+        assert L.dco_densify_create(C.byref(h), 8, 8, C.byref(q), None) == -1 and not h.value
+    h = C.c_void_p()
+    assert L.dco_densify_create(C.byref(h), 0, 8, None, None) == -2
     assert L.dco_stereo_set_stream(None, None) == -1
     L.dco_stereo_destroy(None)
 
