@@ -56,6 +56,8 @@ def lib():
             "orc_vote": [P, P, P, i, i, i, i, P],
             "orc_vote_finish": [P, P, i, i, i, i, P, P],
             "orc_downscale2": [P, i, i, P],
+            "orc_flow_fuse": [P, P, i, i, i, P],
+            "orc_contour": [P, i, i, P, i, i, f, f, f, P, P],
             "orc_depth_half": [P, P, i, i, f, P, P],
             "orc_soft_forward": [P, P, P, P, P, i, i, i, dbl, dbl, dbl, dbl, dbl, P, P],
             "orc_soft_grad": [P, P, P, P, P, i, i, i, dbl, dbl, dbl, dbl, dbl, P, P],
@@ -167,6 +169,36 @@ def match(L, R, D, cw=9, ch=7, L1=17, tau1=20, gamma=1.0, eps=0.8, lam_ad=10.0, 
     lib().orc_match(_p(L), _p(R), W, H, D, cw, ch, L1, tau1, gamma, eps, lam_ad, lam_c, iters,
                     maxdiff, subpixel, vote_iters, _p(disp), _p(valid), _p(dL), _p(dR))
     return disp, valid, dL, dR
+
+
+def flow_fuse(past, future, R=2):
+    """Eq. 6-12 with the box filter and normalisation of Sec. 5.2-5.3.2:
+    the normalised fused amplitude on the flows' grid (h x w float32)."""
+    past = _c(past, np.float32)
+    future = _c(future, np.float32)
+    h, w = past.shape[:2]
+    out = np.empty((h, w), np.float32)
+    lib().orc_flow_fuse(_p(past), _p(future), w, h, R, _p(out))
+    return out
+
+
+def contour(Y, Mn, Thigh=0.06, Tlow=0.03, Tdepth=0.03):
+    """Depth-gated Canny (Sec. 5.3): (B uint8 0/1, MI float32), H x W."""
+    Y = _c(Y, np.uint8)
+    Mn = _c(Mn, np.float32)
+    H, W = Y.shape
+    h, w = Mn.shape
+    B = np.empty((H, W), np.uint8)
+    MI = np.empty((H, W), np.float32)
+    lib().orc_contour(_p(Y), W, H, _p(Mn), w, h, Thigh, Tlow, Tdepth, _p(B), _p(MI))
+    return B, MI
+
+
+def depth_contour(rgb, past, future, R=2, Thigh=0.06, Tlow=0.03, Tdepth=0.03):
+    """The whole Sec. 5 filter given the flows: (B, MI, Mn)."""
+    Mn = flow_fuse(past, future, R)
+    B, MI = contour(grey(rgb), Mn, Thigh, Tlow, Tdepth)
+    return B, MI, Mn
 
 
 def downscale2(rgb):

@@ -338,6 +338,166 @@ void orc_vote_finish(const float* agg, const int16_t* dv, int W, int H, int D, i
     }
 }
 
+/* ------------------------------------------------------------------------
+ * Depth contour extraction given the two optical flow fields (Sec. 5).
+ * The flows are computed elsewhere (DIS flow is not part of this build);
+ * they arrive on the quarter-size grid w x h as (U, V) pairs, float.
+ * ------------------------------------------------------------------------ */
+
+/* Eq. 6-8: r = |I(p)| (FP32, correctly rounded square root); M(p) = max of
+ * |r(p_right) - r(p)| and |r(p_bottom) - r(p)|.
+ * READING (border): a missing right or bottom neighbour contributes 0. */
+static float flow_r(const float* F, int i) {
+    float u = F[2 * i], v = F[2 * i + 1];
+    return sqrtf(u * u + v * v);
+}
+static float flow_amp(const float* F, int w, int h, int x, int y) {
+    int i = y * w + x;
+    float r = flow_r(F, i);
+    float gu = x + 1 < w ? fabsf(flow_r(F, i + 1) - r) : 0.0f;
+    float gv = y + 1 < h ? fabsf(flow_r(F, i + w) - r) : 0.0f;
+    return gu > gv ? gu : gv;
+}
+
+/* Eq. 9-11: the change of the flow projected on its own direction at p:
+ * e = I(p) / |I(p)|, p1 = p + rint(e), p0 = p - rint(e) (clamped to the
+ * grid), f_i = I(p_i) . e, score = f1 - f0.
+ * READING (step): p0 and p1 are the nearest pixels one unit along -e and
+ * +e; the paper draws them near p without a distance.  A zero flow has no
+ * direction and scores 0. */
+static float flow_score(const float* F, int w, int h, int x, int y) {
+    int i = y * w + x;
+    float r = flow_r(F, i);
+    if (r == 0.0f) return 0.0f;
+    float ex = F[2 * i] / r, ey = F[2 * i + 1] / r;
+    int sx = (int)rintf(ex), sy = (int)rintf(ey);
+    int x1 = clampi(x + sx, 0, w - 1), y1 = clampi(y + sy, 0, h - 1);
+    int x0 = clampi(x - sx, 0, w - 1), y0 = clampi(y - sy, 0, h - 1);
+    int j1 = y1 * w + x1, j0 = y0 * w + x0;
+    float f1 = F[2 * j1] * ex + F[2 * j1 + 1] * ey;
+    float f0 = F[2 * j0] * ex + F[2 * j0 + 1] * ey;
+    return f1 - f0;
+}
+
+/* Eq. 12 and the box filter of Sec. 5.2, then the normalisation of
+ * Sec. 5.3.2: Mfuse = M_past where score_past > score_future, M_future
+ * where score_future > score_past; then the mean over the (2R + 1)^2 window
+ * clipped to the grid (summed row by row, left to right), then divided by
+ * its maximum over the grid (all 0 when the maximum is 0).
+ * READING (tie): equal scores keep the larger amplitude.
+ * READING (box): the window size is not given; R is a parameter (default 2).
+ * past, future: h x w x 2; out: h x w. */
+void orc_flow_fuse(const float* past, const float* future, int w, int h, int R, float* out) {
+    float* fu = (float*)malloc(sizeof(float) * (size_t)w * h);
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            float mp = flow_amp(past, w, h, x, y), mf = flow_amp(future, w, h, x, y);
+            float sp = flow_score(past, w, h, x, y), sf = flow_score(future, w, h, x, y);
+            fu[y * w + x] = sp > sf ? mp : (sf > sp ? mf : (mp > mf ? mp : mf));
+        }
+    float mx = 0.0f;
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            float s = 0.0f;
+            int n = 0;
+            for (int yy = y - R; yy <= y + R; ++yy)
+                for (int xx = x - R; xx <= x + R; ++xx)
+                    if (yy >= 0 && yy < h && xx >= 0 && xx < w) {
+                        s += fu[yy * w + xx];
+                        ++n;
+                    }
+            out[y * w + x] = s / (float)n;
+            if (out[y * w + x] > mx) mx = out[y * w + x];
+        }
+    for (size_t i = 0; i < (size_t)w * h; ++i) out[i] = mx > 0.0f ? out[i] / mx : 0.0f;
+    free(fu);
+}
+
+/* Canny with the depth gate (Sec. 5.3) on the full-size grey image Y (W x H,
+ * the census grey of reading 1), given the normalised fused amplitude Mn on
+ * the quarter grid (w = W / 2, h = H / 2).
+ * READING (gradient): 3x3 Sobel on integer grey with replicated borders,
+ *   G2 = gx^2 + gy^2 (exact integers); the normalised magnitude of
+ *   Sec. 7.2 is sqrt(G2 / max G2), so a threshold T is G2 > T^2 max G2
+ *   (compared in double).
+ * READING (suppression): the direction of (gx, gy) falls in one of four
+ *   sectors: horizontal when 128 |gy| < 53 |gx| (tan 22.5 deg ~ 53/128),
+ *   vertical when 128 |gx| < 53 |gy|, else the diagonal given by the sign of
+ *   gx gy; p survives when G2(p) > G2 of the neighbour before it along the
+ *   direction and G2(p) >= G2 of the neighbour after it.
+ * READING (gate): p is dropped when Mn at (min(x / 2, w - 1), min(y / 2,
+ *   h - 1)) is below T_depth.
+ * Double threshold: strong above T_high, weak above T_low; weak pixels
+ * 8-connected (through weak or strong pixels) to a strong one are edges
+ * (breadth-first search here).  Outputs the contour B (uint8 0/1) and the
+ * normalised magnitude MI = sqrt(G2 / max G2) (FP32; 0 when max G2 = 0). */
+void orc_contour(const uint8_t* Y, int W, int H, const float* Mn, int w, int h, float Thigh,
+                 float Tlow, float Tdepth, uint8_t* B, float* MI) {
+    size_t P = (size_t)W * H;
+    int32_t* gx = (int32_t*)malloc(4 * P);
+    int32_t* gy = (int32_t*)malloc(4 * P);
+    int64_t* G2 = (int64_t*)malloc(8 * P);
+    uint8_t* st = (uint8_t*)malloc(P);
+    int* queue = (int*)malloc(sizeof(int) * P);
+#define YV(xx, yy) ((int)Y[(size_t)clampi(yy, 0, H - 1) * W + clampi(xx, 0, W - 1)])
+    int64_t mx = 0;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            int a = YV(x + 1, y - 1) + 2 * YV(x + 1, y) + YV(x + 1, y + 1) - YV(x - 1, y - 1) -
+                    2 * YV(x - 1, y) - YV(x - 1, y + 1);
+            int b = YV(x - 1, y + 1) + 2 * YV(x, y + 1) + YV(x + 1, y + 1) - YV(x - 1, y - 1) -
+                    2 * YV(x, y - 1) - YV(x + 1, y - 1);
+            size_t i = (size_t)y * W + x;
+            gx[i] = a;
+            gy[i] = b;
+            G2[i] = (int64_t)a * a + (int64_t)b * b;
+            if (G2[i] > mx) mx = G2[i];
+        }
+#undef YV
+    double th = (double)Thigh * (double)Thigh * (double)mx;
+    double tl = (double)Tlow * (double)Tlow * (double)mx;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            size_t i = (size_t)y * W + x;
+            st[i] = 0;
+            int ax = absi(gx[i]), ay = absi(gy[i]);
+            int dx, dy;
+            if (128 * ay < 53 * ax) { dx = 1; dy = 0; }
+            else if (128 * ax < 53 * ay) { dx = 0; dy = 1; }
+            else if ((gx[i] > 0) == (gy[i] > 0)) { dx = 1; dy = 1; }
+            else { dx = 1; dy = -1; }
+            int xa = x - dx, ya = y - dy, xb = x + dx, yb = y + dy;
+            int64_t ga = (xa >= 0 && xa < W && ya >= 0 && ya < H) ? G2[(size_t)ya * W + xa] : 0;
+            int64_t gb = (xb >= 0 && xb < W && yb >= 0 && yb < H) ? G2[(size_t)yb * W + xb] : 0;
+            if (!(G2[i] > ga && G2[i] >= gb)) continue;
+            float g = Mn[(size_t)(y / 2 < h ? y / 2 : h - 1) * w + (x / 2 < w ? x / 2 : w - 1)];
+            if (g < Tdepth) continue;
+            double v = (double)G2[i];
+            st[i] = v > th ? 2 : (v > tl ? 1 : 0);
+        }
+    int qh = 0, qt = 0;
+    for (size_t i = 0; i < P; ++i)
+        if (st[i] == 2) queue[qt++] = (int)i;
+    while (qh < qt) {
+        int i = queue[qh++], y = i / W, x = i % W;
+        for (int yy = y - 1; yy <= y + 1; ++yy)
+            for (int xx = x - 1; xx <= x + 1; ++xx)
+                if (yy >= 0 && yy < H && xx >= 0 && xx < W && st[(size_t)yy * W + xx] == 1) {
+                    st[(size_t)yy * W + xx] = 2;
+                    queue[qt++] = yy * W + xx;
+                }
+    }
+    for (size_t i = 0; i < P; ++i) {
+        B[i] = st[i] == 2;
+        MI[i] = mx > 0 ? sqrtf((float)((double)G2[i] / (double)mx)) : 0.0f;
+    }
+    free(gx);
+    free(gy);
+    free(G2);
+    free(st);
+    free(queue);
+}
+
 /* Quarter-size front end (Sec. 4.4: the disparity is computed on the image
  * reduced to a quarter of its area, then doubled before depth conversion).
  * READING (reduction): each output pixel is the mean of a 2 x 2 block, per
