@@ -84,9 +84,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=540)
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="staged,vote,half,densify,batched,soft",
+    ap.add_argument("--extras", default="staged,vote,half,densify,contour,batched,soft",
                     help="comma list of the extra measurements to run "
-                         "(staged, vote, half, densify, batched, soft)")
+                         "(staged, vote, half, densify, contour, batched, soft)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of MiB mebibytes (counter calibration)")
     args = ap.parse_args()
@@ -165,6 +165,9 @@ def main():
     if "half" in want:
         log("bench: quarter-size front end (640x360, D=64, two vote passes, depth)")
         extras["half"] = half_extras(gL, gR, args.steps)
+    if "contour" in want:
+        log("bench: depth contour filter (1280x720 frame, 640x360 flows)")
+        extras["contour"] = contour_extras(args.steps)
     if "densify" in want:
         log("bench: depth densification (Eq. 13-20) at 640x360 and 1280x720")
         extras["densify"] = densify_extras(max(3, args.steps // 10))
@@ -322,6 +325,22 @@ def half_extras(gL, gR, steps):
     m.close()
     return dict(full=f"{W2}x{H2}", reduced=f"{W}x{H}", D=D, vote_passes=2,
                 ms_per_frame=round(ms, 4), valid_frac=round(float(valid.float().mean()), 4))
+
+
+def contour_extras(steps):
+    """The depth contour filter of Sec. 5 on a seeded 1280x720 frame with
+    flows on the 640x360 grid: ms per frame and hysteresis launches."""
+    import torch
+    from paper_2203_02300_amd import ContourFilter, synth
+    d = synth.contour_inputs(1280, 720, 11)
+    t = {k: torch.from_numpy(d[k]).cuda() for k in ("rgb", "past", "future")}
+    f = ContourFilter(1280, 720)
+    ms = _time(lambda: f.run(t["rgb"], t["past"], t["future"]), steps)
+    B, _, _ = f.run(t["rgb"], t["past"], t["future"])
+    out = dict(ms_per_frame=round(ms, 4), hysteresis_launches=f.launches(),
+               contour_frac=round(float(B.float().mean()), 4))
+    f.close()
+    return out
 
 
 def densify_extras(n):

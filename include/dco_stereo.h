@@ -243,6 +243,47 @@ dco_status dco_densify_run(dco_densify* h, const float* Ds, const float* Dpre, c
  * either may be NULL).  Synchronises the stream. */
 dco_status dco_densify_stats(dco_densify* h, int* iters, double* rel_residual);
 
+/* ---- Depth contour extraction given the optical flows (Sec. 5) ---- */
+
+/* From the past and future flow fields of the middle frame (computed
+ * elsewhere, on the quarter-size grid w = W / 2, h = H / 2 as (U, V) float
+ * pairs) and the full-size colour frame:
+ *   r = |I| (correctly rounded); M = max(|r(p_right) - r(p)|, |r(p_bottom) - r(p)|)
+ *       (a missing neighbour gives 0)                                    (Eq. 6-8)
+ *   score = I(p1).e - I(p0).e with e = I(p) / |I(p)|, p1, p0 = p +- rint(e)
+ *       clamped (0 where I(p) = 0)                                       (Eq. 9-11)
+ *   Mfuse = M_past where score_past > score_future, M_future where lower,
+ *       the larger of the two where equal                               (Eq. 12)
+ *   Mn = the (2 box_radius + 1)^2 mean of Mfuse clipped to the grid, divided
+ *       by its maximum (0 when that is 0)                                (Sec. 5.2)
+ *   Canny on the census grey: 3x3 Sobel (replicated borders), G2 = gx^2 + gy^2;
+ *       suppression along the gradient's sector (horizontal when 128|gy| <
+ *       53|gx|, vertical when 128|gx| < 53|gy|, else the diagonal of sign(gx gy)),
+ *       keeping p when G2(p) > G2 before it and >= G2 after it; p dropped when
+ *       Mn(x / 2, y / 2) < T_depth; strong when G2 > T_high^2 max G2, weak when
+ *       G2 > T_low^2 max G2; weak pixels 8-connected to strong ones kept (Sec. 5.3)
+ *   B = the kept pixels (the depth contour B_dp of Eq. 16), MI = sqrt(G2 / max G2)
+ *       (the M_I of Eq. 17). */
+typedef struct {
+    float T_high, T_low, T_depth;  /* >= 0 (Sec. 7.2: 0.06, 0.03, 0.03) */
+    int box_radius;                /* 0..16 (default 2: a 5 x 5 box) */
+} dco_contour_params;
+typedef struct dco_contour dco_contour; /* opaque contour-extraction handle */
+
+dco_status dco_contour_default_params(dco_contour_params* out);
+/* Scratch for W x H frames (W, H >= 2); p may be NULL for the defaults. */
+dco_status dco_contour_create(dco_contour** out, int W, int H, const dco_contour_params* p,
+                              void* stream);
+void dco_contour_destroy(dco_contour* h);
+/* rgb: H x W x 3 uint8; past, future: h x w x 2 float (8-byte aligned);
+ * B: H x W uint8 (out, 0/1); MI: H x W float (out, optional); Mn: h x w
+ * float (out, optional).  Device pointers.  Synchronous: the host repeats
+ * hysteresis launches until one changes nothing. */
+dco_status dco_contour_run(dco_contour* h, const uint8_t* rgb, const float* past,
+                           const float* future, uint8_t* B, float* MI, float* Mn);
+/* Hysteresis launches of the last run (diagnostics). */
+dco_status dco_contour_launches(dco_contour* h, int* launches);
+
 /* ---- Batched matcher: many pairs of uneven size and disparity range ---- */
 
 /* Create a batched matcher for n pairs of sizes W[i] x H[i], disparity

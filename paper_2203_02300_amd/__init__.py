@@ -10,13 +10,14 @@ scene generator can be used without a GPU.
 """
 
 __all__ = ["StereoMatcher", "BatchMatcher", "DcoSoftArgmin", "soft_argmin_disparity",
-           "default_params", "Densifier"]
+           "default_params", "Densifier", "ContourFilter"]
 
 
 import importlib
 
 _LAZY = {"StereoMatcher": "api", "default_params": "api", "BatchMatcher": "batch",
-         "DcoSoftArgmin": "soft", "soft_argmin_disparity": "soft", "Densifier": "densify"}
+         "DcoSoftArgmin": "soft", "soft_argmin_disparity": "soft", "Densifier": "densify",
+         "ContourFilter": "contour"}
 
 
 def __getattr__(name):

@@ -20,6 +20,8 @@ EXPORTS = (
     "dco_batch_tile", "dco_soft_forward", "dco_soft_backward", "dco_vote_refine",
     "dco_stereo_match_half", "dco_densify_default_params", "dco_densify_create",
     "dco_densify_destroy", "dco_densify_run", "dco_densify_stats",
+    "dco_contour_default_params", "dco_contour_create", "dco_contour_destroy",
+    "dco_contour_run", "dco_contour_launches",
     "dco_status_string", "dco_last_error",
 )
 
@@ -49,6 +51,13 @@ class DensifyParams(C.Structure):
     _fields_ = [
         ("lambda_d", C.c_float), ("lambda_s", C.c_float), ("lambda_s2", C.c_float),
         ("tol", C.c_double), ("max_iters", C.c_int), ("iters_per_launch", C.c_int),
+    ]
+
+
+class ContourParams(C.Structure):
+    _fields_ = [
+        ("T_high", C.c_float), ("T_low", C.c_float), ("T_depth", C.c_float),
+        ("box_radius", C.c_int),
     ]
 
 
@@ -91,6 +100,11 @@ def lib():
         "dco_densify_destroy": (None, [P]),
         "dco_densify_run": (st, [P, P, P, P, P, P, P]),
         "dco_densify_stats": (st, [P, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+        "dco_contour_default_params": (st, [C.POINTER(ContourParams)]),
+        "dco_contour_create": (st, [C.POINTER(P), i, i, C.POINTER(ContourParams), P]),
+        "dco_contour_destroy": (None, [P]),
+        "dco_contour_run": (st, [P, P, P, P, P, P, P]),
+        "dco_contour_launches": (st, [P, C.POINTER(C.c_int)]),
         "dco_status_string": (C.c_char_p, [st]),
         "dco_last_error": (C.c_char_p, []),
     }

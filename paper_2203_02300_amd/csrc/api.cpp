@@ -297,7 +297,7 @@ dco_status need(const void* ptr, const char* what) {
     return DCO_OK;
 }
 
-static dco_status need_align(const void* ptr, size_t a, const char* what) {
+dco_status need_align(const void* ptr, size_t a, const char* what) {
     if (((uintptr_t)ptr) % a) {
         dco_set_error("%s must be %zu-byte aligned", what, a);
         return DCO_ERR_ARG;

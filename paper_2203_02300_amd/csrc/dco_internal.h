@@ -119,6 +119,7 @@ inline dco_status dev_alloc(T** p, size_t n) {
 
 // ---- host helpers shared by api.cpp and batch.cpp ----
 dco_status need(const void* ptr, const char* what);
+dco_status need_align(const void* ptr, size_t a, const char* what);
 dco_status check_params(const dco_params& p);
 dco_status check_shape(int W, int H, int D, const dco_params& p);
 void build_tables(const dco_params& p, std::vector<float>& tabA, std::vector<float>& tabC,
@@ -164,6 +165,24 @@ hipError_t launch_densify_setup(const DensifyBufs& b, const float* Ds, const flo
 hipError_t launch_densify_iters(const DensifyBufs& b, int W, int H, double tol, int n,
                                 hipStream_t st);
 hipError_t launch_densify_out(const DensifyBufs& b, int W, int H, float* D, hipStream_t st);
+// Depth contour extraction given the flows (Sec. 5): scratch of one frame
+// (full size W x H, flow grid w x h) and its launches.
+struct ContourBufs {
+    float* fused;        // w x h: Eq. 12 before the box filter
+    unsigned* box_max;   // largest box mean (float bits)
+    int* g2_max;         // largest G2
+    short2* g;           // W x H Sobel gradients
+    int* G2;             // W x H squared magnitudes
+    uint8_t* state[2];   // W x H: 0 none, 1 weak, 2 strong (hysteresis ping-pong)
+    int* changed;        // set by a hysteresis launch that changed a pixel
+};
+hipError_t launch_contour_maps(const float* past, const float* future, int w, int h, int R,
+                               const uint8_t* rgb, int W, int H, float Thigh, float Tlow,
+                               float Tdepth, const ContourBufs& b, float* Mn, float* MI,
+                               hipStream_t st);
+hipError_t launch_contour_hyst(const ContourBufs& b, int W, int H, int parity, hipStream_t st);
+hipError_t launch_contour_edges(const ContourBufs& b, int W, int H, int parity, uint8_t* B,
+                                hipStream_t st);
 // Arms and packed pixels of both views of B pairs (HWC images of 3 W H
 // bytes each, outputs of W H entries each, pair-major) in one launch.
 hipError_t launch_census_pairs(const uint8_t* rgbL, const uint8_t* rgbR, int B, int W, int H,

@@ -417,3 +417,26 @@ def densify_inputs(W=640, H=360, seed=7, fB=1000.0, keep=0.7):
                 Bdp=jump.astype(np.uint8), Mfuse=np.clip(Mfuse, 0, 1).astype(np.float32),
                 MI=np.clip(MI, 0, 1).astype(np.float32), depth=depth.astype(np.float32),
                 W=W, H=H, seed=seed)
+
+
+def contour_inputs(W=1280, H=720, seed=11):
+    """Inputs of the depth contour filter (Sec. 5): the middle colour frame
+    (a slanted-plane scene's left view, W x H x 3 uint8) and the past and
+    future optical flows on the quarter grid (H/2 x W/2 x 2 float32): the
+    foreground boxes of the scene move by +v towards the future frame and by
+    -v towards the past one, with the motion spread over a few pixels at the
+    box borders and N(0, 0.002) noise, while the background stays still."""
+    scene = make_slanted_pair(W, H, 64, seed, n_planes=4, n_boxes=3, dmin=4.0, dmax=40.0,
+                              noise_sigma=2.0)
+    rng = np.random.default_rng(seed + 2000)
+    h, w = H // 2, W // 2
+    disp = scene["disp"][: 2 * h : 2, : 2 * w : 2].astype(np.float64)
+    fg = disp > np.percentile(disp, 80)  # the nearest surfaces move
+    m = fg.astype(np.float64)
+    for _ in range(3):  # spread the motion over the borders
+        m = (m + np.roll(m, 1, 0) + np.roll(m, -1, 0) + np.roll(m, 1, 1) + np.roll(m, -1, 1)) / 5
+    v = rng.uniform(1.0, 4.0, 2)
+    fut = np.stack([m * v[0], m * v[1]], -1) + rng.normal(0, 0.002, (h, w, 2))
+    past = np.stack([-m * v[0], -m * v[1]], -1) + rng.normal(0, 0.002, (h, w, 2))
+    return dict(rgb=scene["left"], past=past.astype(np.float32), future=fut.astype(np.float32),
+                W=W, H=H, seed=seed)

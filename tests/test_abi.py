@@ -88,6 +88,9 @@ def test_null_arguments_rejected(L):
     assert L.dco_stereo_match_half(None, None, None, 2, 2, 1.0, None, None, None) == -1
     assert L.dco_densify_run(None, None, None, None, None, None, None) == -1
     assert L.dco_densify_create(None, 4, 4, None, None) == -1
+    assert L.dco_contour_create(None, 4, 4, None, None) == -1
+    assert L.dco_contour_run(None, None, None, None, None, None, None) == -1
+    L.dco_contour_destroy(None)
     L.dco_densify_destroy(None)
 
 
