@@ -62,6 +62,24 @@ __device__ inline float flow_score(const float2* F, int w, int h, int x, int y) 
     return f1 - f0;
 }
 
+// Largest v over the 256-thread block, then one atomic maximum per block
+// (the maximum does not depend on the order).
+template <typename T>
+__device__ inline void block_max_to(T v, T* out) {
+    __shared__ T red[4];
+    for (int o = 32; o > 0; o >>= 1) {
+        const T u = __shfl_xor(v, o, 64);
+        v = u > v ? u : v;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T m = red[0];
+        for (int k = 1; k < 4; ++k) m = red[k] > m ? red[k] : m;
+        atomicMax(out, m);
+    }
+}
+
 // Eq. 12 per pixel of the flow grid (equal scores keep the larger amplitude).
 __global__ __launch_bounds__(256) void k_fuse(const float2* __restrict__ past,
                                               const float2* __restrict__ future, int w, int h,
@@ -80,18 +98,21 @@ __global__ __launch_bounds__(256) void k_fuse(const float2* __restrict__ past,
 __global__ __launch_bounds__(256) void k_box(const float* __restrict__ fused, int w, int h, int R,
                                              float* __restrict__ box, unsigned* __restrict__ mx) {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= w * h) return;
-    const int y = i / w, x = i - y * w;
-    float s = 0.0f;
-    int n = 0;
-    for (int yy = max(y - R, 0); yy <= min(y + R, h - 1); ++yy)
-        for (int xx = max(x - R, 0); xx <= min(x + R, w - 1); ++xx) {
-            s += fused[yy * w + xx];
-            ++n;
-        }
-    const float v = s / (float)n;
-    box[i] = v;
-    atomicMax(mx, __float_as_uint(v));
+    unsigned bits = 0u;  // the bits of a non-negative float order like the float
+    if (i < w * h) {
+        const int y = i / w, x = i - y * w;
+        float s = 0.0f;
+        int n = 0;
+        for (int yy = max(y - R, 0); yy <= min(y + R, h - 1); ++yy)
+            for (int xx = max(x - R, 0); xx <= min(x + R, w - 1); ++xx) {
+                s += fused[yy * w + xx];
+                ++n;
+            }
+        const float v = s / (float)n;
+        box[i] = v;
+        bits = __float_as_uint(v);
+    }
+    block_max_to(bits, mx);
 }
 
 __global__ __launch_bounds__(256) void k_norm(float* __restrict__ box, int n,
@@ -108,21 +129,23 @@ __global__ __launch_bounds__(256) void k_sobel(const uint8_t* __restrict__ rgb, 
                                                short2* __restrict__ g, int* __restrict__ G2,
                                                int* __restrict__ mx) {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= W * H) return;
-    const int y = i / W, x = i - y * W;
-    auto Y = [&](int xx, int yy) {
-        const size_t q = (size_t)dco::clampi(yy, 0, H - 1) * W + dco::clampi(xx, 0, W - 1);
-        return (int)dco::grey_of((uint32_t)rgb[3 * q] | (uint32_t)rgb[3 * q + 1] << 8 |
-                                 (uint32_t)rgb[3 * q + 2] << 16);
-    };
-    const int a = Y(x + 1, y - 1) + 2 * Y(x + 1, y) + Y(x + 1, y + 1) - Y(x - 1, y - 1) -
-                  2 * Y(x - 1, y) - Y(x - 1, y + 1);
-    const int b = Y(x - 1, y + 1) + 2 * Y(x, y + 1) + Y(x + 1, y + 1) - Y(x - 1, y - 1) -
-                  2 * Y(x, y - 1) - Y(x + 1, y - 1);
-    g[i] = make_short2((short)a, (short)b);
-    const int v = a * a + b * b;
-    G2[i] = v;
-    atomicMax(mx, v);
+    int v = 0;
+    if (i < W * H) {
+        const int y = i / W, x = i - y * W;
+        auto Y = [&](int xx, int yy) {
+            const size_t q = (size_t)dco::clampi(yy, 0, H - 1) * W + dco::clampi(xx, 0, W - 1);
+            return (int)dco::grey_of((uint32_t)rgb[3 * q] | (uint32_t)rgb[3 * q + 1] << 8 |
+                                     (uint32_t)rgb[3 * q + 2] << 16);
+        };
+        const int a = Y(x + 1, y - 1) + 2 * Y(x + 1, y) + Y(x + 1, y + 1) - Y(x - 1, y - 1) -
+                      2 * Y(x - 1, y) - Y(x - 1, y + 1);
+        const int b = Y(x - 1, y + 1) + 2 * Y(x, y + 1) + Y(x + 1, y + 1) - Y(x - 1, y - 1) -
+                      2 * Y(x, y - 1) - Y(x + 1, y - 1);
+        g[i] = make_short2((short)a, (short)b);
+        v = a * a + b * b;
+        G2[i] = v;
+    }
+    block_max_to(v, mx);
 }
 
 // Suppression along the gradient's sector, the depth gate on the flow grid,
