@@ -92,7 +92,7 @@ def main():
     args = ap.parse_args()
     want = set() if args.no_extras else {e for e in args.extras.split(",") if e}
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(pairs would shard across GPUs with no communication); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)

@@ -340,7 +340,7 @@ void orc_vote_finish(const float* agg, const int16_t* dv, int W, int H, int D, i
 
 /* ------------------------------------------------------------------------
  * Depth contour extraction given the two optical flow fields (Sec. 5).
- * The flows are computed elsewhere (DIS flow is not part of this build);
+ * The flows are computed elsewhere (the DIS flow method is not in this library);
  * they arrive on the quarter-size grid w x h as (U, V) pairs, float.
  * ------------------------------------------------------------------------ */
 
