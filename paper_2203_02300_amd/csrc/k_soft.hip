@@ -218,28 +218,14 @@ __device__ inline void prefix_row(const uint4* pl, const uint4* pr, const float*
     __builtin_amdgcn_wave_barrier();
 }
 
-// Adjoint of a row range sum at x': the pixels x whose horizontal range
-// covers x' are x' itself, x' + k with l(x' + k) >= k and x' - k with
-// r(x' - k) >= k (k = 1 .. kLMax); added in a fixed order.  lr holds the
-// arms of the row as bytes (l, r); row and lr are zero-padded by kLMax.
-__device__ inline float row_adjoint(const float* rowp, const uchar2* lrp, int xp) {
-    float s = rowp[xp];
-#pragma unroll
-    for (int k = 1; k <= kLMax; ++k) {
-        s += lrp[xp + k].x >= k ? rowp[xp + k] : 0.0f;
-        s += lrp[xp - k].y >= k ? rowp[xp - k] : 0.0f;
-    }
-    return s;
-}
-
 // Bytes of dynamic LDS per wavefront: forward (one FP64 prefix), gradient
-// (two) and adjoint (padded row + padded arms).
+// (two) and adjoint (64-bit difference array, the row, its arms).
 __host__ __device__ inline size_t row_bytes(int W) { return ((size_t)W * 4 + 15) / 16 * 16; }
 __host__ __device__ inline size_t prefix_bytes(int W) { return ((size_t)(W + 1) * 8 + 15) / 16 * 16; }
 inline size_t row_lds_fwd(int W) { return prefix_bytes(W); }
 inline size_t row_lds_grad(int W) { return 2 * prefix_bytes(W); }
 inline size_t row_lds_adj(int W) {
-    return row_bytes(W + 2 * kLMax) + (size_t)(W + 2 * kLMax) * 2;
+    return ((size_t)(W + 1) * 8 + 15) / 16 * 16 + row_bytes(W) + ((size_t)W * 2 + 15) / 16 * 16;
 }
 
 // Lets a kernel take `bytes` of dynamic LDS (above the default limit for
@@ -357,6 +343,11 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hgrad(SoftGeom g, SoftI
 //   G_A2 / N2 = g w (dhat - d) / (T N2),   dLoss/dT term = g w (d - dhat) A2 / T^2;
 // out = the adjoint of A2's row range sums applied to G_A2 / N2 (G_E2), and
 // the temperature terms of the row summed into one FP64 value per row.
+// The adjoint scatters each G(x) as +G at x - l(x) and -G after x + r(x)
+// into a difference array and prefix-sums it.  The array holds 64-bit
+// integers: G(x) 2^k rounded, with 2^k chosen from the row's largest |G| so
+// that no sum can overflow, so the scatter's LDS atomic adds give the same
+// bits in any order; the result is converted back with 2^-k.
 __global__ __launch_bounds__(64 * kRowWaves) void k_soft_seed_adj(
     SoftGeom g, const float* __restrict__ A2, const float* __restrict__ theta,
     const float* __restrict__ dhat, const float* __restrict__ lse,
@@ -365,25 +356,27 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_seed_adj(
     extern __shared__ __align__(16) unsigned char dyn[];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, W = g.W;
     unsigned char* mine = dyn + w * lds_wave;
-    float* row = reinterpret_cast<float*>(mine);
-    uchar2* lr = reinterpret_cast<uchar2*>(mine + row_bytes(W + 2 * kLMax));
+    long long* Dq = reinterpret_cast<long long*>(mine);  // W + 1 entries
+    float* row = reinterpret_cast<float*>(mine + ((size_t)(W + 1) * 8 + 15) / 16 * 16);
+    uchar2* lr = reinterpret_cast<uchar2*>(reinterpret_cast<unsigned char*>(row) + row_bytes(W));
     const float T = theta[2], invT = 1.0f / T;
     const size_t P = (size_t)W * g.H;
     const int nrows = g.B * g.D * g.H;
     const int r0 = (blockIdx.x * kRowWaves + w) * kRowsPerWave;
-    const int Wp = W + 2 * kLMax;
+    const int c = (W + 63) / 64, x0r = lane * c, nr = max(0, min(c, W - x0r));
     for (int rid = r0; rid < min(nrows, r0 + kRowsPerWave); ++rid) {
         int b, d, y;
         row_of(rid, g.D, g.H, b, d, y);
         const size_t base = ((size_t)b * g.D + d) * P + (size_t)y * W;
         const size_t pix = b * P + (size_t)y * W;
         double acc = 0.0;
-        for (int x0 = 0; x0 < Wp; x0 += 64 * kRowBatch) {  // padded index x + kLMax
+        float gmax = 0.0f;
+        for (int x0 = 0; x0 < W; x0 += 64 * kRowBatch) {
             float a2[kRowBatch], gp[kRowBatch], dh[kRowBatch], l[kRowBatch], n2[kRowBatch];
             uint32_t a[kRowBatch];
 #pragma unroll
             for (int j = 0; j < kRowBatch; ++j) {
-                const size_t xc = (size_t)min(max(x0 + 64 * j + lane - kLMax, 0), W - 1);
+                const size_t xc = (size_t)min(x0 + 64 * j + lane, W - 1);
                 a2[j] = A2[base + xc];
                 gp[j] = gdhat[pix + xc];
                 dh[j] = dhat[pix + xc];
@@ -393,23 +386,49 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_seed_adj(
             }
 #pragma unroll
             for (int j = 0; j < kRowBatch; ++j) {
-                const int i = x0 + 64 * j + lane, x = i - kLMax;
-                const bool in_row = x >= 0 && x < W;
-                const float wgt = expf(-a2[j] * invT - l[j]);
-                const float G = gp[j] * wgt * (dh[j] - (float)d) * invT / n2[j];
-                if (in_row)
+                const int x = x0 + 64 * j + lane;
+                if (x < W) {
+                    const float wgt = expf(-a2[j] * invT - l[j]);
+                    const float G = gp[j] * wgt * (dh[j] - (float)d) * invT / n2[j];
                     acc += (double)(gp[j] * wgt * ((float)d - dh[j]) * a2[j]) *
                            (double)(invT * invT);
-                if (i < Wp) {
-                    row[i] = in_row ? G : 0.0f;
-                    lr[i] = in_row ? make_uchar2((unsigned char)arm(a[j], 0),
-                                                 (unsigned char)arm(a[j], 1))
-                                   : make_uchar2(0, 0);
+                    row[x] = G;
+                    lr[x] = make_uchar2((unsigned char)arm(a[j], 0), (unsigned char)arm(a[j], 1));
+                    gmax = fmaxf(gmax, fabsf(G));
                 }
             }
         }
+        for (int o = 32; o > 0; o >>= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, o, 64));
+        for (int x = lane; x <= W; x += 64) Dq[x] = 0;
         __builtin_amdgcn_wave_barrier();
-        for (int x = lane; x < W; x += 64) out[base + x] = row_adjoint(row + kLMax, lr + kLMax, x);
+        // |G| < 2^(e+1) with e the exponent of the largest; 2^k G < 2^45, and
+        // a pixel sums at most 2 kLMax + 1 of them: far below 2^63
+        const int e = gmax > 0.0f ? ilogbf(gmax) : 0;
+        const double up = ldexp(1.0, 44 - e), down = ldexp(1.0, e - 44);
+        for (int x = lane; x < W; x += 64) {
+            const long long q = llrint((double)row[x] * up);
+            const uchar2 a = lr[x];
+            atomicAdd(reinterpret_cast<unsigned long long*>(&Dq[x - a.x]), (unsigned long long)q);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&Dq[x + a.y + 1]),
+                      (unsigned long long)(-q));
+        }
+        __builtin_amdgcn_wave_barrier();
+        // prefix of the difference array: each lane a contiguous run, run
+        // totals scanned across the wavefront (exact integers)
+        long long run = 0;
+        for (int k = 0; k < nr; ++k) run += Dq[x0r + k];
+        long long inc = run;
+        for (int off = 1; off < 64; off <<= 1) {
+            const long long v = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += v;
+        }
+        long long p = inc - run;
+        for (int k = 0; k < nr; ++k) {
+            p += Dq[x0r + k];
+            row[x0r + k] = (float)((double)p * down);
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int x = lane; x < W; x += 64) out[base + x] = row[x];
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
         if (lane == 0) partT[rid] = acc;
         __builtin_amdgcn_wave_barrier();
