@@ -93,11 +93,25 @@ __device__ inline void census_tile(const uint8_t* __restrict__ rgb, int W, int H
                                    uint32_t* __restrict__ arms, uint32_t* __restrict__ rgb_packed,
                                    uint4* __restrict__ pix, int x0, int y0, CensusLds& S) {
     const int t = threadIdx.x;
-    for (int i = t; i < kCenRW * kCenRH; i += 256) {
-        int ry = i / kCenRW, rx = i - ry * kCenRW;
-        int gx = clampi(x0 - kLMax + rx, 0, W - 1), gy = clampi(y0 - kLMax + ry, 0, H - 1);
-        const uint8_t* p = rgb + 3 * ((size_t)gy * W + gx);
-        S.rgb[ry][rx] = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
+    {   // stage the region: every load issued before any is stored
+        constexpr int kN = (kCenRW * kCenRH + 255) / 256;
+        uint32_t v[kN];
+#pragma unroll
+        for (int k = 0; k < kN; ++k) {
+            const int i = min(t + 256 * k, kCenRW * kCenRH - 1);
+            const int ry = i / kCenRW, rx = i - ry * kCenRW;
+            const int gx = clampi(x0 - kLMax + rx, 0, W - 1), gy = clampi(y0 - kLMax + ry, 0, H - 1);
+            const uint8_t* p = rgb + 3 * ((size_t)gy * W + gx);
+            v[k] = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
+        }
+#pragma unroll
+        for (int k = 0; k < kN; ++k) {
+            const int i = t + 256 * k;
+            if (i < kCenRW * kCenRH) {
+                const int ry = i / kCenRW;
+                S.rgb[ry][i - ry * kCenRW] = v[k];
+            }
+        }
     }
     __syncthreads();
     for (int i = t; i < kCenGW * kCenGH; i += 256) {
@@ -226,15 +240,29 @@ struct GeomLds {
 __device__ inline void geometry_tile(const uint32_t* __restrict__ arms, int W, int H, int iters,
                                      const AggRecords& rec, int x0, int y0, GeomLds& S) {
     const int t = threadIdx.x;
-    for (int i = t; i < kGeoRW * kGeoRH; i += 256) {
-        const int ry = i / kGeoRW, rx = i - ry * kGeoRW;
-        const int x = x0 - kLMax + rx, y = y0 - kLMax + ry;
-        uint32_t hv = 0;
-        if (x >= 0 && x < W && y >= 0 && y < H) {
-            const uint32_t a = arms[(size_t)y * W + x];
-            hv = ((a & 0xff) + ((a >> 8) & 0xff) + 1) | ((a >> 16 & 0xff) + (a >> 24) + 1) << 16;
+    {   // stage the arms: every load issued before any is used (clamped addresses)
+        constexpr int kN = (kGeoRW * kGeoRH + 255) / 256;
+        uint32_t v[kN];
+#pragma unroll
+        for (int k = 0; k < kN; ++k) {
+            const int i = min(t + 256 * k, kGeoRW * kGeoRH - 1);
+            const int ry = i / kGeoRW, rx = i - ry * kGeoRW;
+            const int x = clampi(x0 - kLMax + rx, 0, W - 1), y = clampi(y0 - kLMax + ry, 0, H - 1);
+            v[k] = arms[(size_t)y * W + x];
         }
-        S.hv[ry][rx] = hv;
+#pragma unroll
+        for (int k = 0; k < kN; ++k) {
+            const int i = t + 256 * k;
+            if (i < kGeoRW * kGeoRH) {
+                const int ry = i / kGeoRW, rx = i - ry * kGeoRW;
+                const int x = x0 - kLMax + rx, y = y0 - kLMax + ry;
+                const uint32_t a = v[k];
+                S.hv[ry][rx] = x >= 0 && x < W && y >= 0 && y < H
+                                   ? ((a & 0xff) + ((a >> 8) & 0xff) + 1) |
+                                         ((a >> 16 & 0xff) + (a >> 24) + 1) << 16
+                                   : 0u;
+            }
+        }
     }
     __syncthreads();
     if (t < kGeoTW) {  // column prefixes of h
