@@ -113,6 +113,22 @@ def test_densify_defaults_and_bad_params(L):
     L.dco_stereo_destroy(None)
 
 
+def test_contour_defaults_and_bad_params(L):
+    p = _lib.ContourParams()
+    assert L.dco_contour_default_params(C.byref(p)) == 0
+    assert abs(p.T_high - 0.06) < 1e-8 and abs(p.T_low - 0.03) < 1e-8
+    assert abs(p.T_depth - 0.03) < 1e-8 and p.box_radius == 2
+    for k, v in (("T_high", -1.0), ("T_low", float("inf")), ("box_radius", 17),
+                 ("box_radius", -1)):
+        q = _lib.ContourParams()
+        L.dco_contour_default_params(C.byref(q))
+        setattr(q, k, v)
+        h = C.c_void_p()
+        assert L.dco_contour_create(C.byref(h), 8, 8, C.byref(q), None) == -1 and not h.value
+    h = C.c_void_p()
+    assert L.dco_contour_create(C.byref(h), 1, 8, None, None) == -2
+
+
 def test_status_strings(L):
     assert L.dco_status_string(0) == b"ok"
     assert L.dco_status_string(-4) == b"out of device memory"
