@@ -83,3 +83,12 @@ def test_contour_repeated_runs_are_identical(torch_mod):
         b = [host(t) for t in f.run(dev(d["rgb"]), dev(d["past"]), dev(d["future"]))]
     for x, y in zip(a, b):
         assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
+
+
+@pytest.mark.parametrize("W,H", [(2, 2), (3, 5), (70, 17)])
+def test_contour_small_and_odd_frames(torch_mod, W, H):
+    rng = np.random.default_rng(W * 31 + H)
+    rgb = rng.integers(0, 256, (H, W, 3), dtype=np.uint8)
+    past = rng.normal(0, 2, (H // 2, W // 2, 2)).astype(np.float32)
+    future = rng.normal(0, 2, (H // 2, W // 2, 2)).astype(np.float32)
+    _check(rgb, past, future)

@@ -75,3 +75,18 @@ def test_densify_degenerate_inputs(torch_mod):
     with Densifier(W, H, max_iters=0) as z:
         D = host(z.run(dev(Ds), dev(z0.astype(np.uint8)), dev(z0), dev(z0)))
         assert np.all(D == 0)
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (1, 37), (53, 1), (3, 2)])
+def test_densify_thin_grids(torch_mod, W, H):
+    from paper_2203_02300_amd import Densifier
+    rng = np.random.default_rng(W * 100 + H)
+    Ds = np.where(rng.random((H, W)) < 0.4, rng.uniform(1, 5, (H, W)), 0).astype(np.float32)
+    Ds.flat[0] = 2.0
+    B = (rng.random((H, W)) < 0.2).astype(np.uint8)
+    Mf = rng.random((H, W)).astype(np.float32)
+    MI = rng.random((H, W)).astype(np.float32)
+    want = dz.densify(Ds, None, B, Mf, MI)
+    with Densifier(W, H) as z:
+        D = host(z.run(dev(Ds), dev(B), dev(Mf), dev(MI)))
+    assert np.abs(D - want).max() <= 1e-5 * max(np.abs(want).max(), 1e-30)

@@ -70,3 +70,15 @@ def test_match_half_rejects_mismatched_sizes(torch_mod):
                                               C.c_void_p(valid.data_ptr()),
                                               C.c_void_p(depth.data_ptr()))
         assert st == -1 and b"fB" in _lib.lib().dco_last_error()
+
+
+@pytest.mark.parametrize("W2,H2,D", [(19, 15, 2), (67, 17, 8)])
+def test_match_half_edge_shapes(torch_mod, W2, H2, D):
+    from paper_2203_02300_amd import StereoMatcher, synth
+    p = synth.make_shift_pair(W2, H2, 2, 7 + W2, texture="patches")
+    want_d, want_depth, want_valid = oracle.match_half(p["left"], p["right"], D, 10.0)
+    with StereoMatcher(W2 // 2, H2 // 2, D) as m:
+        d2, valid, depth = m.match_half(dev(p["left"]), dev(p["right"]), 10.0)
+        assert np.array_equal(host(valid), want_valid)
+        assert np.array_equal(host(d2).view(np.uint32), want_d.view(np.uint32))
+        assert np.array_equal(host(depth).view(np.uint32), want_depth.view(np.uint32))

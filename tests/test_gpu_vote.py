@@ -126,3 +126,14 @@ def test_batch_rejects_vote(torch_mod):
     b = C.c_void_p()
     assert L.dco_batch_create(C.byref(b), 1, W, H, D, C.byref(p), None) == -1
     assert b"vote" in L.dco_last_error()
+
+
+@pytest.mark.parametrize("W,H,D", [(9, 7, 1), (33, 7, 8), (190, 9, 60)])
+def test_vote_edge_shapes(torch_mod, W, H, D):
+    from paper_2203_02300_amd import StereoMatcher, synth
+    p = synth.make_shift_pair(W, H, min(3, D - 1) if D > 1 else 0, 40 + W, texture="patches")
+    want_disp, want_valid, _, _ = oracle.match(p["left"], p["right"], D, vote_iters=2)
+    with StereoMatcher(W, H, D, vote_iters=2) as m:
+        disp, valid = m.match(dev(p["left"]), dev(p["right"]))
+        assert np.array_equal(host(valid), want_valid)
+        assert np.array_equal(host(disp).view(np.uint32), want_disp.view(np.uint32))
