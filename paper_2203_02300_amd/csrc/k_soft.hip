@@ -14,15 +14,18 @@
 // Backward, given g = dLoss/d dhat:
 //   G_A2  = g w (dhat - d) / T,   dLoss/dT = sum g w (d - dhat) A2 / T^2
 // then the adjoint of each range sum: an output that summed a range hands its
-// adjoint back to every pixel of that range.  The first row adjoint is a
-// gather over the (at most 2 kLMax + 1) candidate pixels whose range can
-// cover a pixel; column adjoints are FP64 difference arrays streamed down each
-// column by one thread.  The last row adjoint is never formed: with
+// adjoint back to every pixel of that range.  The first row adjoint scatters
+// each G(x) into a 64-bit fixed-point difference array over the row (integer
+// adds, so their order does not matter); column adjoints are FP64 difference
+// arrays streamed down each column by one thread.  The last row adjoint is
+// never formed: with
 // E1 = H c,  sum_p (H^T G)(p) dc/dlambda(p) = sum_x G(x) (H dc/dlambda)(x),
 // so the row range sums of the two cost derivatives are dotted with G:
 //   dLoss/dlambda_AD     = sum G_E1 . H (alpha d(1 - exp(-(s/3)/lambda_AD))/dlambda_AD)
 //   dLoss/dlambda_census = sum G_E1 . H ((1 - alpha) d(1 - exp(-h/lambda_census))/dlambda_census)
-// with fixed-order two-level reductions.  There are no atomics.
+// with fixed-order two-level reductions.  The only atomics are LDS adds whose
+// result does not depend on their order (integers), or that one thread makes
+// to its own column in program order.
 //
 // Layout: volumes are B x D x H x W float in handle scratch; arms and the
 // packed pixels (census, RGB, L_min) are per pair B x H x W.  Row passes run
@@ -436,13 +439,15 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_seed_adj(
 }
 
 // Column passes, streamed down each column: one thread per column, kSoftCols
-// columns per workgroup, rows in order.  FP64 running sums in an LDS ring of
-// kSoftRing rows per column keep every range sum exact to FP32 rounding of
-// the final value, and each thread touches only its own column, so the result
-// does not depend on scheduling.
-constexpr int kSoftCols = 128;
-constexpr int kSoftRing = 2 * kLMax + 2;
-constexpr int kSoftPre = 8;  // rows per load batch (one batch ahead)
+// columns per workgroup, rows in batches of kSoftPre.  FP64 running sums in an
+// LDS ring of kSoftRing rows per column keep every range sum exact to FP32
+// rounding of the final value, and each thread touches only its own column,
+// so the result does not depend on scheduling.  The ring keeps kSoftPre - 1
+// rows more than a range needs, so a batch's ring writes can all go before its
+// ring reads: one LDS round trip per batch instead of one per row.
+constexpr int kSoftCols = 64;
+constexpr int kSoftPre = 8;                          // rows per batch
+constexpr int kSoftRing = 2 * kLMax + 1 + kSoftPre;  // 43
 
 // kSoftPre rows of a column pass's per-row inputs, loaded one batch ahead of
 // the rows being processed (clamped rows: every load is unconditional).
@@ -465,8 +470,21 @@ __device__ inline void col_load(const float* src, const uint32_t* arms, const fl
     }
 }
 
+// Ring slot `back` rows before slot s (0 <= back < kSoftRing).
+__device__ inline int ring_back(int s, int back) {
+    const int r = s - back;
+    return r < 0 ? r + kSoftRing : r;
+}
+__device__ inline int ring_fwd(int s, int fwd) {
+    const int r = s + fwd;
+    return r >= kSoftRing ? r - kSoftRing : r;
+}
+
 // out(y) = (sum of in over the vertical range of pixel y) [/ scale(y)], with
-// the running column prefix P: out(y) = P(y + dn) - P(y - u - 1).
+// the running column prefix P: out(y) = P(y + dn) - P(y - u - 1).  Row y of a
+// batch reads prefixes back to row y - 2 kLMax - 1; the batch's writes reach
+// row y0 + kSoftPre - 1, whose slot last held row y0 + kSoftPre - 1 - kSoftRing
+// = y0 - 2 kLMax - 2: older than any row the batch reads.
 template <bool kScale>
 __global__ __launch_bounds__(kSoftCols) void k_soft_vs(SoftGeom g, const float* __restrict__ in,
                                                        const float* __restrict__ scale,
@@ -483,7 +501,7 @@ __global__ __launch_bounds__(kSoftCols) void k_soft_vs(SoftGeom g, const float* 
     float* dst = out + (size_t)bd * P + xc;
     const int rows = g.H + kLMax;
     double acc = 0.0;
-    int slot = 0;  // ring slot of row y (y mod kSoftRing)
+    int slot = 0;  // ring slot of row y0 (y0 mod kSoftRing)
     ColBatch cur, nxt;
     col_load<kScale, false>(src, arms, sc, g.W, g.H, 0, cur);
     for (int y0 = 0; y0 < rows; y0 += kSoftPre) {
@@ -491,29 +509,40 @@ __global__ __launch_bounds__(kSoftCols) void k_soft_vs(SoftGeom g, const float* 
             col_load<kScale, false>(src, arms, sc, g.W, g.H, y0 + kSoftPre, nxt);
 #pragma unroll
         for (int k = 0; k < kSoftPre; ++k) {
-            const int y = y0 + k, yo = y - kLMax;
-            acc += y < g.H ? (double)cur.v[k] : 0.0;
-            ring[slot][t] = acc;
-            if (yo >= 0 && yo < g.H) {
-                const int u = arm(cur.a[k], 2), dn = arm(cur.a[k], 3);
-                // P(yo + dn) is kLMax - dn rows back, P(yo - u - 1) kLMax + u + 1
-                int sh = slot - (kLMax - dn), sl = slot - (kLMax + u + 1);
-                sh += sh < 0 ? kSoftRing : 0;
-                sl += sl < 0 ? kSoftRing : 0;
-                const double lo = yo - u - 1 >= 0 ? ring[sl][t] : 0.0;
-                const float r = (float)(ring[sh][t] - lo);
-                if (ok) dst[(size_t)yo * g.W] = kScale ? r / cur.s[k] : r;
-            }
-            slot = slot + 1 == kSoftRing ? 0 : slot + 1;
+            acc += y0 + k < g.H ? (double)cur.v[k] : 0.0;
+            ring[ring_fwd(slot, k)][t] = acc;
         }
+        // Rows whose output row yo is outside [0, H) read slots not yet (or
+        // no longer) meaningful; their results are discarded.
+        double hi[kSoftPre], lo[kSoftPre];
+#pragma unroll
+        for (int k = 0; k < kSoftPre; ++k) {
+            const int u = arm(cur.a[k], 2), dn = arm(cur.a[k], 3);
+            const int sk = ring_fwd(slot, k);
+            hi[k] = ring[ring_back(sk, kLMax - dn)][t];
+            lo[k] = ring[ring_back(sk, kLMax + u + 1)][t];
+        }
+#pragma unroll
+        for (int k = 0; k < kSoftPre; ++k) {
+            const int yo = y0 + k - kLMax;
+            const int u = arm(cur.a[k], 2);
+            const float r = (float)(hi[k] - (yo - u - 1 >= 0 ? lo[k] : 0.0));
+            if (ok && yo >= 0 && yo < g.H) dst[(size_t)yo * g.W] = kScale ? r / cur.s[k] : r;
+        }
+        slot = ring_fwd(slot, kSoftPre);
         cur = nxt;
     }
 }
 
 // Adjoint of k_soft_vs: out(y') = sum over pixels y whose vertical range
 // covers y' of in(y), [/ scale(y')].  Each y adds in(y) at row y - u and
-// subtracts it after row y + dn in a ring of differences; row y' is final
-// kLMax rows later and its running sum is the output.
+// subtracts it after row y + dn in a ring of differences (LDS FP64 adds that
+// return nothing, in program order per column); row y' is final kLMax rows
+// later and its running sum is the output.  A batch first makes all its
+// adds, then finishes its rows y0 - kLMax ... y0 + kSoftPre - 1 - kLMax: the
+// adds of a later row of the batch start at or after the row it finishes next
+// and end at most kSoftRing - 1 rows after it, so none lands in a slot that
+// is still to be read as that row.
 template <bool kScale>
 __global__ __launch_bounds__(kSoftCols) void k_soft_vsa(SoftGeom g, const float* __restrict__ in,
                                                         const float* __restrict__ scale,
@@ -531,7 +560,7 @@ __global__ __launch_bounds__(kSoftCols) void k_soft_vsa(SoftGeom g, const float*
     for (int i = 0; i < kSoftRing; ++i) ring[i][t] = 0.0;
     const int rows = g.H + kLMax;
     double run = 0.0;
-    int slot = 0;  // ring slot of row y
+    int slot = 0;  // ring slot of row y0
     ColBatch cur, nxt;
     col_load<kScale, true>(src, arms, sc, g.W, g.H, 0, cur);
     for (int y0 = 0; y0 < rows; y0 += kSoftPre) {
@@ -539,25 +568,33 @@ __global__ __launch_bounds__(kSoftCols) void k_soft_vsa(SoftGeom g, const float*
             col_load<kScale, true>(src, arms, sc, g.W, g.H, y0 + kSoftPre, nxt);
 #pragma unroll
         for (int k = 0; k < kSoftPre; ++k) {
-            const int y = y0 + k, yo = y - kLMax;
-            if (y < g.H) {  // uniform
+            if (y0 + k < g.H) {  // uniform
                 const int u = arm(cur.a[k], 2), dn = arm(cur.a[k], 3);
-                int sa = slot - u, se = slot + dn + 1;
-                sa += sa < 0 ? kSoftRing : 0;
-                se -= se >= kSoftRing ? kSoftRing : 0;
-                ring[sa][t] += (double)cur.v[k];
-                ring[se][t] -= (double)cur.v[k];
+                const int sk = ring_fwd(slot, k);
+                const double v = (double)cur.v[k];
+                __hip_atomic_fetch_add(&ring[ring_back(sk, u)][t], v, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(&ring[ring_fwd(sk, dn + 1)][t], -v, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-            if (yo >= 0) {  // row yo is final: its slot is kLMax rows back
-                int so = slot - kLMax;
-                so += so < 0 ? kSoftRing : 0;
-                run += ring[so][t];
-                ring[so][t] = 0.0;  // reused for row yo + kSoftRing
+        }
+        double dv[kSoftPre];
+#pragma unroll
+        for (int k = 0; k < kSoftPre; ++k) {
+            const int so = ring_back(ring_fwd(slot, k), kLMax);
+            dv[k] = __hip_atomic_exchange(&ring[so][t], 0.0, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+#pragma unroll
+        for (int k = 0; k < kSoftPre; ++k) {
+            const int yo = y0 + k - kLMax;
+            if (yo >= 0) {  // uniform: row yo is final
+                run += dv[k];
                 if (ok && yo < g.H)
                     dst[(size_t)yo * g.W] = kScale ? (float)run / cur.s[k] : (float)run;
             }
-            slot = slot + 1 == kSoftRing ? 0 : slot + 1;
         }
+        slot = ring_fwd(slot, kSoftPre);
         cur = nxt;
     }
 }
