@@ -11,11 +11,13 @@ The JSON line carries:
   value        Mpix*disp/s = W*H*D / seconds per step / 1e6
   roofline     the dominant kernel (largest share of the step) against its
                bound, with its duration from HIP events recorded by the
-               library on its own stream over the timed steps
+               library on its own stream over a second pass of the timed
+               steps (the events stay out of the headline loop)
   cpu_baseline the CPU oracle (single thread) on a bounded sample of the
                same pair
-  extras       (with --extras, default on) the staged four-call path per
-               stage against the HBM roofline
+  extras       stage times, the median / p90 of single-step times, and
+               (with --extras, default on) the staged four-call path per
+               stage against the HBM roofline and the other paths
 """
 from __future__ import annotations
 
@@ -57,6 +59,23 @@ def measured_traffic():
         return int(fields["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def step_distribution(m, gL, gR, disp, valid, steps):
+    """Median and 90th percentile of single-step times (HIP events on the
+    stream the matcher runs on), measured after the timed loop."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for a, b in ev:
+        a.record()
+        m.match(gL, gR, disp, valid)
+        b.record()
+    torch.cuda.synchronize()
+    t = np.sort([a.elapsed_time(b) for a, b in ev])
+    return dict(median=round(float(np.median(t)), 4),
+                p90=round(float(t[min(len(t) - 1, int(np.ceil(0.9 * len(t))) - 1)]), 4),
+                min=round(float(t[0]), 4), n=len(t))
 
 
 def log(msg):
@@ -127,15 +146,21 @@ def main():
     torch.cuda.synchronize()
     log(f"bench: warmup done, timing {args.steps} steps")
 
-    check(lib().dco_stereo_profile(m._h, 1))
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         m.match(gL, gR, disp, valid)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    check(lib().dco_stereo_profile(m._h, 0))
     ms_step = (t1 - t0) * 1e3 / args.steps
+    # Stage times come from a second pass of the same steps with the
+    # library's per-stage HIP events on its stream: ten event records per
+    # step cost ~0.05 ms, so they stay out of the headline loop.
+    log("bench: timing the stages (library HIP events)")
+    check(lib().dco_stereo_profile(m._h, 1))
+    for _ in range(args.steps):
+        m.match(gL, gR, disp, valid)
+    torch.cuda.synchronize()
+    check(lib().dco_stereo_profile(m._h, 0))
     stage_ms = (C.c_float * len(STAGES))()
     calls = C.c_int()
     check(lib().dco_stereo_stage_times(m._h, stage_ms, len(STAGES), C.byref(calls)))
@@ -156,7 +181,8 @@ def main():
                     kernel="k_agg_pair<2>", kernel_ms=round(agg_ms, 4),
                     ops_per_pd=ops_per_unit, units_per_launch=2 * V)
 
-    extras = {"stage_ms": {n: round(t, 4) for n, t in zip(STAGES, per_call)}}
+    extras = {"stage_ms": {n: round(t, 4) for n, t in zip(STAGES, per_call)},
+              "step_ms": step_distribution(m, gL, gR, disp, valid, args.steps)}
     if "staged" in want:
         extras["staged"] = staged_extras(m, gL, gR, args.steps)
     if "vote" in want:
