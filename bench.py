@@ -95,6 +95,54 @@ def cpu_baseline(L, R, D, rows):
                        f"whole plain matcher, {dt:.1f} s")
 
 
+# Rows of context a band needs so that its rows equal the whole-frame
+# result: 2 L1 for the two vertical aggregation stages, plus L1 for the
+# vertical arms of the pixels in those ranges (which also covers the census
+# window's 3 rows).
+BAND_HALO = 51
+
+
+def oracle_bands(L, R, D, nbands, threads):
+    """The oracle over the whole frame in `nbands` row bands run on `threads`
+    threads at once (the oracle's C calls release the GIL).  Each band is
+    matched with BAND_HALO rows of context on each side; its own rows of the
+    result are exactly the whole-frame result.  Returns (disp, valid, seconds,
+    rows matched in all)."""
+    import concurrent.futures as cf
+    import oracle
+    H, W = L.shape[:2]
+    edges = np.linspace(0, H, nbands + 1).round().astype(int)
+    disp = np.empty((H, W), np.float32)
+    valid = np.empty((H, W), np.uint8)
+
+    def run(i):
+        y0, y1 = int(edges[i]), int(edges[i + 1])
+        a, b = max(0, y0 - BAND_HALO), min(H, y1 + BAND_HALO)
+        d, v, _, _ = oracle.match(L[a:b], R[a:b], D)
+        disp[y0:y1] = d[y0 - a:y1 - a]
+        valid[y0:y1] = v[y0 - a:y1 - a]
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(run, range(nbands)))
+    dt = time.perf_counter() - t0
+    rows = sum(min(H, int(edges[i + 1]) + BAND_HALO) - max(0, int(edges[i]) - BAND_HALO)
+               for i in range(nbands))
+    return disp, valid, dt, rows
+
+
+def cpu_all_cores(L, R, D):
+    """Second CPU figure: the same oracle on every host core the process may
+    use (at most 16), over the whole frame in row bands."""
+    n = min(16, len(os.sched_getaffinity(0)))
+    H, W = L.shape[:2]
+    _, _, dt, rows = oracle_bands(L, R, D, n, n)
+    return dict(value=W * H * D / dt / 1e6, unit="Mpix·disp/s", cores=n,
+                kind="oracle, row bands on threads",
+                sample=f"whole {W}x{H} D={D} frame in {n} bands with a {BAND_HALO}-row halo "
+                       f"({rows} rows matched in all), {dt:.1f} s")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,6 +260,8 @@ def main():
     if not args.no_cpu:
         log(f"bench: CPU oracle on {args.cpu_rows} rows")
         cpu = cpu_baseline(L, R, D, args.cpu_rows)
+        log("bench: CPU oracle on all cores (row bands)")
+        extras["cpu_all_cores"] = cpu_all_cores(L, R, D)
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpix·disp/s",

@@ -67,3 +67,24 @@ def test_reciprocal_division_exact():
             assert r == a - q0 * N          # the residual is exact
             q = rn32(q0 + r * y)
             assert q == rn32(a / N), (N, s)
+
+
+def test_bench_oracle_bands_equal_the_whole_frame(monkeypatch):
+    """The all-cores CPU figure runs the oracle in row bands with a halo; the
+    bands' rows must equal the whole-frame oracle result bit for bit (and a
+    halo that is too short must not)."""
+    import bench
+    import oracle
+    from paper_2203_02300_amd import synth
+    p = synth.make_slanted_pair(160, 360, 24, 5, n_planes=4, dmin=2.0, dmax=22.0,
+                                noise_sigma=2.0, occl_strip_frac=0.03)
+    L, R = p["left"], p["right"]
+    want_d, want_v, _, _ = oracle.match(L, R, 24)
+    for nb, th in ((6, 3), (4, 2)):
+        d, v, _, rows = bench.oracle_bands(L, R, 24, nb, th)
+        assert np.array_equal(v, want_v)
+        assert np.array_equal(d.view(np.uint32), want_d.view(np.uint32))
+        assert 360 < rows <= 360 + 2 * bench.BAND_HALO * (nb - 1)
+    monkeypatch.setattr(bench, "BAND_HALO", 4)
+    d, v, _, _ = bench.oracle_bands(L, R, 24, 6, 3)
+    assert not (np.array_equal(v, want_v) and np.array_equal(d.view(np.uint32), want_d.view(np.uint32)))
