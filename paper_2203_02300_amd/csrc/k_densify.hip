@@ -25,33 +25,44 @@ namespace {
 constexpr int kDzThreads = 256;
 constexpr int kDzPix = 4;  // pixels per thread: a block covers 1024 consecutive pixels
 
-// Sum of n block partials in a fixed order, the same in every block: thread
-// t adds t, t + 256, ... in turn, then a fixed tree over the 256 threads.
-__device__ inline double block_sum_fixed(const double* __restrict__ part, int n,
-                                         double* red) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += kDzThreads) s += part[i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = kDzThreads / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
+constexpr int kDzWaves = kDzThreads / 64;
+
+// Block sums of N values per thread, in one fixed order: an xor-butterfly
+// across each wavefront (every lane ends with the same bits: each step adds
+// the same two values in either order), then the wavefront totals in a fixed
+// tree.  Every thread returns the N sums.  Two barriers whatever N is.
+template <int N>
+__device__ inline void block_sums(double (&v)[N], double* red /* N x kDzWaves */) {
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        for (int o = 32; o > 0; o >>= 1) v[j] += __shfl_xor(v[j], o, 64);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) red[j * kDzWaves + w] = v[j];
     }
-    const double v = red[0];
     __syncthreads();
-    return v;
+    static_assert(kDzWaves == 4, "fixed tree of four wavefront totals");
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const double* t = red + j * kDzWaves;
+        v[j] = (t[0] + t[1]) + (t[2] + t[3]);
+    }
+    __syncthreads();  // red may be reused
 }
 
-// Block sum of one value per thread (fixed tree); thread 0 writes it.
-__device__ inline void block_partial(double v, double* red, double* out) {
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = kDzThreads / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
+// Sums of N arrays of n block partials, the same bits in every block: thread
+// t adds entries t, t + 256, ... in turn, then block_sums.
+template <int N>
+__device__ inline void partial_sums(const double* const (&part)[N], int n, double (&out)[N],
+                                    double* red) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < n; i += kDzThreads) s += part[j][i];
+        out[j] = s;
     }
-    if (threadIdx.x == 0) *out = red[0];
-    __syncthreads();
+    block_sums<N>(out, red);
 }
 
 // Coefficients, right-hand side and the initial state x = 0, r = b, p = 0,
@@ -66,7 +77,7 @@ __global__ __launch_bounds__(kDzThreads) void k_dz_setup(
     double* __restrict__ p0, double* __restrict__ p1, double* __restrict__ rz_part,
     double* __restrict__ rr_part, double* __restrict__ bb_part, double* __restrict__ rz_init,
     int* __restrict__ flags) {
-    __shared__ double red[kDzThreads];
+    __shared__ double red[2 * kDzWaves];
     const int P = W * H;
     double rz = 0.0, rr = 0.0;
     for (int k = 0; k < kDzPix; ++k) {
@@ -101,10 +112,14 @@ __global__ __launch_bounds__(kDzThreads) void k_dz_setup(
         rz += bi * bi * id;
         rr += bi * bi;
     }
-    block_partial(rz, red, &rz_part[blockIdx.x]);
-    block_partial(rr, red, &rr_part[blockIdx.x]);
-    block_partial(rr, red, &bb_part[blockIdx.x]);
-    if (threadIdx.x == 0) rz_init[blockIdx.x] = 1.0;  // any nonzero "old" r.z: p starts at 0
+    double sums[2] = {rz, rr};
+    block_sums<2>(sums, red);
+    if (threadIdx.x == 0) {
+        rz_part[blockIdx.x] = sums[0];
+        rr_part[blockIdx.x] = sums[1];
+        bb_part[blockIdx.x] = sums[1];
+        rz_init[blockIdx.x] = 1.0;  // any nonzero "old" r.z: p starts at 0
+    }
     if (blockIdx.x == 0 && threadIdx.x < 2) flags[threadIdx.x] = 0;
 }
 
@@ -137,9 +152,12 @@ __global__ __launch_bounds__(kDzThreads) void k_dz_dir(DzState s, const double* 
                                                        const double* __restrict__ p_in,
                                                        double* __restrict__ p_out,
                                                        double* __restrict__ pq_part) {
-    __shared__ double red[kDzThreads];
+    __shared__ double red[2 * kDzWaves];
     if (solve_done(s.flags)) return;
-    const double beta = block_sum_fixed(rz_new, s.nblk, red) / block_sum_fixed(rz_old, s.nblk, red);
+    const double* const parts[2] = {rz_new, rz_old};
+    double rz[2];
+    partial_sums<2>(parts, s.nblk, rz, red);
+    const double beta = rz[0] / rz[1];
     const int W = s.W, P = W * s.H;
     double pq = 0.0;
     for (int k = 0; k < kDzPix; ++k) {
@@ -158,7 +176,9 @@ __global__ __launch_bounds__(kDzThreads) void k_dz_dir(DzState s, const double* 
         s.q[i] = qi;
         pq += pc * qi;
     }
-    block_partial(pq, red, &pq_part[blockIdx.x]);
+    double sum[1] = {pq};
+    block_sums<1>(sum, red);
+    if (threadIdx.x == 0) pq_part[blockIdx.x] = sum[0];
 }
 
 // alpha = rz / pq; x += alpha p; r -= alpha q; block sums of r.z and r.r of
@@ -171,16 +191,17 @@ __global__ __launch_bounds__(kDzThreads) void k_dz_update(DzState s,
                                                           const double* __restrict__ p,
                                                           double* __restrict__ rz_out,
                                                           double* __restrict__ rr_out) {
-    __shared__ double red[kDzThreads];
+    __shared__ double red[4 * kDzWaves];
     if (solve_done(s.flags)) return;
-    const double rr = block_sum_fixed(rr_in, s.nblk, red);
-    const double bb = block_sum_fixed(s.bb_part, s.nblk, red);
+    const double* const parts[4] = {rr_in, s.bb_part, pq_part, rz_in};
+    double sums[4];
+    partial_sums<4>(parts, s.nblk, sums, red);
+    const double rr = sums[0], bb = sums[1], pq = sums[2];
     if (rr <= s.tol2 * bb) {  // converged before this step: the same decision in every block
         if (blockIdx.x == 0 && threadIdx.x == 0) s.flags[0] = 1;
         return;
     }
-    const double pq = block_sum_fixed(pq_part, s.nblk, red);
-    const double alpha = pq > 0.0 ? block_sum_fixed(rz_in, s.nblk, red) / pq : 0.0;
+    const double alpha = pq > 0.0 ? sums[3] / pq : 0.0;
     const int P = s.W * s.H;
     double rz = 0.0, rrn = 0.0;
     for (int k = 0; k < kDzPix; ++k) {
@@ -192,9 +213,13 @@ __global__ __launch_bounds__(kDzThreads) void k_dz_update(DzState s,
         rz += ri * ri * s.invdiag[i];
         rrn += ri * ri;
     }
-    block_partial(rz, red, &rz_out[blockIdx.x]);
-    block_partial(rrn, red, &rr_out[blockIdx.x]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) s.flags[1] += 1;
+    double out[2] = {rz, rrn};
+    block_sums<2>(out, red);
+    if (threadIdx.x == 0) {
+        rz_out[blockIdx.x] = out[0];
+        rr_out[blockIdx.x] = out[1];
+        if (blockIdx.x == 0) s.flags[1] += 1;
+    }
 }
 
 __global__ __launch_bounds__(kDzThreads) void k_dz_out(const double* __restrict__ x, int P,
