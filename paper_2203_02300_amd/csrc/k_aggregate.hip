@@ -5,6 +5,8 @@
 // (the one-call matcher) instead of being read from a cost volume (the
 // staged dco_aggregate).  The stage body (dco::agg_stream) lives in
 // dco_device.h.
+#include <atomic>
+
 #include "dco_device.h"
 
 namespace {
@@ -78,19 +80,25 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_agg_pair(dco::AggArgs A0, 
 template <int ITERS>
 hipError_t launch_pair(const dco::AggArgs& a0, const AggRecords& rec1, float* out1,
                        hipStream_t st) {
-    static int slots_per_cu = 0, cus = 0;
-    if (!slots_per_cu) {
-        int dev = 0, nb = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e == hipSuccess)
-            e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // resident workgroups of the whole device, per device (queried once each;
+    // concurrent first calls store the same value)
+    constexpr int kMaxDev = 64;
+    static std::atomic<int> slots[kMaxDev];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    int total = dev < kMaxDev ? slots[dev].load(std::memory_order_relaxed) : 0;
+    if (!total) {
+        int cus = 0, nb = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_agg_pair<ITERS>,
                                                              kStripThreads, 0);
         if (e != hipSuccess) return e;
-        slots_per_cu = nb > 0 ? nb : 1;
+        total = (nb > 0 ? nb : 1) * (cus > 0 ? cus : 1);
+        if (dev < kMaxDev) slots[dev].store(total, std::memory_order_relaxed);
     }
-    const int s8 = slots_per_cu * cus / 8;
+    const int s8 = total / 8;
     const int N = 2 * a0.nstrips * a0.D;
     int most = 1;
     for (int x = 0; x < 8; ++x) {
