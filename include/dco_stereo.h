@@ -73,8 +73,8 @@ typedef struct {
 dco_status dco_default_params(dco_params* out);
 
 /* Create a matcher for W x H images and disparities d = 0 .. D-1.
- * Requires 1 <= D < W, W >= census_w, H >= census_h, W, H <= 16384 and
- * W * H * D < 2^31.  Copies *p (NULL = defaults), builds the Eq. 1 tables on
+ * Requires 1 <= D < W, W >= census_w, H >= census_h, W, H <= 16384,
+ * W * H <= 2^27 and W * H * D < 2^31 (else DCO_ERR_SHAPE).  Copies *p (NULL = defaults), builds the Eq. 1 tables on
  * the host in double precision and uploads them, and allocates the scratch
  * that dco_stereo_match needs.  Synchronous.  On failure *out is NULL. */
 dco_status dco_stereo_create(dco_stereo** out, int W, int H, int D, const dco_params* p,
@@ -323,7 +323,9 @@ dco_status dco_batch_tile(const dco_batch* b, int i, int* strip_w, int* band_h, 
  * means as in dco_aggregate but in float with no rounding step, and
  *   dhat = sum_d d softmax_d(-agg(p, d) / T).
  * dhat: B x H x W float (out); lse: B x H x W float (out), the log-sum-exp
- * of -agg/T per pixel, kept for the backward pass. */
+ * of -agg/T per pixel, kept for the backward pass.  DCO_ERR_SHAPE unless the
+ * handle has W <= 2048 and two-stage aggregation, B * D <= 65535 and
+ * B * D * H < 2^31. */
 dco_status dco_soft_forward(dco_stereo* h, int B, const uint8_t* L, const uint8_t* R,
                             const float* theta, float* dhat, float* lse);
 

@@ -89,11 +89,14 @@ dco_status check_params(const dco_params& p) {
     return DCO_OK;
 }
 
+// W * H <= 2^27 keeps every byte offset of the aggregation kernels' 32-bit
+// buffer addressing in range (16-byte packed pixels, and 16-byte records
+// over the padded width and H + kLMax + 1 rows).
 dco_status check_shape(int W, int H, int D, const dco_params& p) {
     if (W < p.census_w || H < p.census_h || W > 16384 || H > 16384 || D < 1 || D >= W ||
-        D > 32767 || (long long)W * H * D >= (1LL << 31)) {
+        D > 32767 || (long long)W * H > (1LL << 27) || (long long)W * H * D >= (1LL << 31)) {
         dco_set_error("shape W=%d H=%d D=%d: need 1 <= D < W, W >= census_w, H >= census_h, "
-                      "W, H <= 16384 and W*H*D < 2^31",
+                      "W, H <= 16384, W*H <= 2^27 and W*H*D < 2^31",
                       W, H, D);
         return DCO_ERR_SHAPE;
     }
@@ -546,6 +549,11 @@ static dco_status soft_check(dco_stereo* h, int B) {
     }
     if (h->W > 2048 || h->p.agg_iters != 2) {
         dco_set_error("the soft path needs W <= 2048 and two-stage aggregation");
+        return DCO_ERR_SHAPE;
+    }
+    if ((long long)B * h->D > 65535 || (long long)B * h->D * h->H >= (1LL << 31)) {
+        dco_set_error("the soft path needs B*D <= 65535 and B*D*H < 2^31 (B=%d, D=%d, H=%d)", B,
+                      h->D, h->H);
         return DCO_ERR_SHAPE;
     }
     return DCO_OK;

@@ -59,7 +59,9 @@ def create(L, W, H, D, **kw):
 
 
 @pytest.mark.parametrize("W,H,D", [(64, 48, 64), (64, 48, 0), (8, 48, 4), (64, 6, 4),
-                                   (20000, 8, 4), (16384, 16384, 16)])
+                                   (20000, 8, 4), (16384, 16384, 16),
+                                   # W * H above 2^27 with W * H * D < 2^31
+                                   (16384, 16384, 1), (16384, 8193, 1)])
 def test_bad_shapes_rejected(L, W, H, D):
     st, h = create(L, W, H, D)
     assert st == -2 and not h.value

@@ -170,3 +170,52 @@ def test_full_size_1280x720_properties_and_crops(torch_mod):
         assert np.array_equal(st["dL"][sl], dL[y0:y1, x0:x1])
         assert np.array_equal(st["valid"][sl], valid[y0:y1, x0:x1])
         assert np.array_equal(st["disp"][sl], disp[y0:y1, x0:x1])
+
+
+def _crop_check(L, R, D, disp, valid, x0, y0, iw=96, ih=32):
+    """Oracle on a crop around [x0, x0 + iw) x [y0, y0 + ih) with margins wide
+    enough that the interior equals the whole-frame result."""
+    H, W = L.shape[:2]
+    mx, my = D + 60, 60
+    cx0, cx1 = max(0, x0 - mx), min(W, x0 + iw + mx)
+    cy0, cy1 = max(0, y0 - my), min(H, y0 + ih + my)
+    st = oracle.stages(L[cy0:cy1, cx0:cx1], R[cy0:cy1, cx0:cx1], D)
+    sl = (slice(y0 - cy0, y0 - cy0 + ih), slice(x0 - cx0, x0 - cx0 + iw))
+    assert np.array_equal(st["valid"][sl], valid[y0:y0 + ih, x0:x0 + iw])
+    assert np.array_equal(st["disp"][sl].view(np.uint32),
+                          disp[y0:y0 + ih, x0:x0 + iw].view(np.uint32))
+
+
+@pytest.mark.parametrize("W,H,D", [(16384, 8, 4), (2050, 8, 2048)])
+def test_maximum_width_and_range(torch_mod, W, H, D):
+    """The widest frame the library takes, and a disparity range near the
+    width, against the whole-frame oracle."""
+    from paper_2203_02300_amd import StereoMatcher
+    rng = np.random.default_rng(W + D)
+    L = rng.integers(0, 256, (H, W, 3), dtype=np.uint8)
+    R = np.roll(L, -3, axis=1)
+    print(f"maximum sizes {W}x{H} D={D}", flush=True)
+    st = oracle.stages(L, R, D)
+    with StereoMatcher(W, H, D) as m:
+        disp, valid = m.match(dev(L), dev(R))
+        assert np.array_equal(host(valid), st["valid"])
+        assert np.array_equal(host(disp).view(np.uint32), st["disp"].view(np.uint32))
+
+
+def test_maximum_area(torch_mod):
+    """16384 x 8192 (W * H = 2^27, the largest area the library takes), D = 2:
+    the largest 32-bit buffer offsets of the aggregation kernels.  Crops at
+    the four corners and the centre against the oracle."""
+    from paper_2203_02300_amd import StereoMatcher
+    W, H, D = 16384, 8192, 2
+    rng = np.random.default_rng(7)
+    L = rng.integers(0, 256, (H, W, 3), dtype=np.uint8)
+    R = np.roll(L, -1, axis=1)
+    print(f"maximum area {W}x{H} D={D}", flush=True)
+    with StereoMatcher(W, H, D) as m:
+        disp, valid = m.match(dev(L), dev(R))
+        disp, valid = host(disp), host(valid)
+    for x0, y0 in ((0, 0), (W - 96, 0), (0, H - 32), (W - 96, H - 32), (W // 2, H // 2)):
+        _crop_check(L, R, D, disp, valid, x0, y0)
+    # a pure shift by one: every pixel whose partner is inside matches d = 1
+    assert valid[:, 1:].mean() > 0.99

@@ -136,3 +136,13 @@ def test_soft_full_size_batch(torch_mod):
     g_ref = oracle.soft_grad(Lb, Rb, cL, cR, aL, D, gd[0].astype(np.float64), lam_ad=10.0,
                              lam_c=30.0, T=1.0)
     assert np.all(np.abs(g0 - g_ref) <= 1e-3 * np.abs(g_ref).max()), (g0, g_ref)
+
+
+def test_soft_rejects_oversized_batches(torch_mod):
+    """B * D above the column passes' grid limit is refused before any work."""
+    from paper_2203_02300_amd import StereoMatcher, _lib
+    L = _lib.lib()
+    with StereoMatcher(64, 48, 16) as m:
+        assert L.dco_soft_forward(m._h, 5000, None, None, None, None, None) == -2
+        assert b"B*D" in L.dco_last_error()
+        assert L.dco_soft_forward(m._h, 0, None, None, None, None, None) == -1
