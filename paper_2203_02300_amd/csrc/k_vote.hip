@@ -135,7 +135,9 @@ __global__ __launch_bounds__(64) void k_vote(const int16_t* __restrict__ din,
     const int u = min((int)((a >> 16) & 0xff), kLMax), dn = min((int)(a >> 24), kLMax);
     int best = 0, bc = -1;
     for (int base = vlo; base <= vhi; base += kVBins) {  // uniform
-        for (int i = lane; i < kVBins * 64 / 8; i += 64)
+        // bins past vhi get no votes: clear and scan only the nb in range
+        const int nb = min(kVBins, vhi - base + 1);
+        for (int i = lane; i < nb * 64 / 8; i += 64)
             reinterpret_cast<uint4*>(S.hist)[i] = make_uint4(0, 0, 0, 0);
         __syncthreads();
         if (mine >= 0) {
@@ -145,14 +147,14 @@ __global__ __launch_bounds__(64) void k_vote(const int16_t* __restrict__ din,
                 const int k1 = S.rs[ry][hi];
                 for (int j = S.rs[ry][lo]; j <= k1; ++j) {
                     const int b = S.rv[ry][j] - base;
-                    if (b >= 0 && b < kVBins) {
+                    if (b >= 0 && b < nb) {
                         const int s0 = max((int)S.st[ry][j], lo);
                         const int s1 = min((int)S.st[ry][j + 1] - 1, hi);
                         S.hist[b * 64 + lane] += (uint16_t)(s1 - s0 + 1);
                     }
                 }
             }
-            for (int b = 0; b < kVBins; ++b) {
+            for (int b = 0; b < nb; ++b) {
                 const int c = S.hist[b * 64 + lane];
                 if (c > bc) {
                     bc = c;
