@@ -78,6 +78,16 @@ def step_distribution(m, gL, gR, disp, valid, steps):
                 min=round(float(t[0]), 4), n=len(t))
 
 
+def _guarded(fn, *args):
+    """Run one extra measurement; a Python-level failure is recorded in its
+    place so that the headline line is still printed."""
+    try:
+        return fn(*args)
+    except Exception as e:  # noqa: BLE001 - reported, not hidden
+        log(f"bench: {fn.__name__} failed: {e!r}")
+        return {"error": repr(e)}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -232,28 +242,28 @@ def main():
     extras = {"stage_ms": {n: round(t, 4) for n, t in zip(STAGES, per_call)},
               "step_ms": step_distribution(m, gL, gR, disp, valid, args.steps)}
     if "staged" in want:
-        extras["staged"] = staged_extras(m, gL, gR, args.steps)
+        extras["staged"] = _guarded(staged_extras, m, gL, gR, args.steps)
     if "vote" in want:
         log("bench: one-call match with two Eq. 4 vote passes")
-        extras["vote"] = vote_extras(gL, gR, disp, valid, args.steps)
+        extras["vote"] = _guarded(vote_extras, gL, gR, disp, valid, args.steps)
     if "half" in want:
         log("bench: quarter-size front end (640x360, D=64, two vote passes, depth)")
-        extras["half"] = half_extras(gL, gR, args.steps)
+        extras["half"] = _guarded(half_extras, gL, gR, args.steps)
     if "contour" in want:
         log("bench: depth contour filter (1280x720 frame, 640x360 flows)")
-        extras["contour"] = contour_extras(args.steps)
+        extras["contour"] = _guarded(contour_extras, args.steps)
     if "densify" in want:
         log("bench: depth densification (Eq. 13-20) at 640x360 and 1280x720")
-        extras["densify"] = densify_extras(max(3, args.steps // 10))
+        extras["densify"] = _guarded(densify_extras, max(3, args.steps // 10))
     del m
     torch.cuda.empty_cache()
     if "batched" in want:
         log("bench: batched matcher (32 mixed pairs)")
-        extras["batched"] = batched_extras(max(3, args.steps // 10))
+        extras["batched"] = _guarded(batched_extras, max(3, args.steps // 10))
         torch.cuda.empty_cache()
     if "soft" in want:
         log("bench: differentiable soft-argmin (8 x 640x480, D=64)")
-        extras["soft"] = soft_extras(max(3, args.steps // 10))
+        extras["soft"] = _guarded(soft_extras, max(3, args.steps // 10))
         torch.cuda.empty_cache()
 
     cpu = None
@@ -261,7 +271,7 @@ def main():
         log(f"bench: CPU oracle on {args.cpu_rows} rows")
         cpu = cpu_baseline(L, R, D, args.cpu_rows)
         log("bench: CPU oracle on all cores (row bands)")
-        extras["cpu_all_cores"] = cpu_all_cores(L, R, D)
+        extras["cpu_all_cores"] = _guarded(cpu_all_cores, L, R, D)
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpix·disp/s",
