@@ -661,7 +661,7 @@ __device__ inline void tree3(double (*red)[256], double a, double c, double t) {
     red[2][threadIdx.x] = t;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s)
+        if ((int)threadIdx.x < s)
             for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
         __syncthreads();
     }
