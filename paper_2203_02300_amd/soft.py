@@ -9,7 +9,6 @@ differentiated; only (dhat, lse) are kept between the two passes.
 """
 from __future__ import annotations
 
-
 import torch
 
 from ._lib import check, lib
