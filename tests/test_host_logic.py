@@ -88,3 +88,16 @@ def test_bench_oracle_bands_equal_the_whole_frame(monkeypatch):
     monkeypatch.setattr(bench, "BAND_HALO", 4)
     d, v, _, _ = bench.oracle_bands(L, R, 24, 6, 3)
     assert not (np.array_equal(v, want_v) and np.array_equal(d.view(np.uint32), want_d.view(np.uint32)))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with a message before
+    touching a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
