@@ -146,3 +146,7 @@ def test_soft_rejects_oversized_batches(torch_mod):
         assert L.dco_soft_forward(m._h, 5000, None, None, None, None, None) == -2
         assert b"B*D" in L.dco_last_error()
         assert L.dco_soft_forward(m._h, 0, None, None, None, None, None) == -1
+    with StereoMatcher(2100, 8, 4) as m:  # wider than the row passes' LDS allows
+        assert L.dco_soft_forward(m._h, 1, None, None, None, None, None) == -2
+        assert b"W <= 2048" in L.dco_last_error()
+        assert L.dco_soft_backward(m._h, 1, None, None, None, None, None, None, None) == -2
