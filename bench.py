@@ -161,9 +161,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=540)
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="staged,vote,half,densify,contour,batched,soft",
+    ap.add_argument("--extras", default="staged,sizes,vote,half,densify,contour,batched,soft",
                     help="comma list of the extra measurements to run "
-                         "(staged, vote, half, densify, contour, batched, soft)")
+                         "(staged, sizes, vote, half, densify, contour, batched, soft)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of MiB mebibytes (counter calibration)")
     args = ap.parse_args()
@@ -243,6 +243,9 @@ def main():
               "step_ms": step_distribution(m, gL, gR, disp, valid, args.steps)}
     if "staged" in want:
         extras["staged"] = _guarded(staged_extras, m, gL, gR, args.steps)
+    if "sizes" in want:
+        log("bench: one-call match at 64x48 D=16 and 640x480 D=64")
+        extras["sizes"] = _guarded(sizes_extras, args.steps)
     if "vote" in want:
         log("bench: one-call match with two Eq. 4 vote passes")
         extras["vote"] = _guarded(vote_extras, gL, gR, disp, valid, args.steps)
@@ -367,6 +370,26 @@ def soft_extras(n):
                 Mpix_disp_s=round(units / (ms_fb / 1e3) / 1e6, 1),
                 plain_ms=round(ms_plain, 3), ratio_to_plain=round(ms_fb / ms_plain, 3),
                 loss=round(loss, 4), grad_theta=[round(g, 6) for g in grad])
+
+
+def sizes_extras(steps):
+    """The one-call match on the two smaller workloads (64x48 with D = 16,
+    launch-bound; 640x480 with D = 64): ms per frame and Mpix*disp/s."""
+    import torch
+    from paper_2203_02300_amd import StereoMatcher, synth
+    out = {}
+    for name, pair, D in (("64x48 D=16", synth.config_c1(), 16),
+                          ("640x480 D=64", synth.config_c2(), 64)):
+        L = torch.from_numpy(pair["left"]).cuda()
+        R = torch.from_numpy(pair["right"]).cuda()
+        H, W = L.shape[:2]
+        m = StereoMatcher(W, H, D)
+        disp = torch.empty((H, W), dtype=torch.float32, device="cuda")
+        valid = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+        ms = _time(lambda: m.match(L, R, disp, valid), steps)
+        m.close()
+        out[name] = dict(ms_per_frame=round(ms, 4), Mpix_disp_s=round(W * H * D / ms / 1e3, 1))
+    return out
 
 
 def vote_extras(gL, gR, disp0, valid0, steps):
