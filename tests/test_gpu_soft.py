@@ -150,3 +150,40 @@ def test_soft_rejects_oversized_batches(torch_mod):
         assert L.dco_soft_forward(m._h, 1, None, None, None, None, None) == -2
         assert b"W <= 2048" in L.dco_last_error()
         assert L.dco_soft_backward(m._h, 1, None, None, None, None, None, None, None) == -2
+
+
+@pytest.mark.parametrize("W,H,D,B", [(2048, 9, 6, 1), (23, 11, 5, 3)])
+def test_soft_widest_and_smallest_frames(torch_mod, W, H, D, B):
+    """The widest frame the row passes' LDS takes (W = 2048) and a small
+    ragged batch: dhat, lse and the theta gradient against the FP64 oracle."""
+    torch = torch_mod
+    from paper_2203_02300_amd import StereoMatcher
+    from paper_2203_02300_amd.soft import soft_backward, soft_forward
+    rng = np.random.default_rng(W + B)
+    Ls = rng.integers(0, 256, (B, H, W, 3), dtype=np.uint8)
+    Rs = np.roll(Ls, -2, axis=2)
+    theta_np = np.array([10.0, 30.0, 1.0])
+    print(f"soft {B} x {W}x{H} D={D}", flush=True)
+    gd = rng.normal(0, 1e-3, (B, H, W)).astype(np.float32)
+    with StereoMatcher(W, H, D) as m:
+        L, R = dev(Ls), dev(Rs)
+        theta = torch.tensor(theta_np, dtype=torch.float32, device="cuda")
+        dhat, lse = soft_forward(m, L, R, theta)
+        g = soft_backward(m, L, R, theta, dhat, lse, dev(gd))
+        dh_gpu, lse_gpu, g_gpu = host(dhat), host(lse), host(g).astype(np.float64)
+    g_ref = np.zeros(3)
+    for b in range(B):
+        cL, cR = oracle.census(oracle.grey(Ls[b])), oracle.census(oracle.grey(Rs[b]))
+        aL = oracle.arms(Ls[b])
+        dh, vol = oracle.soft_forward(Ls[b], Rs[b], cL, cR, aL, D, lam_ad=10.0, lam_c=30.0,
+                                      T=1.0, want_volume=True)
+        assert np.abs(dh_gpu[b] - dh).max() < 1e-3
+        z = -vol
+        mx = z.max(axis=0)
+        lse_ref = mx + np.log(np.exp(z - mx).sum(axis=0))
+        assert np.abs(lse_gpu[b] - lse_ref).max() < 1e-3 * max(1.0, np.abs(lse_ref).max())
+        g_ref += oracle.soft_grad(Ls[b], Rs[b], cL, cR, aL, D, gd[b].astype(np.float64),
+                                  lam_ad=10.0, lam_c=30.0, T=1.0)
+    scale = np.abs(g_ref).max()
+    assert scale > 0
+    assert np.all(np.abs(g_gpu - g_ref) <= 1e-3 * scale), (g_gpu, g_ref)
