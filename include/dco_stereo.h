@@ -226,7 +226,8 @@ typedef struct dco_densify dco_densify; /* opaque densification handle */
 dco_status dco_densify_default_params(dco_densify_params* out);
 
 /* Buffers for an H x W grid and the captured iteration graph (p may be
- * NULL for the defaults; stream: the HIP stream the solves run on). */
+ * NULL for the defaults; stream: the HIP stream the solves run on).
+ * Requires 1 <= W, H and W * H <= 2^23 (else DCO_ERR_SHAPE). */
 dco_status dco_densify_create(dco_densify** out, int W, int H, const dco_densify_params* p,
                               void* stream);
 void dco_densify_destroy(dco_densify* h);

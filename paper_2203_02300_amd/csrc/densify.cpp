@@ -60,8 +60,10 @@ extern "C" dco_status dco_densify_create(dco_densify** out, int W, int H,
         prm = *p;
     else
         dco_densify_default_params(&prm);
-    if (W < 1 || H < 1 || (long long)W * H > (1LL << 28)) {
-        dco_set_error("densify grid %d x %d: need 1 <= W, H and W*H <= 2^28", W, H);
+    // every block sums all blocks' partials in a fixed order, a cost that grows
+    // with the square of the grid: 2^23 pixels (a 3840 x 2160 frame) at most
+    if (W < 1 || H < 1 || (long long)W * H > (1LL << 23)) {
+        dco_set_error("densify grid %d x %d: need 1 <= W, H and W*H <= 2^23", W, H);
         return DCO_ERR_SHAPE;
     }
     if (!(std::isfinite(prm.lambda_d) && prm.lambda_d >= 0.0f) ||

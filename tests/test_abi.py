@@ -111,6 +111,7 @@ def test_densify_defaults_and_bad_params(L):
         assert L.dco_densify_create(C.byref(h), 8, 8, C.byref(q), None) == -1 and not h.value
     h = C.c_void_p()
     assert L.dco_densify_create(C.byref(h), 0, 8, None, None) == -2
+    assert L.dco_densify_create(C.byref(h), 4096, 2049, None, None) == -2 and not h.value
     assert L.dco_stereo_set_stream(None, None) == -1
     L.dco_stereo_destroy(None)
 
