@@ -42,23 +42,41 @@ TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "prof
                                "plain_match_1280x720_D128_hbm_counters.md")
 
 
+SQ_PROFILE = os.path.join(os.path.dirname(TRAFFIC_PROFILE),
+                          "plain_match_1280x720_D128_sq_counters.md")
+
+
+def _profile_fields(path, keys):
+    """The `key: value` lines of a committed counter summary, or None when the
+    dominant kernel's sources have changed since those counters were taken."""
+    import hashlib
+    try:
+        fields = dict(l.split(": ", 1) for l in open(path).read().splitlines()
+                      if l.startswith(tuple(keys) + ("kernel_source",)))
+        h = hashlib.sha256()
+        for s in fields["kernel_sources"].split():
+            h.update(open(os.path.join(os.path.dirname(path), "..", s), "rb").read())
+        if h.hexdigest() != fields["kernel_source_sha256"].strip():
+            return None
+        return {k: fields[k].strip() for k in keys}
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def measured_traffic():
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
     kernel's sources have changed since those counters were taken."""
-    import hashlib
-    try:
-        fields = dict(l.split(": ", 1) for l in open(TRAFFIC_PROFILE).read().splitlines()
-                      if l.startswith(("traffic_bytes_per_launch", "kernel_source")))
-        h = hashlib.sha256()
-        root = os.path.dirname(TRAFFIC_PROFILE)
-        for s in fields["kernel_sources"].split():
-            h.update(open(os.path.join(root, "..", s), "rb").read())
-        if h.hexdigest() != fields["kernel_source_sha256"].strip():
-            return None
-        return int(fields["traffic_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
-        return None
+    f = _profile_fields(TRAFFIC_PROFILE, ["traffic_bytes_per_launch"])
+    return int(f["traffic_bytes_per_launch"]) if f else None
+
+
+def measured_busy():
+    """Busy fractions of the dominant kernel's VALU, TA, TD and LDS from the
+    committed SQ/TA/TD counter summary (same validity rule as the traffic)."""
+    keys = ["busy_valu", "busy_ta", "busy_td", "busy_lds", "valu_lane_ops_per_pd"]
+    f = _profile_fields(SQ_PROFILE, keys)
+    return {k.replace("busy_", ""): float(v) for k, v in f.items()} if f else None
 
 
 def step_distribution(m, gL, gR, disp, valid, steps):
@@ -237,7 +255,8 @@ def main():
     roofline = dict(bound="alu", achieved=round(achieved, 2), peak=round(VALU_PEAK_TOPS, 2),
                     unit="TOP/s", frac=round(achieved / VALU_PEAK_TOPS, 4), traffic=measured_traffic(),
                     kernel="k_agg_pair<2>", kernel_ms=round(agg_ms, 4),
-                    ops_per_pd=ops_per_unit, units_per_launch=2 * V)
+                    ops_per_pd=ops_per_unit, units_per_launch=2 * V,
+                    units_busy=measured_busy())
 
     extras = {"stage_ms": {n: round(t, 4) for n, t in zip(STAGES, per_call)},
               "step_ms": step_distribution(m, gL, gR, disp, valid, args.steps)}
