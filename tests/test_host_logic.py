@@ -101,3 +101,13 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_committed_counter_summaries_match_the_kernel_sources():
+    """The HBM-traffic and SQ/TA/TD summaries under profiles/ were taken from
+    the aggregation kernel's current sources (bench.py reports them only
+    then): a change to those sources needs a fresh profile."""
+    import bench
+    assert bench.measured_traffic() is not None
+    busy = bench.measured_busy()
+    assert busy is not None and 0.0 < busy["valu"] <= 1.0 and 0.0 < busy["td"] <= 1.0
