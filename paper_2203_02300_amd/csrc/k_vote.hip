@@ -6,13 +6,14 @@
 // disparity.  Invalid pixels (-1) neither vote nor change.  Passes read only
 // the previous pass's map.
 //
-// Layout: one wavefront per 8 x 8 pixel tile.  The tile's votes plus a kLMax
-// apron on every side (42 x 42 int16) and the horizontal arms of the tile
-// columns over the apron rows go to LDS, and each staged row is run-length
-// coded once (runs of equal votes: start column, value, and the run of each
-// column).  Every lane then counts its own region into its own counters: a
-// segment adds, for each run it meets, the overlap length to the run's
-// value.  Counters cover a window of kVBins disparities at a time (16-bit,
+// Layout: one workgroup of four wavefronts per 16 x 16 pixel tile, one
+// thread per pixel.  The tile's votes plus a kLMax apron on every side
+// (50 x 50 int16) and the horizontal arms of the tile columns over the apron
+// rows go to LDS, and each staged row is run-length coded once (runs of equal
+// votes: start column, value, and the run of each column).  Every thread then
+// counts its own region into its own counters: a segment adds, for each run
+// it meets, the overlap length to the run's value.  Counters cover a window
+// of kVBins disparities at a time (16-bit, one set per wavefront,
 // lane-interleaved so that the 64 lanes' counters of one disparity are 128
 // contiguous bytes: no bank conflicts whatever the disparities); the windows
 // step from the smallest to the largest vote staged for the tile, and the
@@ -23,20 +24,24 @@
 
 namespace {
 
-constexpr int kVT = 8;                // tile side
-constexpr int kVR = kVT + 2 * kLMax;  // staged side
+constexpr int kVT = 16;                     // tile side
+constexpr int kVThreads = kVT * kVT;        // one thread per tile pixel
+constexpr int kVWaves = kVThreads / 64;
+constexpr int kVR = kVT + 2 * kLMax;        // staged side
 constexpr int kVStride = kVR + 2;
 
 constexpr int kVBins = 64;  // disparities per counter window
-constexpr int kVStage = (kVR * kVR + 63) / 64;
+constexpr int kVStage = (kVR * kVR + kVThreads - 1) / kVThreads;
+constexpr int kVArms = (kVR * kVT + kVThreads - 1) / kVThreads;
 
 struct VoteLds {
-    __align__(16) uint16_t hist[kVBins * 64];  // counters of one window, [bin][lane]
-    int16_t d[kVR][kVStride];                  // votes of the staged region (-1: none)
-    int16_t rv[kVR][kVR];                      // value of run k of each staged row
-    uint8_t rs[kVR][kVR + 2];                  // run of each column
-    uint8_t st[kVR][kVR + 2];                  // start column of run k; st[nruns] = kVR
-    uint8_t l[kVR][kVT], r[kVR][kVT];          // horizontal arms of the tile columns
+    __align__(16) uint16_t hist[kVWaves][kVBins * 64];  // per wavefront: [bin][lane]
+    int16_t d[kVR][kVStride];                           // votes of the staged region (-1: none)
+    int16_t rv[kVR][kVR];                               // value of run k of each staged row
+    uint8_t rs[kVR][kVR + 2];                           // run of each column
+    uint8_t st[kVR][kVR + 2];                           // start column of run k; st[nruns] = kVR
+    uint8_t l[kVR][kVT], r[kVR][kVT];                   // horizontal arms of the tile columns
+    int lo[kVWaves], hi[kVWaves];                       // vote range seen by each wavefront
 };
 
 __device__ inline int wave_min(int v) {
@@ -50,20 +55,20 @@ __device__ inline int wave_max(int v) {
 
 // din: H x W int16; valid (first pass only, else null): H x W uint8; a vote
 // outside [0, D) counts as invalid.  dout: H x W int16, -1 where invalid.
-__global__ __launch_bounds__(64) void k_vote(const int16_t* __restrict__ din,
-                                             const uint8_t* __restrict__ valid,
-                                             const uint32_t* __restrict__ arms, int W, int H,
-                                             int D, int16_t* __restrict__ dout) {
+__global__ __launch_bounds__(kVThreads) void k_vote(const int16_t* __restrict__ din,
+                                                    const uint8_t* __restrict__ valid,
+                                                    const uint32_t* __restrict__ arms, int W,
+                                                    int H, int D, int16_t* __restrict__ dout) {
     __shared__ __align__(16) VoteLds S;
-    const int lane = threadIdx.x, tx = lane & (kVT - 1), ty = lane / kVT;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tx = tid & (kVT - 1), ty = tid / kVT;
     const int x0 = blockIdx.x * kVT, y0 = blockIdx.y * kVT;
-    int vlo, vhi;
     {   // stage the votes: every load issued before any is used (clamped addresses)
         int dv[kVStage];
         bool ok[kVStage];
 #pragma unroll
         for (int t = 0; t < kVStage; ++t) {
-            const int i = min(lane + 64 * t, kVR * kVR - 1);
+            const int i = min(tid + kVThreads * t, kVR * kVR - 1);
             const int ry = i / kVR, rx = i - ry * kVR;
             const int x = x0 - kLMax + rx, y = y0 - kLMax + ry;
             ok[t] = x >= 0 && x < W && y >= 0 && y < H;
@@ -74,7 +79,7 @@ __global__ __launch_bounds__(64) void k_vote(const int16_t* __restrict__ din,
         int lo = D, hi = -1;
 #pragma unroll
         for (int t = 0; t < kVStage; ++t) {
-            const int i = lane + 64 * t;
+            const int i = tid + kVThreads * t;
             const int v = ok[t] && dv[t] >= 0 && dv[t] < D ? dv[t] : -1;
             if (i < kVR * kVR) {
                 const int ry = i / kVR;
@@ -85,22 +90,25 @@ __global__ __launch_bounds__(64) void k_vote(const int16_t* __restrict__ din,
                 }
             }
         }
-        vlo = __builtin_amdgcn_readfirstlane(wave_min(lo));  // the tile's vote range
-        vhi = __builtin_amdgcn_readfirstlane(wave_max(hi));  // (empty when vhi < vlo)
+        lo = wave_min(lo);
+        hi = wave_max(hi);
+        if (lane == 0) {
+            S.lo[w] = lo;
+            S.hi[w] = hi;
+        }
     }
     {   // horizontal arms of the tile columns (loads issued together, clamped)
-        constexpr int kN = (kVR * kVT + 63) / 64;
-        uint32_t av[kN];
+        uint32_t av[kVArms];
 #pragma unroll
-        for (int t = 0; t < kN; ++t) {
-            const int i = min(lane + 64 * t, kVR * kVT - 1);
+        for (int t = 0; t < kVArms; ++t) {
+            const int i = min(tid + kVThreads * t, kVR * kVT - 1);
             const int ry = i / kVT, cx = i - ry * kVT;
             const int x = min(x0 + cx, W - 1), y = min(max(y0 - kLMax + ry, 0), H - 1);
             av[t] = arms[(size_t)y * W + x];
         }
 #pragma unroll
-        for (int t = 0; t < kN; ++t) {
-            const int i = lane + 64 * t;
+        for (int t = 0; t < kVArms; ++t) {
+            const int i = tid + kVThreads * t;
             const int ry = i / kVT, cx = i - ry * kVT;
             const int x = x0 + cx, y = y0 - kLMax + ry;
             const uint32_t a = x < W && y >= 0 && y < H ? av[t] : 0u;
@@ -111,20 +119,26 @@ __global__ __launch_bounds__(64) void k_vote(const int16_t* __restrict__ din,
         }
     }
     __syncthreads();
-    if (lane < kVR) {  // run-length code staged row `lane`
+    int vlo = S.lo[0], vhi = S.hi[0];  // the tile's vote range (empty when vhi < vlo)
+#pragma unroll
+    for (int k = 1; k < kVWaves; ++k) {
+        vlo = min(vlo, S.lo[k]);
+        vhi = max(vhi, S.hi[k]);
+    }
+    if (tid < kVR) {  // run-length code staged row `tid`
         int n = 0, prev = 0;
-#pragma unroll 6
+#pragma unroll 5
         for (int c = 0; c < kVR; ++c) {
-            const int v = S.d[lane][c];
+            const int v = S.d[tid][c];
             if (c == 0 || v != prev) {
-                S.st[lane][n] = (uint8_t)c;
-                S.rv[lane][n] = (int16_t)v;
+                S.st[tid][n] = (uint8_t)c;
+                S.rv[tid][n] = (int16_t)v;
                 ++n;
                 prev = v;
             }
-            S.rs[lane][c] = (uint8_t)(n - 1);
+            S.rs[tid][c] = (uint8_t)(n - 1);
         }
-        S.st[lane][n] = (uint8_t)kVR;
+        S.st[tid][n] = (uint8_t)kVR;
     }
     __syncthreads();
 
@@ -133,12 +147,13 @@ __global__ __launch_bounds__(64) void k_vote(const int16_t* __restrict__ din,
     const int mine = S.d[ty + kLMax][tx + kLMax];
     const uint32_t a = in ? arms[(size_t)y * W + x] : 0u;
     const int u = min((int)((a >> 16) & 0xff), kLMax), dn = min((int)(a >> 24), kLMax);
+    uint16_t* hist = S.hist[w];
     int best = 0, bc = -1;
     for (int base = vlo; base <= vhi; base += kVBins) {  // uniform
         // bins past vhi get no votes: clear and scan only the nb in range
         const int nb = min(kVBins, vhi - base + 1);
         for (int i = lane; i < nb * 64 / 8; i += 64)
-            reinterpret_cast<uint4*>(S.hist)[i] = make_uint4(0, 0, 0, 0);
+            reinterpret_cast<uint4*>(hist)[i] = make_uint4(0, 0, 0, 0);
         __syncthreads();
         if (mine >= 0) {
             for (int k = -u; k <= dn; ++k) {
@@ -150,12 +165,12 @@ __global__ __launch_bounds__(64) void k_vote(const int16_t* __restrict__ din,
                     if (b >= 0 && b < nb) {
                         const int s0 = max((int)S.st[ry][j], lo);
                         const int s1 = min((int)S.st[ry][j + 1] - 1, hi);
-                        S.hist[b * 64 + lane] += (uint16_t)(s1 - s0 + 1);
+                        hist[b * 64 + lane] += (uint16_t)(s1 - s0 + 1);
                     }
                 }
             }
             for (int b = 0; b < nb; ++b) {
-                const int c = S.hist[b * 64 + lane];
+                const int c = hist[b * 64 + lane];
                 if (c > bc) {
                     bc = c;
                     best = base + b;
@@ -203,7 +218,7 @@ hipError_t launch_vote(const int16_t* dL, const uint8_t* valid, const uint32_t* 
     int16_t* bufs[2] = {buf0, buf1};
     for (int it = 0; it < iters; ++it) {
         int16_t* dst = bufs[it & 1];
-        hipLaunchKernelGGL(k_vote, grid, dim3(64), 0, st, src, mask, arms, W, H, D, dst);
+        hipLaunchKernelGGL(k_vote, grid, dim3(kVThreads), 0, st, src, mask, arms, W, H, D, dst);
         src = dst;
         mask = nullptr;
     }
