@@ -86,14 +86,15 @@ extern "C" dco_status dco_contour_create(dco_contour** out, int W, int H,
     dco_status st;
     if ((st = dev_alloc(&b.fused, q)) != DCO_OK) return fail(st);
     if ((st = dev_alloc(&h->Mn, q)) != DCO_OK) return fail(st);
-    if ((st = dev_alloc(&b.box_max, 1)) != DCO_OK) return fail(st);
-    if ((st = dev_alloc(&b.g2_max, 1)) != DCO_OK) return fail(st);
+    if ((st = dev_alloc(&b.box_max, kContourMaxSlots)) != DCO_OK) return fail(st);
+    if ((st = dev_alloc(&b.g2_max, kContourMaxSlots)) != DCO_OK) return fail(st);
     if ((st = dev_alloc(&b.g, P)) != DCO_OK) return fail(st);
     if ((st = dev_alloc(&b.G2, P)) != DCO_OK) return fail(st);
     if ((st = dev_alloc(&b.state[0], P)) != DCO_OK) return fail(st);
     if ((st = dev_alloc(&b.state[1], P)) != DCO_OK) return fail(st);
-    if ((st = dev_alloc(&b.changed, 1)) != DCO_OK) return fail(st);
-    if (hipHostMalloc((void**)&h->changed_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    if ((st = dev_alloc(&b.changed, kHystGroup)) != DCO_OK) return fail(st);
+    if (hipHostMalloc((void**)&h->changed_host, kHystGroup * sizeof(int), hipHostMallocDefault) !=
+        hipSuccess) {
         (void)hipGetLastError();
         dco_set_error("pinned allocation failed");
         return fail(DCO_ERR_OOM);
@@ -115,16 +116,25 @@ extern "C" dco_status dco_contour_run(dco_contour* h, const uint8_t* rgb, const 
     const dco_contour_params& p = h->p;
     DCO_HIP_CHECK(launch_contour_maps(past, future, h->w, h->h, p.box_radius, rgb, h->W, h->H,
                                       p.T_high, p.T_low, p.T_depth, h->b, mn, MI, h->stream));
+    // Groups of kHystGroup launches, one host check per group; each launch
+    // that changes a pixel turns a weak pixel strong, so at most W H launches
+    // change anything.  The first launch that changed nothing read the final
+    // state; it and the launches before it are counted.
     int parity = 0;
     h->launches = 0;
-    for (;;) {  // each launch that changes a pixel turns a weak pixel strong: at most W H launches
-        DCO_HIP_CHECK(launch_contour_hyst(h->b, h->W, h->H, parity, h->stream));
-        parity = 1 - parity;
-        ++h->launches;
-        DCO_HIP_CHECK(hipMemcpyAsync(h->changed_host, h->b.changed, sizeof(int),
+    for (;;) {
+        DCO_HIP_CHECK(launch_contour_hyst_group(h->b, h->W, h->H, parity, h->stream));
+        DCO_HIP_CHECK(hipMemcpyAsync(h->changed_host, h->b.changed, kHystGroup * sizeof(int),
                                      hipMemcpyDeviceToHost, h->stream));
         DCO_HIP_CHECK(hipStreamSynchronize(h->stream));
-        if (!*h->changed_host) break;
+        int k = 0;
+        while (k < kHystGroup && h->changed_host[k]) ++k;
+        if (k < kHystGroup) {
+            h->launches += k + 1;
+            parity ^= k & 1;  // the input of launch k
+            break;
+        }
+        h->launches += kHystGroup;  // the group's last output is state[parity] again
     }
     DCO_HIP_CHECK(launch_contour_edges(h->b, h->W, h->H, parity, B, h->stream));
     return DCO_OK;

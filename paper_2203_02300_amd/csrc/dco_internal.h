@@ -165,22 +165,28 @@ hipError_t launch_densify_setup(const DensifyBufs& b, const float* Ds, const flo
 hipError_t launch_densify_iters(const DensifyBufs& b, int W, int H, double tol, int n,
                                 hipStream_t st);
 hipError_t launch_densify_out(const DensifyBufs& b, int W, int H, float* D, hipStream_t st);
+
 // Depth contour extraction given the flows (Sec. 5): scratch of one frame
 // (full size W x H, flow grid w x h) and its launches.
+constexpr int kContourMaxSlots = 64;  // slots of the contour kernels' block maxima
 struct ContourBufs {
     float* fused;        // w x h: Eq. 12 before the box filter
-    unsigned* box_max;   // largest box mean (float bits)
-    int* g2_max;         // largest G2
+    unsigned* box_max;   // largest box mean (float bits), kContourMaxSlots partial maxima
+    int* g2_max;         // largest G2, kContourMaxSlots partial maxima
     short2* g;           // W x H Sobel gradients
     int* G2;             // W x H squared magnitudes
     uint8_t* state[2];   // W x H: 0 none, 1 weak, 2 strong (hysteresis ping-pong)
-    int* changed;        // set by a hysteresis launch that changed a pixel
+    int* changed;        // kHystGroup flags: set by a hysteresis launch that changed a pixel
 };
 hipError_t launch_contour_maps(const float* past, const float* future, int w, int h, int R,
                                const uint8_t* rgb, int W, int H, float Thigh, float Tlow,
                                float Tdepth, const ContourBufs& b, float* Mn, float* MI,
                                hipStream_t st);
-hipError_t launch_contour_hyst(const ContourBufs& b, int W, int H, int parity, hipStream_t st);
+// Hysteresis launches go in groups of kHystGroup with one host check per
+// group: launch k of a group does nothing once launch k - 1 changed nothing.
+constexpr int kHystGroup = 4;
+hipError_t launch_contour_hyst_group(const ContourBufs& b, int W, int H, int parity,
+                                     hipStream_t st);
 hipError_t launch_contour_edges(const ContourBufs& b, int W, int H, int parity, uint8_t* B,
                                 hipStream_t st);
 // Arms and packed pixels of both views of B pairs (HWC images of 3 W H

@@ -63,9 +63,10 @@ __device__ inline float flow_score(const float2* F, int w, int h, int x, int y) 
 }
 
 // Largest v over the 256-thread block, then one atomic maximum per block
-// (the maximum does not depend on the order).
+// into one of kContourMaxSlots slots (spread so that thousands of blocks do
+// not queue on one address); the maximum does not depend on the order.
 template <typename T>
-__device__ inline void block_max_to(T v, T* out) {
+__device__ inline void block_max_to(T v, T* slots) {
     __shared__ T red[4];
     for (int o = 32; o > 0; o >>= 1) {
         const T u = __shfl_xor(v, o, 64);
@@ -76,8 +77,26 @@ __device__ inline void block_max_to(T v, T* out) {
     if (threadIdx.x == 0) {
         T m = red[0];
         for (int k = 1; k < 4; ++k) m = red[k] > m ? red[k] : m;
-        atomicMax(out, m);
+        atomicMax(slots + ((blockIdx.x + blockIdx.y * gridDim.x) & (kContourMaxSlots - 1)), m);
     }
+}
+
+// The maximum over the slots, for every thread of the block (all threads
+// must call it).
+template <typename T>
+__device__ inline T slots_max(const T* slots) {
+    static_assert(kContourMaxSlots == 64, "one slot per lane of the first wavefront");
+    __shared__ T m;
+    if (threadIdx.x < 64) {
+        T v = slots[threadIdx.x];
+        for (int o = 32; o > 0; o >>= 1) {
+            const T u = __shfl_xor(v, o, 64);
+            v = u > v ? u : v;
+        }
+        if (threadIdx.x == 0) m = v;
+    }
+    __syncthreads();
+    return m;
 }
 
 // Eq. 12 per pixel of the flow grid (equal scores keep the larger amplitude).
@@ -117,30 +136,42 @@ __global__ __launch_bounds__(256) void k_box(const float* __restrict__ fused, in
 
 __global__ __launch_bounds__(256) void k_norm(float* __restrict__ box, int n,
                                               const unsigned* __restrict__ mx) {
+    const float m = __uint_as_float(slots_max(mx));
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    const float m = __uint_as_float(*mx);
     box[i] = m > 0.0f ? box[i] / m : 0.0f;
 }
 
 // Sobel of the census grey (replicated borders): gx, gy and G2 = gx^2 + gy^2
-// (exact integers); the largest G2 goes to *mx.
+// (exact integers); the largest G2 goes to *mx.  One block per 64 x 4 tile:
+// the grey of the tile and a one-pixel ring is computed once into LDS (the
+// ring clamped to the image, which replicates the borders), then each
+// thread reads its 3 x 3 neighbourhood from there.
+constexpr int kSobTW = 64, kSobTH = 4;
 __global__ __launch_bounds__(256) void k_sobel(const uint8_t* __restrict__ rgb, int W, int H,
                                                short2* __restrict__ g, int* __restrict__ G2,
                                                int* __restrict__ mx) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    constexpr int RW = kSobTW + 2, RH = kSobTH + 2, N = RW * RH;
+    __shared__ int Yt[RH][RW];
+    const int x0 = blockIdx.x * kSobTW, y0 = blockIdx.y * kSobTH, t = threadIdx.x;
+    for (int k = t; k < N; k += 256) {
+        const int ry = k / RW, rx = k - ry * RW;
+        const int xx = dco::clampi(x0 + rx - 1, 0, W - 1), yy = dco::clampi(y0 + ry - 1, 0, H - 1);
+        const size_t q = 3 * ((size_t)yy * W + xx);
+        Yt[ry][rx] = (int)dco::grey_of((uint32_t)rgb[q] | (uint32_t)rgb[q + 1] << 8 |
+                                       (uint32_t)rgb[q + 2] << 16);
+    }
+    __syncthreads();
+    const int tx = t & (kSobTW - 1), ty = t / kSobTW;
+    const int x = x0 + tx, y = y0 + ty;
     int v = 0;
-    if (i < W * H) {
-        const int y = i / W, x = i - y * W;
-        auto Y = [&](int xx, int yy) {
-            const size_t q = (size_t)dco::clampi(yy, 0, H - 1) * W + dco::clampi(xx, 0, W - 1);
-            return (int)dco::grey_of((uint32_t)rgb[3 * q] | (uint32_t)rgb[3 * q + 1] << 8 |
-                                     (uint32_t)rgb[3 * q + 2] << 16);
-        };
-        const int a = Y(x + 1, y - 1) + 2 * Y(x + 1, y) + Y(x + 1, y + 1) - Y(x - 1, y - 1) -
-                      2 * Y(x - 1, y) - Y(x - 1, y + 1);
-        const int b = Y(x - 1, y + 1) + 2 * Y(x, y + 1) + Y(x + 1, y + 1) - Y(x - 1, y - 1) -
-                      2 * Y(x, y - 1) - Y(x + 1, y - 1);
+    if (x < W && y < H) {
+        // Yt[ty + 1 + dy][tx + 1 + dx] is the grey at (x + dx, y + dy), clamped
+        const int a = Yt[ty][tx + 2] + 2 * Yt[ty + 1][tx + 2] + Yt[ty + 2][tx + 2] - Yt[ty][tx] -
+                      2 * Yt[ty + 1][tx] - Yt[ty + 2][tx];
+        const int b = Yt[ty + 2][tx] + 2 * Yt[ty + 2][tx + 1] + Yt[ty + 2][tx + 2] - Yt[ty][tx] -
+                      2 * Yt[ty][tx + 1] - Yt[ty][tx + 2];
+        const size_t i = (size_t)y * W + x;
         g[i] = make_short2((short)a, (short)b);
         v = a * a + b * b;
         G2[i] = v;
@@ -157,10 +188,10 @@ __global__ __launch_bounds__(256) void k_nms(const short2* __restrict__ g,
                                              const int* __restrict__ mxp, float Thigh, float Tlow,
                                              float Tdepth, uint8_t* __restrict__ st,
                                              float* __restrict__ MI) {
+    const int mx = slots_max(mxp);
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= W * H) return;
     const int y = i / W, x = i - y * W;
-    const int mx = *mxp;
     const int v = G2[i];
     if (MI) MI[i] = mx > 0 ? sqrt_rn((float)((double)v / (double)mx)) : 0.0f;
     const short2 gi = g[i];
@@ -201,8 +232,13 @@ __global__ __launch_bounds__(256) void k_nms(const short2* __restrict__ g,
 constexpr int kHTW = 64, kHTH = 16;
 
 __global__ __launch_bounds__(256) void k_hyst(const uint8_t* __restrict__ in, int W, int H,
-                                              uint8_t* __restrict__ out, int* __restrict__ changed) {
+                                              uint8_t* __restrict__ out,
+                                              const int* __restrict__ prev,
+                                              int* __restrict__ changed) {
     __shared__ uint8_t T[kHTH + 2][kHTW + 2];
+    // the previous launch of the group changed nothing: the state is final
+    // (the same value for every thread of every block)
+    if (prev && *prev == 0) return;
     const int x0 = blockIdx.x * kHTW, y0 = blockIdx.y * kHTH;
     for (int k = threadIdx.x; k < (kHTH + 2) * (kHTW + 2); k += 256) {
         const int ty = k / (kHTW + 2), tx = k - ty * (kHTW + 2);
@@ -242,14 +278,14 @@ __global__ __launch_bounds__(256) void k_edges(const uint8_t* __restrict__ st, i
 }
 
 __global__ void k_zero2(unsigned* a, int* b) {
-    if (threadIdx.x == 0) {
-        *a = 0u;
-        *b = 0;
+    if (threadIdx.x < kContourMaxSlots) {
+        a[threadIdx.x] = 0u;
+        b[threadIdx.x] = 0;
     }
 }
 
-__global__ void k_zero1(int* a) {
-    if (threadIdx.x == 0) *a = 0;
+__global__ void k_zero1(int* a, int n) {
+    if ((int)threadIdx.x < n) a[threadIdx.x] = 0;
 }
 
 inline dim3 grid1(int n) { return dim3((n + 255) / 256); }
@@ -260,23 +296,32 @@ hipError_t launch_contour_maps(const float* past, const float* future, int w, in
                                const uint8_t* rgb, int W, int H, float Thigh, float Tlow,
                                float Tdepth, const ContourBufs& b, float* Mn, float* MI,
                                hipStream_t st) {
-    hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, st, b.box_max, b.g2_max);
+    hipLaunchKernelGGL(k_zero2, dim3(1), dim3(kContourMaxSlots), 0, st, b.box_max, b.g2_max);
     hipLaunchKernelGGL(k_fuse, grid1(w * h), dim3(256), 0, st,
                        reinterpret_cast<const float2*>(past),
                        reinterpret_cast<const float2*>(future), w, h, b.fused);
     hipLaunchKernelGGL(k_box, grid1(w * h), dim3(256), 0, st, b.fused, w, h, R, Mn, b.box_max);
     hipLaunchKernelGGL(k_norm, grid1(w * h), dim3(256), 0, st, Mn, w * h, b.box_max);
-    hipLaunchKernelGGL(k_sobel, grid1(W * H), dim3(256), 0, st, rgb, W, H, b.g, b.G2, b.g2_max);
+    hipLaunchKernelGGL(k_sobel, dim3((W + kSobTW - 1) / kSobTW, (H + kSobTH - 1) / kSobTH),
+                       dim3(256), 0, st, rgb, W, H, b.g, b.G2, b.g2_max);
     hipLaunchKernelGGL(k_nms, grid1(W * H), dim3(256), 0, st, b.g, b.G2, W, H, Mn, w, h, b.g2_max,
                        Thigh, Tlow, Tdepth, b.state[0], MI);
     return hipGetLastError();
 }
 
-hipError_t launch_contour_hyst(const ContourBufs& b, int W, int H, int parity, hipStream_t st) {
-    hipLaunchKernelGGL(k_zero1, dim3(1), dim3(64), 0, st, b.changed);
+// Launch k of the group reads state[parity ^ (k & 1)] and writes the other
+// buffer; kHystGroup is even, so the group's last output is state[parity].
+hipError_t launch_contour_hyst_group(const ContourBufs& b, int W, int H, int parity,
+                                     hipStream_t st) {
+    static_assert(kHystGroup % 2 == 0 && kHystGroup <= 64, "even group, one flag per lane");
+    hipLaunchKernelGGL(k_zero1, dim3(1), dim3(64), 0, st, b.changed, kHystGroup);
     const dim3 grid((W + kHTW - 1) / kHTW, (H + kHTH - 1) / kHTH);
-    hipLaunchKernelGGL(k_hyst, grid, dim3(256), 0, st, b.state[parity], W, H, b.state[1 - parity],
-                       b.changed);
+    for (int k = 0; k < kHystGroup; ++k) {
+        const int p = parity ^ (k & 1);
+        hipLaunchKernelGGL(k_hyst, grid, dim3(256), 0, st, b.state[p], W, H, b.state[1 - p],
+                           k ? (const int*)(b.changed + k - 1) : (const int*)nullptr,
+                           b.changed + k);
+    }
     return hipGetLastError();
 }
 
