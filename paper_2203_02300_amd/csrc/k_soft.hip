@@ -64,23 +64,42 @@ __global__ void k_soft_tables(const float* __restrict__ theta, float* __restrict
     }
 }
 
-// Region pixel counts of the left view (as floats) for every pair.
-__global__ void k_soft_counts(SoftGeom g, float* __restrict__ n1, float* __restrict__ n2) {
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int b = blockIdx.z;
-    if (x >= g.W || y >= g.H) return;
+// Region pixel counts of the left view (as floats) for every pair: one
+// block per 64 x 4 tile.  The row lengths l + r + 1 of the tile's columns
+// over kLMax rows above and below, and the column lengths u + dn + 1 of the
+// tile's rows over kLMax columns left and right, go to LDS (0 outside the
+// image, where no arm reaches); each count is then a sum of LDS entries.
+constexpr int kCntTW = 64, kCntTH = 4;
+__global__ __launch_bounds__(256) void k_soft_counts(SoftGeom g, float* __restrict__ n1,
+                                                     float* __restrict__ n2) {
+    constexpr int CH = kCntTH + 2 * kLMax, RW = kCntTW + 2 * kLMax;
+    __shared__ uint8_t hl[CH][kCntTW];  // l + r + 1 down each tile column
+    __shared__ uint8_t vl[kCntTH][RW];  // u + dn + 1 along each tile row
+    const int t = threadIdx.x, b = blockIdx.z;
+    const int x0 = blockIdx.x * kCntTW, y0 = blockIdx.y * kCntTH;
     const uint32_t* A = g.arms + (size_t)b * g.W * g.H;
+    for (int k = t; k < CH * kCntTW; k += 256) {
+        const int r = k / kCntTW, c = k - r * kCntTW;
+        const int x = x0 + c, y = y0 - kLMax + r;
+        const bool in = x < g.W && y >= 0 && y < g.H;
+        const uint32_t q = in ? A[(size_t)y * g.W + x] : 0u;
+        hl[r][c] = in ? (uint8_t)(arm(q, 0) + arm(q, 1) + 1) : 0;
+    }
+    for (int k = t; k < kCntTH * RW; k += 256) {
+        const int r = k / RW, c = k - r * RW;
+        const int x = x0 - kLMax + c, y = y0 + r;
+        const bool in = x >= 0 && x < g.W && y < g.H;
+        const uint32_t q = in ? A[(size_t)y * g.W + x] : 0u;
+        vl[r][c] = in ? (uint8_t)(arm(q, 2) + arm(q, 3) + 1) : 0;
+    }
+    __syncthreads();
+    const int tx = t & (kCntTW - 1), ty = t / kCntTW;
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= g.W || y >= g.H) return;
     const uint32_t a = A[(size_t)y * g.W + x];
     int s1 = 0, s2 = 0;
-    for (int yy = max(0, y - arm(a, 2)); yy <= min(g.H - 1, y + arm(a, 3)); ++yy) {
-        const uint32_t q = A[(size_t)yy * g.W + x];
-        s1 += arm(q, 0) + arm(q, 1) + 1;
-    }
-    for (int xx = max(0, x - arm(a, 0)); xx <= min(g.W - 1, x + arm(a, 1)); ++xx) {
-        const uint32_t q = A[(size_t)y * g.W + xx];
-        s2 += arm(q, 2) + arm(q, 3) + 1;
-    }
+    for (int k = -arm(a, 2); k <= arm(a, 3); ++k) s1 += hl[ty + kLMax + k][tx];
+    for (int k = -arm(a, 0); k <= arm(a, 1); ++k) s2 += vl[ty][tx + kLMax + k];
     const size_t i = (size_t)b * g.W * g.H + (size_t)y * g.W + x;
     n1[i] = (float)s1;
     n2[i] = (float)s2;
@@ -703,7 +722,8 @@ hipError_t soft_prepare(const float* theta, float* tab, const uint32_t* arms, in
                         int D, float* n1, float* n2, hipStream_t st) {
     hipLaunchKernelGGL(k_soft_tables, dim3(4), dim3(256), 0, st, theta, tab);
     SoftGeom g{arms, nullptr, nullptr, B, W, H, D};
-    hipLaunchKernelGGL(k_soft_counts, dim3((W + 63) / 64, (H + 3) / 4, B), dim3(256), 0, st, g, n1,
+    hipLaunchKernelGGL(k_soft_counts, dim3((W + kCntTW - 1) / kCntTW, (H + kCntTH - 1) / kCntTH, B),
+                       dim3(256), 0, st, g, n1,
                        n2);
     return hipGetLastError();
 }
