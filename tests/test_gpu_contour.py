@@ -92,3 +92,16 @@ def test_contour_small_and_odd_frames(torch_mod, W, H):
     past = rng.normal(0, 2, (H // 2, W // 2, 2)).astype(np.float32)
     future = rng.normal(0, 2, (H // 2, W // 2, 2)).astype(np.float32)
     _check(rgb, past, future)
+
+
+def test_hysteresis_over_several_launch_groups(torch_mod):
+    """A weak chain across twelve 64-wide tiles: hysteresis needs more than
+    one group of launches, and the final state comes from the right buffer."""
+    H, W = 96, 768
+    Y = np.full((H, W), 50, np.uint8)
+    Y[48:] = 50 + 20 + np.arange(W) // 12
+    rgb = np.repeat(Y[:, :, None], 3, axis=2)
+    past = np.zeros((H // 2, W // 2, 2), np.float32)
+    past[..., 0] = np.arange(W // 2, dtype=np.float32)[None, :] * 0.1
+    B, n = _check(rgb, past, past, Thigh=0.95, Tlow=0.2)
+    assert n > 8 and (B[47] | B[48]).sum() > 0.9 * W
