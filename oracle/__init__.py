@@ -35,12 +35,27 @@ def build(force: bool = True) -> str:
     return _SO
 
 
+def swap_library(path):
+    """Load the oracle from another build of ``dco_oracle.c`` (the mutation
+    tests load deliberately broken copies); ``None`` returns to the default
+    build.  Returns the path that was in use before."""
+    global _lib, _override
+    prev, _override, _lib = _override, path, None
+    return prev
+
+
+_override = None
+
+
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = C.CDLL(_SO)
+        so = _override
+        if so is None:
+            so = _SO
+            if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+                build(force=True)
+        L = C.CDLL(so)
         P = C.c_void_p
         i, f, dbl = C.c_int, C.c_float, C.c_double
         sig = {
@@ -57,6 +72,7 @@ def lib():
             "orc_vote_finish": [P, P, i, i, i, i, P, P],
             "orc_downscale2": [P, i, i, P],
             "orc_flow_fuse": [P, P, i, i, i, P],
+            "orc_flow_terms": [P, i, i, P, P],
             "orc_contour": [P, i, i, P, i, i, f, f, f, P, P],
             "orc_depth_half": [P, P, i, i, f, P, P],
             "orc_soft_forward": [P, P, P, P, P, i, i, i, dbl, dbl, dbl, dbl, dbl, P, P],
@@ -180,6 +196,16 @@ def flow_fuse(past, future, R=2):
     out = np.empty((h, w), np.float32)
     lib().orc_flow_fuse(_p(past), _p(future), w, h, R, _p(out))
     return out
+
+
+def flow_terms(F):
+    """Amplitude M (Eq. 6-8) and score (Eq. 9-11) of one flow field, h x w."""
+    F = _c(F, np.float32)
+    h, w = F.shape[:2]
+    M = np.empty((h, w), np.float32)
+    S = np.empty((h, w), np.float32)
+    lib().orc_flow_terms(_p(F), w, h, _p(M), _p(S))
+    return M, S
 
 
 def contour(Y, Mn, Thigh=0.06, Tlow=0.03, Tdepth=0.03):

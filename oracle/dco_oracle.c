@@ -379,6 +379,17 @@ static float flow_score(const float* F, int w, int h, int x, int y) {
     return f1 - f0;
 }
 
+/* The two per-pixel terms of one flow field before fusion: the amplitude M
+ * of Eq. 6-8 and the score of Eq. 9-11 (h x w each).  Exposed so that the
+ * tests can pin each term on hand-built flows. */
+void orc_flow_terms(const float* F, int w, int h, float* M, float* score) {
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            M[y * w + x] = flow_amp(F, w, h, x, y);
+            score[y * w + x] = flow_score(F, w, h, x, y);
+        }
+}
+
 /* Eq. 12 and the box filter of Sec. 5.2, then the normalisation of
  * Sec. 5.3.2: Mfuse = M_past where score_past > score_future, M_future
  * where score_future > score_past; then the mean over the (2R + 1)^2 window

@@ -171,3 +171,97 @@ def box_mean_int(a, r):
 
 def alpha_closed(L, gamma=1.0, eps=0.8):
     return 1.0 - math.exp(-gamma / (L + eps))
+
+
+# ---------------------------------------------------------------------------
+# Depth contour filter (Sec. 5), written with whole-array shifts
+# ---------------------------------------------------------------------------
+
+def flow_terms_ref(F):
+    """Amplitude (Eq. 6-8) and score (Eq. 9-11) of one flow field, float32,
+    as array expressions: neighbours by slicing, p0 / p1 by fancy indexing."""
+    F = np.asarray(F, np.float32)
+    U, V = F[..., 0], F[..., 1]
+    h, w = U.shape
+    r = np.sqrt(U * U + V * V)                       # float32, correctly rounded
+    gu = np.zeros_like(r)
+    gv = np.zeros_like(r)
+    gu[:, :-1] = np.abs(r[:, 1:] - r[:, :-1])
+    gv[:-1, :] = np.abs(r[1:, :] - r[:-1, :])
+    M = np.maximum(gu, gv)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ex = np.where(r > 0, U / r, np.float32(0)).astype(np.float32)
+        ey = np.where(r > 0, V / r, np.float32(0)).astype(np.float32)
+    sx, sy = np.rint(ex).astype(int), np.rint(ey).astype(int)
+    ys, xs = np.mgrid[0:h, 0:w]
+    x1, y1 = np.clip(xs + sx, 0, w - 1), np.clip(ys + sy, 0, h - 1)
+    x0, y0 = np.clip(xs - sx, 0, w - 1), np.clip(ys - sy, 0, h - 1)
+    f1 = U[y1, x1] * ex + V[y1, x1] * ey
+    f0 = U[y0, x0] * ex + V[y0, x0] * ey
+    S = np.where(r > 0, f1 - f0, np.float32(0)).astype(np.float32)
+    return M, S
+
+
+def flow_fuse_ref(past, future, R=2):
+    """Eq. 12 (larger score wins; equal scores keep the larger amplitude),
+    the clipped (2R+1)^2 window mean in float64, and the division by the
+    maximum.  Agrees with the oracle to float32 rounding of the window sums."""
+    Mp, Sp = flow_terms_ref(past)
+    Mf, Sf = flow_terms_ref(future)
+    fu = np.where(Sp > Sf, Mp, np.where(Sf > Sp, Mf, np.maximum(Mp, Mf))).astype(np.float64)
+    h, w = fu.shape
+    pad = np.pad(fu, R)
+    one = np.pad(np.ones((h, w)), R)
+    s = np.zeros((h, w))
+    n = np.zeros((h, w))
+    for dy in range(2 * R + 1):
+        for dx in range(2 * R + 1):
+            s += pad[dy:dy + h, dx:dx + w]
+            n += one[dy:dy + h, dx:dx + w]
+    box = s / n
+    return box / box.max() if box.max() > 0 else np.zeros_like(box)
+
+
+def contour_ref(Y, Mn, Thigh=0.06, Tlow=0.03, Tdepth=0.03):
+    """Gated Canny of Sec. 5.3 with the readings of the oracle, as array
+    operations: Sobel by shifted copies of the edge-padded image, the sector
+    of every pixel, suppression by gathering the two neighbours, and
+    hysteresis as 8-connected component labelling (scipy)."""
+    from scipy import ndimage
+    Y = np.asarray(Y, np.int64)
+    H, W = Y.shape
+    pad = np.pad(Y, 1, mode="edge")
+
+    def at(dx, dy):
+        return pad[1 + dy:1 + dy + H, 1 + dx:1 + dx + W]
+
+    gx = (at(1, -1) + 2 * at(1, 0) + at(1, 1)) - (at(-1, -1) + 2 * at(-1, 0) + at(-1, 1))
+    gy = (at(-1, 1) + 2 * at(0, 1) + at(1, 1)) - (at(-1, -1) + 2 * at(0, -1) + at(1, -1))
+    G2 = gx * gx + gy * gy
+    mx = int(G2.max())
+    ax, ay = np.abs(gx), np.abs(gy)
+    horiz = 128 * ay < 53 * ax
+    vert = ~horiz & (128 * ax < 53 * ay)
+    same = (gx > 0) == (gy > 0)
+    dx = np.where(horiz, 1, np.where(vert, 0, 1))
+    dy = np.where(horiz, 0, np.where(vert, 1, np.where(same, 1, -1)))
+    ys, xs = np.mgrid[0:H, 0:W]
+    G2p = np.pad(G2, 1)                                  # 0 outside the image
+    before = G2p[1 + ys - dy, 1 + xs - dx]
+    after = G2p[1 + ys + dy, 1 + xs + dx]
+    keep = (G2 > before) & (G2 >= after)
+    h, w = Mn.shape
+    Mn = np.asarray(Mn, np.float32)
+    gate = Mn[np.minimum(ys // 2, h - 1), np.minimum(xs // 2, w - 1)] >= np.float32(Tdepth)
+    keep &= gate
+    v = G2.astype(np.float64)
+    th, tl = float(np.float32(Thigh)), float(np.float32(Tlow))   # float parameters
+    strong = keep & (v > th * th * mx)
+    weak = keep & (v > tl * tl * mx)
+    lab, n = ndimage.label(weak, structure=np.ones((3, 3)))
+    on = np.zeros(n + 1, bool)
+    on[np.unique(lab[strong])] = True
+    on[0] = False
+    B = on[lab].astype(np.uint8)
+    MI = (np.sqrt((v / mx).astype(np.float32)) if mx > 0 else np.zeros((H, W), np.float32))
+    return B, MI

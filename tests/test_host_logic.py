@@ -2,11 +2,22 @@
 
 1. Stage-1 rounding: floor(n / N) == (n * m) >> sh with sh = 31 + ceil(log2 N)
    and m = ceil(2^sh / N) < 2^32, for every 1 <= N <= 1225 and 0 <= n < 2^31.
+   Proof: with e = m N - 2^sh in [0, N), n m / 2^sh = n / N + n e / (N 2^sh)
+   and the second term is below 2^31 N / (N 2^(31 + lg)) = 2^-lg <= 1 / N, so
+   it cannot carry n / N = k + j / N (j <= N - 1) past k + 1.  The test checks
+   the bound m < 2^32 for every N and the identity at the extreme numerators.
 2. Final division: with y = RN(1/N), q0 = RN(a y), r = RN(a - q0 N) (one
-   fused multiply-add), q = RN(q0 + r y) equals RN(a / N) for every float a
-   that is an integer below 2^31 and every integer 1 <= N <= 1225.
-Both are emulated exactly (Python integers, fractions) on dense samples.
+   fused multiply-add), q = RN(q0 + r y) equals RN(a / N) for every float
+   0 <= a < 2^31 and every integer 1 <= N <= 1225.  The one-correction
+   theorem for a faithful first quotient does not cover a q0 up to two ulps
+   off, so the claim is checked exhaustively instead: tests/div_exhaustive.c
+   enumerates every odd N and every 24-bit significand (5.1e9 cases, the
+   host's fused multiply-add), and two exact scaling reductions (below) carry
+   the result to every even N and every exponent.  A sampled exact-rational
+   emulation stays as a second, independent check.
 """
+import os
+import subprocess
 from fractions import Fraction
 
 import numpy as np
@@ -67,6 +78,44 @@ def test_reciprocal_division_exact():
             assert r == a - q0 * N          # the residual is exact
             q = rn32(q0 + r * y)
             assert q == rn32(a / N), (N, s)
+
+
+def test_reciprocal_division_exhaustive(tmp_path):
+    """Every odd N <= 1225 and every significand in [2^23, 2^24), on all host
+    threads (a few seconds).  The program prints the number of cases."""
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "div_exhaustive.c")
+    exe = str(tmp_path / "div_exhaustive")
+    subprocess.check_call(["gcc", "-O2", "-mfma", "-ffp-contract=off", "-std=c99", "-pthread",
+                           "-o", exe, src, "-lm"])
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    r = subprocess.run([exe, str(NMAX), str(threads)], capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 0, r.stdout
+    assert f"checks {613 * (1 << 23)} nmax {NMAX} fail 0" in r.stdout
+
+
+def test_division_scaling_reductions():
+    """The two reductions the exhaustive program relies on, checked with exact
+    rationals on samples: the sequence for N = 2^k N' equals 2^-k times the
+    sequence for N', and the sequence for m 2^e equals 2^e times the one
+    for m."""
+    rng = np.random.default_rng(5)
+
+    def seq(a, N):
+        y = rn32(Fraction(1, N))
+        q0 = rn32(a * y)
+        r = rn32(a - q0 * N)
+        return rn32(q0 + r * y)
+
+    for _ in range(300):
+        Np = int(rng.integers(0, 612)) * 2 + 1
+        k = int(rng.integers(0, 11))
+        if Np << k > NMAX:
+            continue
+        m = int(rng.integers(1 << 23, 1 << 24))
+        e = int(rng.integers(-23, 8))
+        a = Fraction(m) * Fraction(2) ** e
+        assert seq(a, Np << k) == seq(Fraction(m), Np) * Fraction(2) ** (e - k)
 
 
 def test_bench_oracle_bands_equal_the_whole_frame(monkeypatch):

@@ -88,3 +88,85 @@ def test_solution_minimises_the_printed_objective(seed):
                    dz.energy(D - e, Ds, Dpre, B, Mf, MI)) / (2 * h)
     scale = np.abs(b).max()
     assert np.abs(g).max() < 1e-6 * max(scale, 1.0)
+
+
+# ---------------------------------------------------------------------------
+# Edge weights with s = M_fuse * M_I != 0, solved by hand
+# ---------------------------------------------------------------------------
+
+def _pair_solution(a, b, w, lam_d=0.8, lam_s=1.2):
+    # two pixels with data a and b joined by one edge of weight w:
+    # E = lam_d ((D0 - a)^2 + (D1 - b)^2) + 2 lam_s w (D0 - D1)^2 (the double
+    # sum visits the pair twice).  With D0 = m - t, D1 = m + t, m = (a + b) / 2,
+    # dE/dt = 0 gives t = lam_d (b - a) / (2 lam_d + 8 lam_s w).
+    m = 0.5 * (a + b)
+    t = lam_d * (b - a) / (2 * lam_d + 8 * lam_s * w)
+    return m - t, m + t
+
+
+@pytest.mark.parametrize("vertical", [False, True])
+def test_pair_weight_uses_the_smaller_product(vertical):
+    # s0 = 0.5 * 0.5 = 0.25, s1 = 1.0 * 0.75 = 0.75: w = 1 - min = 0.75.
+    # D0, D1 = 3.5 -/+ 0.8 * 5 / (1.6 + 7.2).
+    # Kills: min swapped for max (w = 0.25 gives 2.5, 4.5); s as a sum
+    # (M_fuse + M_I > 1 gives w = 0); the right / down weight taken from the
+    # wrong neighbour.
+    Ds = np.array([[1.0, 6.0]])
+    Mf = np.array([[0.5, 1.0]])
+    MI = np.array([[0.5, 0.75]])
+    B = np.zeros((1, 2), np.uint8)
+    if vertical:
+        Ds, Mf, MI, B = Ds.T.copy(), Mf.T.copy(), MI.T.copy(), B.T.copy()
+    D = dz.densify(Ds, None, B, Mf, MI).ravel()
+    want = _pair_solution(1.0, 6.0, 0.75)
+    assert np.allclose(D, want, atol=1e-12)
+    assert abs(want[0] - (3.5 - 4.0 / 8.8)) < 1e-15
+
+
+def test_pair_weight_is_clamped_at_zero():
+    # s = 2 on both pixels: 1 - min(s) < 0 is clamped to 0, the pixels
+    # decouple and keep their data.  Kills: the clamp removed (a negative
+    # weight pushes the two depths apart).
+    D = dz.densify(np.array([[1.0, 6.0]]), None, np.zeros((1, 2), np.uint8),
+                   np.array([[2.0, 2.0]]), np.array([[1.0, 1.0]]))
+    assert np.allclose(D, [[1.0, 6.0]], atol=1e-12)
+
+
+def test_pair_on_the_contour_stays_coupled():
+    # both pixels on B_dp: the edge is not cut (only a pixel pair with exactly
+    # one end on the contour is).  Kills: cutting every edge that touches B.
+    Mf = np.array([[0.5, 1.0]])
+    MI = np.array([[0.5, 0.75]])
+    D = dz.densify(np.array([[1.0, 6.0]]), None, np.ones((1, 2), np.uint8), Mf, MI)
+    assert np.allclose(D.ravel(), _pair_solution(1.0, 6.0, 0.75), atol=1e-12)
+    D1 = dz.densify(np.array([[1.0, 6.0]]), None, np.array([[1, 0]], np.uint8), Mf, MI)
+    assert np.allclose(D1, [[1.0, 6.0]], atol=1e-12)
+
+
+def test_two_by_two_grid_with_every_weight_different():
+    # s = M_fuse * M_I = [[0.1, 0.6], [0.3, 0.9]] (M_I = 1).  Edge weights by
+    # hand: top (0,0)-(0,1): 1 - 0.1 = 0.9; bottom (1,0)-(1,1): 1 - 0.3 = 0.7;
+    # left (0,0)-(1,0): 1 - 0.1 = 0.9; right (0,1)-(1,1): 1 - 0.6 = 0.4.
+    # Data on the diagonal only.  The normal equations written out from
+    # Eq. 20: 2 lam_d w_sp (D_p - Ds_p) + 4 lam_s sum_e w_e (D_p - D_q) = 0.
+    # Kills: the weights of the down edges computed with the transposed s
+    # (they become 0.9 / 0.4 / 0.7 in other places).
+    s = np.array([[0.1, 0.6], [0.3, 0.9]])
+    Ds = np.array([[2.0, 0.0], [0.0, 7.0]])
+    edges = {(0, 1): 0.9, (2, 3): 0.7, (0, 2): 0.9, (1, 3): 0.4}   # pixels 0..3 row-major
+    lam_d, lam_s = 0.8, 1.2
+    A = np.zeros((4, 4))
+    rhs = np.zeros(4)
+    for p, v in enumerate(Ds.ravel()):
+        if v > 0:
+            A[p, p] += 2 * lam_d
+            rhs[p] += 2 * lam_d * v
+    for (p, q), w in edges.items():
+        for a, b in ((p, q), (q, p)):
+            A[a, a] += 4 * lam_s * w
+            A[a, b] -= 4 * lam_s * w
+    want = np.linalg.solve(A, rhs).reshape(2, 2)
+    D = dz.densify(Ds, None, np.zeros((2, 2), np.uint8), s, np.ones((2, 2)))
+    assert np.allclose(D, want, atol=1e-12)
+    wr, wd = dz.edge_weights(np.zeros((2, 2), np.uint8), s, np.ones((2, 2)))
+    assert np.allclose(wr, [[0.9, 0.0], [0.7, 0.0]]) and np.allclose(wd, [[0.9, 0.4], [0.0, 0.0]])
