@@ -71,6 +71,14 @@ def measured_traffic():
     return int(f["traffic_bytes_per_launch"]) if f else None
 
 
+def measured_frame_traffic():
+    """HBM bytes of one whole one-call frame (FETCH_SIZE + WRITE_SIZE of
+    every kernel of the step, copy-calibrated) from the committed counter
+    summary, or None when a kernel of the step has changed since."""
+    f = _profile_fields(TRAFFIC_PROFILE, ["frame_traffic_bytes"])
+    return int(f["frame_traffic_bytes"]) if f else None
+
+
 def measured_busy():
     """Busy fractions of the dominant kernel's VALU, TA, TD and LDS from the
     committed SQ/TA/TD counter summary (same validity rule as the traffic)."""
@@ -161,14 +169,26 @@ def oracle_bands(L, R, D, nbands, threads):
 
 def cpu_all_cores(L, R, D):
     """Second CPU figure: the same oracle on every host core the process may
-    use (at most 16), over the whole frame in row bands."""
+    use (at most 16), over the whole frame in row bands.  Returns the figure
+    and the oracle's (disp, valid) of the whole frame."""
     n = min(16, len(os.sched_getaffinity(0)))
     H, W = L.shape[:2]
-    _, _, dt, rows = oracle_bands(L, R, D, n, n)
+    disp, valid, dt, rows = oracle_bands(L, R, D, n, n)
     return dict(value=W * H * D / dt / 1e6, unit="Mpix·disp/s", cores=n,
                 kind="oracle, row bands on threads",
                 sample=f"whole {W}x{H} D={D} frame in {n} bands with a {BAND_HALO}-row halo "
-                       f"({rows} rows matched in all), {dt:.1f} s")
+                       f"({rows} rows matched in all), {dt:.1f} s"), disp, valid
+
+
+def accuracy_gate(disp, valid, odisp, ovalid):
+    """The timed step's output against the oracle's whole frame, bit for bit."""
+    bad_v = int(np.count_nonzero(valid != ovalid))
+    bad_d = int(np.count_nonzero(disp.view(np.uint32) != odisp.astype(np.float32).view(np.uint32)))
+    return dict(bit_exact=bad_v == 0 and bad_d == 0, mismatched_valid=bad_v,
+                mismatched_disp=bad_d, pixels=int(valid.size),
+                valid_frac=round(float(ovalid.mean()), 4),
+                compared="every pixel of disp (float bits) and valid of the timed step's "
+                         "output against the oracle's whole frame")
 
 
 def main():
@@ -252,12 +272,25 @@ def main():
     # for the four range sums and two divisions per (p, d), for 2 V entries
     ops_per_unit = 40
     achieved = ops_per_unit * 2 * V / (agg_ms / 1e3) / 1e12
+    # the whole step against HBM: the staged path's algorithmic bytes
+    # (32 V + 99 P, what the four-call chain must move) and the bytes the
+    # one-call step measurably moves (all of its kernels, counters)
+    staged_bytes = 32 * V + 99 * P
+    frame_bytes = measured_frame_traffic()
+    step_s = ms_step / 1e3
+    hbm = dict(staged_algorithmic_bytes=staged_bytes,
+               staged_bytes_frac=round(staged_bytes / step_s / 1e9 / HBM_PEAK_GBS, 4),
+               measured_frame_bytes=frame_bytes,
+               measured_frame_frac=(round(frame_bytes / step_s / 1e9 / HBM_PEAK_GBS, 4)
+                                    if frame_bytes else None),
+               peak_GBs=HBM_PEAK_GBS)
     roofline = dict(bound="alu", achieved=round(achieved, 2), peak=round(VALU_PEAK_TOPS, 2),
                     unit="TOP/s", frac=round(achieved / VALU_PEAK_TOPS, 4), traffic=measured_traffic(),
                     kernel="k_agg_pair<2>", kernel_ms=round(agg_ms, 4),
                     ops_per_pd=ops_per_unit, units_per_launch=2 * V,
-                    units_busy=measured_busy())
+                    units_busy=measured_busy(), hbm_step=hbm)
 
+    head_disp, head_valid = disp.cpu().numpy(), valid.cpu().numpy()
     extras = {"stage_ms": {n: round(t, 4) for n, t in zip(STAGES, per_call)},
               "step_ms": step_distribution(m, gL, gR, disp, valid, args.steps)}
     if "staged" in want:
@@ -289,11 +322,18 @@ def main():
         torch.cuda.empty_cache()
 
     cpu = None
+    accuracy = dict(bit_exact=None, compared="not run (--no-cpu)")
     if not args.no_cpu:
         log(f"bench: CPU oracle on {args.cpu_rows} rows")
         cpu = cpu_baseline(L, R, D, args.cpu_rows)
         log("bench: CPU oracle on all cores (row bands)")
-        extras["cpu_all_cores"] = _guarded(cpu_all_cores, L, R, D)
+        res = _guarded(cpu_all_cores, L, R, D)
+        if isinstance(res, tuple):
+            extras["cpu_all_cores"], odisp, ovalid = res
+            accuracy = accuracy_gate(head_disp, head_valid, odisp, ovalid)
+            log(f"bench: accuracy gate bit_exact={accuracy['bit_exact']}")
+        else:
+            extras["cpu_all_cores"] = res
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpix·disp/s",
@@ -304,6 +344,7 @@ def main():
         "config": {"workload": "plain matcher, one 1280x720 RGB pair, D=128, 10 slanted planes "
                                "+ 2 boxes, noise 2, right gain 0.9..1.1 (seed 3)",
                    "W": W, "H": H, "D": D, "entry": "dco_stereo_match"},
+        "bit_exact": accuracy["bit_exact"], "accuracy": accuracy,
         "roofline": roofline, "cpu_baseline": cpu, "extras": extras,
     }
     print(json.dumps(out), flush=True)

@@ -57,7 +57,11 @@ typedef enum {
  * two-stage aggregation, LR tolerance 0, sub-pixel on. */
 typedef struct {
     int census_w, census_h;   /* odd, census_w * census_h - 1 <= 64 (default 9, 7) */
-    int arm_L1, arm_tau1;     /* 0 <= L1 <= 17; 1 <= tau1 <= 256 (default 17, 20) */
+    int arm_L1, arm_tau1;     /* 0 <= L1 <= 17; 1 <= tau1 <= 256 (default 17, 20).
+                                 The paper gives no L1; the kernels are built for
+                                 arms of at most 17 (aggregation halos of 34
+                                 columns and LDS rings of 36 rows), so a larger
+                                 L1 is refused with DCO_ERR_ARG. */
     float lambda_ad;          /* > 0 (Eq. 1) */
     float lambda_census;      /* > 0 (Eq. 1) */
     float gamma_L, eps;       /* > 0 (Eq. 1, weight alpha) */
@@ -138,10 +142,18 @@ dco_status dco_aggregate(dco_stereo* h, const float* cost, const uint8_t* arms_r
 dco_status dco_wta_lrcheck(dco_stereo* h, const float* aggL, const float* aggR, float* disp,
                            uint8_t* valid, int16_t* dL, int16_t* dR);
 
-/* The whole plain matcher in one call: census and arms of both views, then
- * cost, aggregation and WTA of both views streamed per disparity with no
- * cost volume in memory, then the LR check.  Results are bit-identical to
- * dco_census -> dco_cost_volume -> dco_aggregate -> dco_wta_lrcheck.
+/* The whole plain matcher in one call (Sec. 4, Eq. 1-3, LR check):
+ *  1. census, arms and the region counts of both views (one launch);
+ *  2. the raw cost of Eq. 1 computed on the fly inside the two-stage
+ *     aggregation of both views (one launch): no raw cost volume exists,
+ *     but the two aggregated volumes (D x H x W float each, 2 x 472 MB at
+ *     1280 x 720, D = 128) are written to the handle's scratch;
+ *  3. WTA with sub-pixel refinement of both views, reading those volumes
+ *     (a separate pass), then the LR check;
+ *  4. when vote_iters > 0, the Eq. 4 vote of dco_vote_refine.
+ * With vote_iters = 0 the results are bit-identical to dco_census ->
+ * dco_cost_volume -> dco_aggregate -> dco_wta_lrcheck; with vote_iters = n
+ * they equal that chain followed by dco_vote_refine with iters = n.
  * rgbL, rgbR: H x W x 3 uint8; disp: H x W float (out); valid: H x W uint8 (out). */
 dco_status dco_stereo_match(dco_stereo* h, const uint8_t* rgbL, const uint8_t* rgbR, float* disp,
                             uint8_t* valid);
@@ -295,9 +307,12 @@ dco_status dco_contour_launches(dco_contour* h, int* launches);
  * choice from its cache file (the environment variable DCO_AUTOTUNE_CACHE,
  * default $HOME/.cache/dco_stereo_autotune.txt; DCO_AUTOTUNE=0 skips tuning
  * and takes full-height bands of one disparity).  It then allocates each
- * pair's scratch, builds the device work list (stages in order, longest
- * aggregation items first) and captures its five stage launches (each a
- * persistent work-list kernel over all pairs) in one HIP graph.  Synchronous. */
+ * pair's scratch, builds the device work list (stages in order; the
+ * aggregation items in pair, view, strip, band, disparity order, cut into
+ * one contiguous part of about equal cost per XCD, so that the workgroups
+ * an XCD runs together share a strip's inputs in its L2) and captures its
+ * five stage launches (each a persistent work-list kernel over all pairs)
+ * in one HIP graph.  Synchronous. */
 dco_status dco_batch_create(dco_batch** out, int n, const int* W, const int* H, const int* D,
                             const dco_params* p, void* stream);
 void dco_batch_destroy(dco_batch* b);
@@ -341,6 +356,23 @@ dco_status dco_soft_backward(dco_stereo* h, int B, const uint8_t* L, const uint8
 /* ---- Diagnostics ---- */
 const char* dco_status_string(dco_status s);
 const char* dco_last_error(void); /* thread-local; "" when none */
+
+/* Aggregated costs A2 (Eq. 2 applied as two stages) of disparities
+ * d0 .. d0 + n - 1 of one view (0 = left reference, 1 = right), as left in
+ * the handle's scratch by the last dco_stereo_match: copied on the handle's
+ * stream into out (device, n x H x W float).  Lets a test compare the fused
+ * path's volume element by element.  DCO_ERR_ARG for a bad view or range. */
+dco_status dco_stereo_agg_slices(dco_stereo* h, int view, int d0, int n, float* out);
+
+/* Testing hooks for the error paths.  dco_debug_fail_alloc(k) makes the
+ * k-th device or pinned allocation made by the library from now on fail
+ * with DCO_ERR_OOM (k <= 0 disarms; DCO_FAIL_ALLOC=k in the environment arms
+ * it when the library loads).  dco_debug_live_allocations() is the number
+ * of the library's device and pinned allocations not yet freed, so a test
+ * can check that a failed create frees exactly what it allocated.
+ * Process-wide; not meant for concurrent use with other calls. */
+void dco_debug_fail_alloc(int k);
+long dco_debug_live_allocations(void);
 
 #ifdef __cplusplus
 }

@@ -77,6 +77,7 @@ def lib():
             "orc_depth_half": [P, P, i, i, f, P, P],
             "orc_soft_forward": [P, P, P, P, P, i, i, i, dbl, dbl, dbl, dbl, dbl, P, P],
             "orc_soft_grad": [P, P, P, P, P, i, i, i, dbl, dbl, dbl, dbl, dbl, P, P],
+            "orc_soft_grad_mag": [P, P, P, P, P, i, i, i, dbl, dbl, dbl, dbl, dbl, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -321,4 +322,19 @@ def soft_grad(L, R, cL, cR, armsL, D, gdhat, gamma=1.0, eps=0.8, lam_ad=10.0, la
     lib().orc_soft_grad(_p(L), _p(R), _p(_c(cL, np.uint64)), _p(_c(cR, np.uint64)),
                         _p(_c(armsL, np.uint8)), W, H, D, gamma, eps, lam_ad, lam_c, T,
                         _p(_c(gdhat, np.float64)), _p(g))
+    return g
+
+
+def soft_grad_mag(L, R, cL, cR, armsL, D, gdhat, gamma=1.0, eps=0.8, lam_ad=10.0, lam_c=30.0,
+                  T=1.0):
+    """Per component, the sum of the magnitudes of the terms of soft_grad (a
+    bound on the sum of absolute contributions): the scale for the rounding
+    error of a float evaluation of the same gradient."""
+    L = _c(L, np.uint8)
+    R = _c(R, np.uint8)
+    H, W = L.shape[:2]
+    g = np.empty(3, np.float64)
+    lib().orc_soft_grad_mag(_p(L), _p(R), _p(_c(cL, np.uint64)), _p(_c(cR, np.uint64)),
+                            _p(_c(armsL, np.uint8)), W, H, D, gamma, eps, lam_ad, lam_c, T,
+                            _p(_c(gdhat, np.float64)), _p(g))
     return g

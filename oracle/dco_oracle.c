@@ -732,10 +732,10 @@ void orc_soft_forward(const uint8_t* rgbL, const uint8_t* rgbR, const uint64_t* 
  * then the adjoint of each region sum (every output scatters its adjoint back
  * over the same ranges it summed), divided by N where the forward divided,
  * and finally dc/dlambda.  grad[0..2] = (lambda_ad, lambda_census, T). */
-void orc_soft_grad(const uint8_t* rgbL, const uint8_t* rgbR, const uint64_t* cL,
-                   const uint64_t* cR, const uint8_t* armsL, int W, int H, int D, double gamma,
-                   double eps, double lam_ad, double lam_c, double T, const double* gdhat,
-                   double* grad) {
+static void soft_grad_impl(const uint8_t* rgbL, const uint8_t* rgbR, const uint64_t* cL,
+                           const uint64_t* cR, const uint8_t* armsL, int W, int H, int D,
+                           double gamma, double eps, double lam_ad, double lam_c, double T,
+                           const double* gdhat, int magnitude, double* grad) {
     size_t P = (size_t)W * H;
     soft_geom g = {W, H, D, armsL, (double*)malloc(8 * P), (double*)malloc(8 * P)};
     soft_counts(&g);
@@ -766,7 +766,9 @@ void orc_soft_grad(const uint8_t* rgbL, const uint8_t* rgbR, const uint64_t* cL,
         for (size_t i = 0; i < P; ++i) {
             double w = exp(-(a2[i] - mn[i]) / T) / z[i];
             gA[i] = gdhat[i] * w * (dhat[i] - d) / T;
-            gT += gdhat[i] * w * (d - dhat[i]) * a2[i] / (T * T);
+            double tT = gdhat[i] * w * (d - dhat[i]) * a2[i] / (T * T);
+            if (magnitude) gA[i] = fabs(gA[i]), tT = fabs(tT);
+            gT += tT;
         }
         /* adjoint of A2 = S2 / N2, S2 = horizontal sum of E2 over p's arms */
         memset(g1, 0, 8 * P);
@@ -799,8 +801,8 @@ void orc_soft_grad(const uint8_t* rgbL, const uint8_t* rgbR, const uint64_t* cL,
         soft_cost_slice(rgbL, rgbR, cL, cR, armsL, W, H, d, gamma, eps, lam_ad, lam_c, c, dca,
                         dcc);
         for (size_t i = 0; i < P; ++i) {
-            gad += g2[i] * dca[i];
-            gc += g2[i] * dcc[i];
+            gad += g2[i] * (magnitude ? fabs(dca[i]) : dca[i]);
+            gc += g2[i] * (magnitude ? fabs(dcc[i]) : dcc[i]);
         }
     }
     grad[0] = gad;
@@ -808,4 +810,25 @@ void orc_soft_grad(const uint8_t* rgbL, const uint8_t* rgbR, const uint64_t* cL,
     grad[2] = gT;
     free(vol); free(dhat); free(c); free(dca); free(dcc); free(gA); free(g1); free(g2);
     free(mn); free(z); free(g.n1); free(g.n2);
+}
+
+void orc_soft_grad(const uint8_t* rgbL, const uint8_t* rgbR, const uint64_t* cL,
+                   const uint64_t* cR, const uint8_t* armsL, int W, int H, int D, double gamma,
+                   double eps, double lam_ad, double lam_c, double T, const double* gdhat,
+                   double* grad) {
+    soft_grad_impl(rgbL, rgbR, cL, cR, armsL, W, H, D, gamma, eps, lam_ad, lam_c, T, gdhat, 0,
+                   grad);
+}
+
+/* The same chain with every per-entry term replaced by its magnitude: the
+ * seed |dL/dA2|, the temperature terms |.|, and |dc/dlambda|.  The region
+ * adjoints are non-negative linear maps, so mag[k] bounds the sum of the
+ * absolute values of the terms that add up to grad[k]: the scale against
+ * which a float evaluation's rounding error in grad[k] is measured. */
+void orc_soft_grad_mag(const uint8_t* rgbL, const uint8_t* rgbR, const uint64_t* cL,
+                       const uint64_t* cR, const uint8_t* armsL, int W, int H, int D,
+                       double gamma, double eps, double lam_ad, double lam_c, double T,
+                       const double* gdhat, double* mag) {
+    soft_grad_impl(rgbL, rgbR, cL, cR, armsL, W, H, D, gamma, eps, lam_ad, lam_c, T, gdhat, 1,
+                   mag);
 }

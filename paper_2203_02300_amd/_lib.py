@@ -22,7 +22,8 @@ EXPORTS = (
     "dco_densify_destroy", "dco_densify_run", "dco_densify_stats",
     "dco_contour_default_params", "dco_contour_create", "dco_contour_destroy",
     "dco_contour_run", "dco_contour_launches",
-    "dco_status_string", "dco_last_error",
+    "dco_status_string", "dco_last_error", "dco_stereo_agg_slices", "dco_debug_fail_alloc",
+    "dco_debug_live_allocations",
 )
 
 DCO_OK = 0
@@ -107,6 +108,9 @@ def lib():
         "dco_contour_launches": (st, [P, C.POINTER(C.c_int)]),
         "dco_status_string": (C.c_char_p, [st]),
         "dco_last_error": (C.c_char_p, []),
+        "dco_stereo_agg_slices": (st, [P, i, i, i, P]),
+        "dco_debug_fail_alloc": (None, [i]),
+        "dco_debug_live_allocations": (C.c_long, []),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)

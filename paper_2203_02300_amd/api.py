@@ -178,6 +178,16 @@ class StereoMatcher:
         check(lib().dco_stereo_last_disparities(self._h, _ptr(dL), _ptr(dR)))
         return dL, dR
 
+    def agg_slices(self, view, d0=0, n=None):
+        """Aggregated costs of disparities d0 .. d0 + n - 1 of one view (0 =
+        left, 1 = right) left in the scratch by the last ``match``:
+        an n x H x W float tensor."""
+        self._begin()
+        n = self.D - d0 if n is None else n
+        out = self._empty((n, self.H, self.W), torch.float32)
+        check(lib().dco_stereo_agg_slices(self._h, int(view), int(d0), int(n), _ptr(out)))
+        return out
+
     def match_staged(self, L, R):
         """The same result through the four staged calls (volumes in memory)."""
         cL, aL = self.census(L)

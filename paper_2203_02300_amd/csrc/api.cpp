@@ -1,6 +1,7 @@
 // api.cpp -- host side of the C ABI declared in include/dco_stereo.h:
 // argument validation, the matcher handle, the Eq. 1 lookup tables, scratch
 // memory and the kernel sequence of each entry point.
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -12,6 +13,27 @@
 #include "dco_internal.h"
 
 static thread_local char g_err[512] = "";
+
+// Allocation-failure injection: allocations left before the one that fails
+// (0 = none armed), and the count of live allocations.
+static std::atomic<long> g_fail_countdown{[] {
+    const char* v = getenv("DCO_FAIL_ALLOC");
+    return v ? atol(v) : 0L;
+}()};
+static std::atomic<long> g_live_allocs{0};
+
+bool alloc_fault_injected() {
+    long v = g_fail_countdown.load(std::memory_order_relaxed);
+    while (v > 0)
+        if (g_fail_countdown.compare_exchange_weak(v, v - 1)) return v == 1;
+    return false;
+}
+
+void alloc_count(int delta) { g_live_allocs.fetch_add(delta); }
+
+extern "C" void dco_debug_fail_alloc(int k) { g_fail_countdown.store(k > 0 ? k : 0); }
+
+extern "C" long dco_debug_live_allocations(void) { return g_live_allocs.load(); }
 
 void dco_set_error(const char* fmt, ...) {
     va_list ap;
@@ -135,8 +157,7 @@ static void free_handle_memory(dco_stereo* h) {
                     h->soft.arms,    h->soft.arms_r,  h->soft.n1,      h->soft.n2,
                     h->soft.tab,     h->soft.vol[0],  h->soft.vol[1],  h->soft.vol[2],
                     h->soft.partAC,  h->soft.partT};
-    for (void* p : ptrs)
-        if (p) (void)hipFree(p);
+    for (void* p : ptrs) dev_free(p);
 }
 
 // Aggregation records with a zero apron and a zero extra row (zeroed once:
@@ -486,6 +507,27 @@ extern "C" dco_status dco_vote_refine(dco_stereo* h, const uint8_t* armsL, const
     return DCO_OK;
 }
 
+extern "C" dco_status dco_stereo_agg_slices(dco_stereo* h, int view, int d0, int n, float* out) {
+    DCO_TRY(need(h, "handle"));
+    DCO_TRY(need(out, "out"));
+    if (view != 0 && view != 1) {
+        dco_set_error("view must be 0 (left) or 1 (right), got %d", view);
+        return DCO_ERR_ARG;
+    }
+    if (d0 < 0 || n < 1 || d0 > h->D - n) {
+        dco_set_error("slices %d .. %d outside 0 .. %d", d0, d0 + n - 1, h->D - 1);
+        return DCO_ERR_ARG;
+    }
+    if (!h->scratch_ready) {
+        dco_set_error("handle has no scratch");
+        return DCO_ERR_STATE;
+    }
+    const size_t P = (size_t)h->W * h->H;
+    DCO_HIP_CHECK(hipMemcpyAsync(out, h->s.agg[view] + (size_t)d0 * P, (size_t)n * P * sizeof(float),
+                                 hipMemcpyDeviceToDevice, h->stream));
+    return DCO_OK;
+}
+
 extern "C" dco_status dco_stereo_last_disparities(dco_stereo* h, int16_t* dL, int16_t* dR) {
     DCO_TRY(need(h, "handle"));
     const size_t bytes = (size_t)h->W * h->H * sizeof(int16_t);
@@ -501,8 +543,7 @@ extern "C" dco_status dco_stereo_last_disparities(dco_stereo* h, int16_t* dL, in
 static void free_soft(SoftScratch& f) {
     void* ptrs[] = {f.pix[0], f.pix[1], f.arms,   f.arms_r, f.n1,     f.n2,
                     f.tab,    f.vol[0], f.vol[1], f.vol[2], f.partAC, f.partT};
-    for (void* p : ptrs)
-        if (p) (void)hipFree(p);
+    for (void* p : ptrs) dev_free(p);
     f = SoftScratch{};
 }
 

@@ -75,7 +75,9 @@ dco_status alloc_pair(dco_batch* b, BatchPair& pr, int W, int H, int D) {
     return DCO_OK;
 }
 
-// Stage-ordered work list; within stage 2 the longest items come first.
+// Stage-ordered work list.  Stage 2 keeps pair, view, strip, band,
+// disparity order (no sort by length: neighbouring items share inputs) and
+// is cut into kXcds contiguous parts of about equal cost.
 std::vector<BatchItem> make_items(std::vector<BatchPair>& pairs, int* xsplit) {
     std::vector<BatchItem> st[kBatchStages];
     for (int i = 0; i < (int)pairs.size(); ++i) {
@@ -179,7 +181,7 @@ dco_status upload(dco_batch* b) {
     std::vector<BatchItem> items = make_items(b->pairs, b->xsplit);
     DCO_TRY(check_items(items, b->pairs, b->first));
     if (b->d_items) {
-        (void)hipFree(b->d_items);
+        dev_free(b->d_items);
         b->allocs.erase(std::find(b->allocs.begin(), b->allocs.end(), (void*)b->d_items));
         b->d_items = nullptr;
     }
@@ -220,8 +222,9 @@ void release(dco_batch* b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->io_copied) (void)hipEventDestroy(b->io_copied);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-    if (b->h_io) (void)hipHostFree(b->h_io);
-    for (void* p : b->allocs) (void)hipFree(p);
+    pinned_free(b->h_io);
+    b->h_io = nullptr;
+    for (void* p : b->allocs) dev_free(p);
     b->allocs.clear();
 }
 
@@ -462,10 +465,7 @@ extern "C" dco_status dco_batch_create(dco_batch** out, int n, const int* W, con
         b->pairs[i].dchunk = std::min(tiles[i].dchunk, D[i]);
     }
     if ((s = upload(b)) != DCO_OK) return fail(s);
-    if (hipHostMalloc((void**)&b->h_io, sizeof(BatchIO) * n, hipHostMallocDefault) != hipSuccess) {
-        dco_set_error("hipHostMalloc of the pointer table failed");
-        return fail(DCO_ERR_OOM);
-    }
+    if ((s = pinned_alloc((void**)&b->h_io, sizeof(BatchIO) * n)) != DCO_OK) return fail(s);
     std::memset(b->h_io, 0, sizeof(BatchIO) * n);
     hipError_t e = hipEventCreateWithFlags(&b->io_copied, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);

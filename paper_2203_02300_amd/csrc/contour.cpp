@@ -31,9 +31,8 @@ static void free_contour(dco_contour* h) {
     ContourBufs& b = h->b;
     void* ptrs[] = {b.fused, b.box_max, b.g2_max, b.g, b.G2, b.state[0], b.state[1], b.changed,
                     h->Mn};
-    for (void* q : ptrs)
-        if (q) (void)hipFree(q);
-    if (h->changed_host) (void)hipHostFree(h->changed_host);
+    for (void* q : ptrs) dev_free(q);
+    pinned_free(h->changed_host);
 }
 
 extern "C" void dco_contour_destroy(dco_contour* h) {
@@ -93,12 +92,8 @@ extern "C" dco_status dco_contour_create(dco_contour** out, int W, int H,
     if ((st = dev_alloc(&b.state[0], P)) != DCO_OK) return fail(st);
     if ((st = dev_alloc(&b.state[1], P)) != DCO_OK) return fail(st);
     if ((st = dev_alloc(&b.changed, kHystGroup)) != DCO_OK) return fail(st);
-    if (hipHostMalloc((void**)&h->changed_host, kHystGroup * sizeof(int), hipHostMallocDefault) !=
-        hipSuccess) {
-        (void)hipGetLastError();
-        dco_set_error("pinned allocation failed");
-        return fail(DCO_ERR_OOM);
-    }
+    if ((st = pinned_alloc((void**)&h->changed_host, kHystGroup * sizeof(int))) != DCO_OK)
+        return fail(st);
     *out = h;
     return DCO_OK;
 }

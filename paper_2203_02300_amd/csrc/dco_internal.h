@@ -97,14 +97,22 @@ void dco_set_error(const char* fmt, ...);
         if (_s != DCO_OK) return _s; \
     } while (0)
 
-// hipMalloc of n elements with the library's error reporting (DCO_FAIL_ALLOC
-// in the environment makes it fail, to exercise the error paths).
+// Allocation-failure injection and accounting (testing hooks of the ABI):
+// dco_debug_fail_alloc(k), or DCO_FAIL_ALLOC=k in the environment when the
+// library loads, makes the k-th device or pinned allocation from then on
+// fail as if memory were exhausted; every allocation and free made through
+// the helpers below is counted, so a test can check that an error path
+// frees exactly what it allocated.
+bool alloc_fault_injected();
+void alloc_count(int delta);
+
+// hipMalloc of n elements with the library's error reporting.
 template <class T>
 inline dco_status dev_alloc(T** p, size_t n) {
     *p = nullptr;
     if (n == 0) return DCO_OK;
-    if (getenv("DCO_FAIL_ALLOC")) {
-        dco_set_error("allocation of %zu bytes refused (DCO_FAIL_ALLOC)", n * sizeof(T));
+    if (alloc_fault_injected()) {
+        dco_set_error("allocation of %zu bytes refused (injected failure)", n * sizeof(T));
         return DCO_ERR_OOM;
     }
     hipError_t e = hipMalloc((void**)p, n * sizeof(T));
@@ -114,7 +122,34 @@ inline dco_status dev_alloc(T** p, size_t n) {
         dco_set_error("hipMalloc(%zu) failed: %s", n * sizeof(T), hipGetErrorString(e));
         return e == hipErrorOutOfMemory ? DCO_ERR_OOM : DCO_ERR_HIP;
     }
+    alloc_count(1);
     return DCO_OK;
+}
+
+// hipFree of a dev_alloc pointer (nullptr is ignored).
+inline void dev_free(void* p) {
+    if (!p) return;
+    (void)hipFree(p);
+    alloc_count(-1);
+}
+
+// Pinned host memory of `bytes` bytes, counted like device memory.
+inline dco_status pinned_alloc(void** p, size_t bytes) {
+    *p = nullptr;
+    if (alloc_fault_injected() || hipHostMalloc(p, bytes, hipHostMallocDefault) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        dco_set_error("pinned allocation of %zu bytes failed", bytes);
+        return DCO_ERR_OOM;
+    }
+    alloc_count(1);
+    return DCO_OK;
+}
+
+inline void pinned_free(void* p) {
+    if (!p) return;
+    (void)hipHostFree(p);
+    alloc_count(-1);
 }
 
 // ---- host helpers shared by api.cpp and batch.cpp ----

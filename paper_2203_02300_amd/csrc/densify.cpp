@@ -35,10 +35,9 @@ static void free_densify(dco_densify* h) {
     DensifyBufs& b = h->b;
     void* ptrs[] = {b.cr, b.cd, b.diag, b.invdiag, b.x,  b.r,     b.q,  b.p[0],
                     b.p[1], b.rz[0], b.rz[1], b.rr[0], b.rr[1], b.pq, b.bb, b.flags};
-    for (void* q : ptrs)
-        if (q) (void)hipFree(q);
+    for (void* q : ptrs) dev_free(q);
     if (h->exec) (void)hipGraphExecDestroy(h->exec);
-    if (h->flags_host) (void)hipHostFree(h->flags_host);
+    pinned_free(h->flags_host);
 }
 
 extern "C" void dco_densify_destroy(dco_densify* h) {
@@ -100,12 +99,7 @@ extern "C" dco_status dco_densify_create(dco_densify** out, int W, int H,
     for (double** v : parts)
         if ((st = dev_alloc(v, nb)) != DCO_OK) return fail(st);
     if ((st = dev_alloc(&b.flags, 2)) != DCO_OK) return fail(st);
-    if (hipHostMalloc((void**)&h->flags_host, 2 * sizeof(int), hipHostMallocDefault) !=
-        hipSuccess) {
-        (void)hipGetLastError();
-        dco_set_error("pinned allocation failed");
-        return fail(DCO_ERR_OOM);
-    }
+    if ((st = pinned_alloc((void**)&h->flags_host, 2 * sizeof(int))) != DCO_OK) return fail(st);
     // one launch = iters_per_launch iterations (two kernels each), captured
     // once on a private stream of default priority; no memset nodes
     hipStream_t cap;

@@ -3,7 +3,8 @@
 //
 // The host builds a work list ordered by stage (0 census + arms of a 64 x 64
 // block, 1 region counts and records of a 64 x 64 block, 2 cost +
-// aggregation of d-chunk x column strip x row band, longest first, 3 WTA of
+// aggregation of d-chunk x column strip x row band, in pair, view, strip,
+// band, disparity order and cut into one contiguous part per XCD, 3 WTA of
 // a pixel block, 4 LR check of a row block) over every pair of the batch.
 // The kernel of stage s runs a grid sized to the GPU's resident capacity; its
 // workgroup w takes the stage's items w, w + G, w + 2G, ...  The kernel

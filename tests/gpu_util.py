@@ -65,3 +65,46 @@ def crop_windows(W, H, D, n, seed, interior=(96, 32)):
         cy0, cy1 = max(0, y0 - my), min(H, y0 + ih + my)
         out.append(((cx0, cx1, cy0, cy1), (x0, x0 + iw, y0, y0 + ih)))
     return out
+
+
+# Rows of context a band of the oracle needs so that its own rows equal the
+# whole-frame result: 2 L1 for the two vertical aggregation stages plus L1
+# for the vertical arms of the pixels in those ranges; every Eq. 4 vote pass
+# reads the pass before it over a further L1 rows.
+BAND_HALO = 51
+
+
+def oracle_banded(L, R, D, nbands=None, threads=None, **kw):
+    """The whole-frame oracle match computed in row bands on host threads
+    (the oracle's C calls release the GIL): (disp, valid, dL, dR)."""
+    import concurrent.futures as cf
+    import os
+    H, W = L.shape[:2]
+    threads = threads or max(1, min(16, len(os.sched_getaffinity(0))))
+    nbands = nbands or threads
+    halo = BAND_HALO + 17 * kw.get("vote_iters", 0)
+    edges = np.linspace(0, H, nbands + 1).round().astype(int)
+    disp = np.empty((H, W), np.float32)
+    valid = np.empty((H, W), np.uint8)
+    dL = np.empty((H, W), np.int16)
+    dR = np.empty((H, W), np.int16)
+
+    def run(i):
+        y0, y1 = int(edges[i]), int(edges[i + 1])
+        a, b = max(0, y0 - halo), min(H, y1 + halo)
+        d, v, l, r = oracle.match(L[a:b], R[a:b], D, **kw)
+        disp[y0:y1], valid[y0:y1] = d[y0 - a:y1 - a], v[y0 - a:y1 - a]
+        dL[y0:y1], dR[y0:y1] = l[y0 - a:y1 - a], r[y0 - a:y1 - a]
+
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(run, range(nbands)))
+    return disp, valid, dL, dR
+
+
+def thread_map(fn, items, threads=None):
+    """fn over items on host threads (for oracle calls, which release the GIL)."""
+    import concurrent.futures as cf
+    import os
+    threads = threads or max(1, min(16, len(os.sched_getaffinity(0))))
+    with cf.ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(fn, items))

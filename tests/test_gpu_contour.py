@@ -105,3 +105,67 @@ def test_hysteresis_over_several_launch_groups(torch_mod):
     past[..., 0] = np.arange(W // 2, dtype=np.float32)[None, :] * 0.1
     B, n = _check(rgb, past, past, Thigh=0.95, Tlow=0.2)
     assert n > 8 and (B[47] | B[48]).sum() > 0.9 * W
+    # the ridge zig-zags across the boundary of two tile rows, which costs a
+    # launch per crossing: the count equals the host model's
+    Mn = oracle.flow_fuse(past, past, R=2)
+    grey = oracle.grey(rgb)
+    strong, _ = oracle.contour(grey, Mn, Thigh=0.95, Tlow=0.95)
+    cand, _ = oracle.contour(grey, Mn, Thigh=0.2, Tlow=0.2)
+    assert n == _launch_model(cand.astype(np.uint8) + strong.astype(np.uint8))
+
+
+def _launch_model(state, tw=64, th=16):
+    """Launch count of the tiled hysteresis: each launch grows strong pixels
+    into 8-connected weak ones inside every 64 x 16 tile until the tile is
+    stable, reading the tile's one-pixel halo from the launch's input; the
+    launches stop after the first one that changes nothing (counted)."""
+    H, W = state.shape
+    s = state.copy()
+    n = 0
+    while True:
+        n += 1
+        pad = np.pad(s, 1)
+        new = s.copy()
+        for y0 in range(0, H, th):
+            for x0 in range(0, W, tw):
+                T = pad[y0:y0 + th + 2, x0:x0 + tw + 2].copy()
+                h, w = T.shape[0] - 2, T.shape[1] - 2
+                while True:
+                    strong = T == 2
+                    near = np.zeros_like(strong)
+                    for dy in (-1, 0, 1):
+                        for dx in (-1, 0, 1):
+                            near[1:-1, 1:-1] |= strong[1 + dy:1 + dy + h, 1 + dx:1 + dx + w]
+                    grow = (T[1:-1, 1:-1] == 1) & near[1:-1, 1:-1]
+                    if not grow.any():
+                        break
+                    T[1:-1, 1:-1][grow] = 2
+                new[y0:y0 + h, x0:x0 + w] = T[1:-1, 1:-1]
+        if np.array_equal(new, s):
+            return n
+        s = new
+
+
+@pytest.mark.parametrize("tiles", [5, 6, 7, 8])
+def test_hysteresis_stop_position_in_a_later_group(torch_mod, tiles):
+    """Weak chains across 5 .. 8 tiles of 64 columns, seeded strong only in
+    the last tile: the launch count n (groups of four launches, the first
+    unchanged launch of a group ends it) takes all four values of n mod 4
+    above one group, and each n equals the count of a host model of the
+    tiled growth; B is bit-exact against the oracle (in _check)."""
+    H, W = 96, 64 * tiles
+    Y = np.full((H, W), 50, np.uint8)
+    Y[41:] = 50 + 20 + np.arange(W) // 12      # ridge on rows 40 / 41: one tile row
+    rgb = np.repeat(Y[:, :, None], 3, axis=2)
+    past = np.zeros((H // 2, W // 2, 2), np.float32)
+    past[..., 0] = np.arange(W // 2, dtype=np.float32)[None, :] * 0.1
+    print(f"hysteresis chain across {tiles} tiles", flush=True)
+    B, n = _check(rgb, past, past, Thigh=0.95, Tlow=0.2)
+    Mn = oracle.flow_fuse(past, past, R=2)
+    grey = oracle.grey(rgb)
+    strong, _ = oracle.contour(grey, Mn, Thigh=0.95, Tlow=0.95)
+    cand, _ = oracle.contour(grey, Mn, Thigh=0.2, Tlow=0.2)
+    assert strong[:, : W - 64].sum() == 0 and strong.any()   # seeds in the last tile only
+    want = _launch_model(cand.astype(np.uint8) + strong.astype(np.uint8))
+    assert n == want == tiles + 1, (n, want)   # 6, 7, 8, 9: every n mod 4
+    assert (B[40] | B[41]).sum() > 0.9 * W

@@ -187,3 +187,53 @@ def test_soft_widest_and_smallest_frames(torch_mod, W, H, D, B):
     scale = np.abs(g_ref).max()
     assert scale > 0
     assert np.all(np.abs(g_gpu - g_ref) <= 1e-3 * scale), (g_gpu, g_ref)
+
+
+def test_soft_every_pair_of_the_benchmark_batch(torch_mod):
+    """All 8 pairs of 640x480, D = 64 (the benchmarked differentiable
+    workload): dhat of every pair against the FP64 oracle, and the batch
+    gradient per component against the oracle's within 1e-4 of that
+    component's magnitude sum M_k (oracle.soft_grad_mag: the same chain with
+    every term replaced by its absolute value, so M_k bounds the sum of the
+    absolute contributions).  A float32 evaluation keeps each of those terms
+    to a few float32 roundings (~1e-6 relative: A2 from FP64 prefix sums,
+    float softmax, FP64 adjoints), so its error is a small multiple of
+    1e-6 M_k; cancellation between contributions (the lambda_census
+    component is ~1 % of its M_k) cannot inflate it."""
+    torch = torch_mod
+    from paper_2203_02300_amd import StereoMatcher
+    from paper_2203_02300_amd.soft import soft_backward, soft_forward
+    from gpu_util import thread_map
+    ps = synth.config_c5()
+    W, H, D = 640, 480, 64
+    print("soft, 8 pairs of 640x480 D=64: GPU forward and backward", flush=True)
+    theta = torch.tensor([10.0, 30.0, 1.0], dtype=torch.float32, device="cuda")
+    with StereoMatcher(W, H, D) as m:
+        L = dev(np.stack([p["left"] for p in ps]))
+        R = dev(np.stack([p["right"] for p in ps]))
+        dhat, lse = soft_forward(m, L, R, theta)
+        gt = np.stack([p["disp"] for p in ps])
+        occ = np.stack([p["occluded"] for p in ps])
+        dh_gpu = host(dhat)
+        gd = l1_seed(dh_gpu, gt, occ).astype(np.float32)
+        g_gpu = host(soft_backward(m, L, R, theta, dhat, lse, dev(gd))).astype(np.float64)
+
+    def ref(b):
+        Lb, Rb, cL, cR, aL = oracle_inputs(ps[b])
+        kw = dict(lam_ad=10.0, lam_c=30.0, T=1.0)
+        dh = oracle.soft_forward(Lb, Rb, cL, cR, aL, D, **kw)
+        g = oracle.soft_grad(Lb, Rb, cL, cR, aL, D, gd[b].astype(np.float64), **kw)
+        M = oracle.soft_grad_mag(Lb, Rb, cL, cR, aL, D, gd[b].astype(np.float64), **kw)
+        return dh, g, M
+
+    print("soft, 8 pairs: FP64 oracle on host threads", flush=True)
+    refs = thread_map(ref, range(len(ps)))
+    for b, (dh, _, _) in enumerate(refs):
+        err = np.abs(dh_gpu[b] - dh).max()
+        print(f"pair {b}: max |dhat - oracle| = {err:.3g} px", flush=True)
+        assert err < 1e-3, b
+    g_ref = sum(r[1] for r in refs)
+    M = sum(r[2] for r in refs)
+    ratio = np.abs(g_gpu - g_ref) / M
+    print(f"grad gpu {g_gpu}, oracle {g_ref}, M {M}, |diff| / M {ratio}", flush=True)
+    assert np.all(M > 0) and np.all(ratio <= 1e-4), (g_gpu, g_ref, M)

@@ -160,3 +160,22 @@ def test_committed_counter_summaries_match_the_kernel_sources():
     assert bench.measured_traffic() is not None
     busy = bench.measured_busy()
     assert busy is not None and 0.0 < busy["valu"] <= 1.0 and 0.0 < busy["td"] <= 1.0
+
+
+def test_banded_oracle_of_the_gpu_tests_equals_the_whole_frame():
+    """tests/gpu_util.oracle_banded (the reference of the whole-frame GPU
+    parity tests) equals the whole-frame oracle bit for bit, with and without
+    two Eq. 4 vote passes (whose halo grows by L1 rows per pass)."""
+    import oracle
+    from gpu_util import oracle_banded
+    from paper_2203_02300_amd import synth
+    p = synth.make_slanted_pair(150, 300, 20, 9, n_planes=4, dmin=2.0, dmax=18.0,
+                                noise_sigma=2.0, occl_strip_frac=0.03)
+    L, R = p["left"], p["right"]
+    for kw in ({}, {"vote_iters": 2}):
+        want = oracle.match(L, R, 20, **kw)
+        got = oracle_banded(L, R, 20, nbands=5, threads=5, **kw)
+        assert np.array_equal(got[1], want[1])
+        assert np.array_equal(got[0].view(np.uint32), want[0].astype(np.float32).view(np.uint32))
+        if not kw:
+            assert np.array_equal(got[2], want[2]) and np.array_equal(got[3], want[3])
