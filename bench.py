@@ -286,7 +286,7 @@ def main():
                peak_GBs=HBM_PEAK_GBS)
     roofline = dict(bound="alu", achieved=round(achieved, 2), peak=round(VALU_PEAK_TOPS, 2),
                     unit="TOP/s", frac=round(achieved / VALU_PEAK_TOPS, 4), traffic=measured_traffic(),
-                    kernel="k_agg_pair<2>", kernel_ms=round(agg_ms, 4),
+                    kernel="k_agg_pair_ws", kernel_ms=round(agg_ms, 4),
                     ops_per_pd=ops_per_unit, units_per_launch=2 * V,
                     units_busy=measured_busy(), hbm_step=hbm)
 

@@ -421,7 +421,7 @@ extern "C" dco_status dco_stereo_match(dco_stereo* h, const uint8_t* rgbL, const
     DCO_TRY(prof_mark(h));
     DCO_HIP_CHECK(launch_front2(img[0], img[1], h->W, h->H, p.census_w, p.census_h, p.arm_L1,
                                 p.arm_tau1, p.agg_iters, s.arms[0], s.arms[1], s.pix[0], s.pix[1],
-                                s.rec[0], s.rec[1], h->stream));
+                                s.rec[0], s.rec[1], pair_rec_geom(p.agg_iters), h->stream));
     DCO_TRY(prof_mark(h));
     DCO_TRY(prof_mark(h));
     DCO_HIP_CHECK(launch_cost_aggregate2(s.pix[0], s.pix[1], s.rec[0], s.rec[1], h->W, h->H, h->D,

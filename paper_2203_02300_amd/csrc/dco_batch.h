@@ -16,7 +16,7 @@ struct BatchPair {
     int dchunk;   // disparities per aggregation item (tuned)
     int nitems[kBatchStages];
     uint32_t* arms[2];
-    uint4* pix[2];   // packed pixels: census, RGB | 8 L_min << 24
+    uint4* pix[2];   // packed pixels: census lo, census hi, RGB, 8 L_min
     AggRecords rec[2];
     float* agg[2];
     int16_t* dint[2];

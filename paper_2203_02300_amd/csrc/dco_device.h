@@ -154,11 +154,10 @@ __device__ inline void census_tile(const uint8_t* __restrict__ rgb, int W, int H
         if (rgb_packed) rgb_packed[(size_t)y * W + x] = cp;
         // everything the fused raw cost needs of one pixel in one 16-byte
         // load: census code, packed RGB, and 8 L_min (the byte offset of the
-        // pixel's (alpha, beta) pair) in the top byte
+        // pixel's (alpha, beta) pair)
         if (pix)
-            pix[(size_t)y * W + x] =
-                make_uint4((uint32_t)code, (uint32_t)(code >> 32),
-                           cp | (uint32_t)(8 * min(min(al, ar), min(au, ad))) << 24, 0u);
+            pix[(size_t)y * W + x] = make_uint4((uint32_t)code, (uint32_t)(code >> 32), cp,
+                                                (uint32_t)(8 * min(min(al, ar), min(au, ad))));
     }
 }
 
@@ -188,25 +187,34 @@ constexpr uint32_t kOOB = 0x7fffffffu;                // buffer offset that read
 static_assert(kRing2 * kSlotBytes < 65536, "ring offsets are stored in 16 bits");
 static_assert(kStripThreads == 256 && kAggK == 4, "one row per wavefront per chunk");
 
-__device__ inline uint32_t ring_slot_bytes(int row, int ring) {
+__device__ inline uint32_t ring_slot(int row, int ring) {
     int s = row % ring;
     if (s < 0) s += ring;
-    return (uint32_t)s * kSlotBytes;
+    return (uint32_t)s;
 }
+__device__ inline uint32_t ring_slot_bytes(int row, int ring) {
+    return ring_slot(row, ring) * kSlotBytes;
+}
+
+// Records for the single-slice kernels (k_agg_stream, k_agg_pair<1>, the
+// batched path).
+constexpr RecGeom kRecPlain{kRing1, kRing2, kSlotBytes, kSlotBytes, 4};
 
 // Records of pixel (x, y) with arms word a and region counts n1, n2 (layout:
 // AggRecords).  The b row of the pixel's own row gets its horizontal arms
 // (low half of word 2); the b row kLMax rows below gets its stage-1 data.
+// ring1 and ring2 are the row counts of the two rings of the kernel that
+// reads the records.
 __device__ inline void write_records(const AggRecords& rec, int x, int y, int iters, uint32_t a,
-                                     uint32_t n1, uint32_t n2) {
+                                     uint32_t n1, uint32_t n2, const RecGeom& g) {
     const uint32_t l = a & 0xff, r = (a >> 8) & 0xff, u = (a >> 16) & 0xff, dn = a >> 24;
-    const uint32_t lr = 4 * (r + 1) | (4 * l) << 8;
+    const uint32_t lr = g.hw * (r + 1) | (g.hw * l) << 8;
     const uint32_t hi = (uint32_t)y + dn, lo = (uint32_t)y - u - 1;
     const size_t col = (size_t)x + rec.apron;
     uint32_t* bo = rec.b + 4 * ((size_t)y * rec.Wp + col);
     reinterpret_cast<uint16_t*>(bo + 2)[0] = (uint16_t)lr;
     uint32_t* bv = rec.b + 4 * ((size_t)(y + kLMax) * rec.Wp + col);
-    bv[1] = ring_slot_bytes((int)hi, kRing1) | ring_slot_bytes((int)lo, kRing1) << 16;
+    bv[1] = ring_slot((int)hi, g.ring1) * g.step1 | ring_slot((int)lo, g.ring1) * g.step1 << 16;
     if (iters == 2) {
         const uint32_t lg = n1 <= 1 ? 0u : 32u - (uint32_t)__clz((int)(n1 - 1));
         const uint32_t sh = 31u + lg;
@@ -214,9 +222,10 @@ __device__ inline void write_records(const AggRecords& rec, int x, int y, int it
         bv[0] = (uint32_t)((num + n1 - 1) / n1);
         reinterpret_cast<uint16_t*>(bv + 2)[1] = (uint16_t)((n1 >> 1) | sh << 10);
         uint32_t* c = rec.c + 4 * ((size_t)y * rec.Wp + col);
-        c[0] = ring_slot_bytes((int)hi, kRing2) | ring_slot_bytes((int)lo, kRing2) << 16;
+        c[0] = ring_slot((int)hi, g.ring2) * g.step2 | ring_slot((int)lo, g.ring2) * g.step2 << 16;
         c[1] = __float_as_uint((1.0f / (float)n2) * 0x1p-20f);
         c[2] = lr | n2 << 16;
+        c[3] = __float_as_uint((float)n2 * 0x1p20f);
     } else {
         bv[0] = __float_as_uint((1.0f / (float)n1) * 0x1p-20f);
         reinterpret_cast<uint16_t*>(bv + 2)[1] = (uint16_t)n1;
@@ -238,7 +247,8 @@ struct GeomLds {
 };
 
 __device__ inline void geometry_tile(const uint32_t* __restrict__ arms, int W, int H, int iters,
-                                     const AggRecords& rec, int x0, int y0, GeomLds& S) {
+                                     const AggRecords& rec, int x0, int y0, GeomLds& S,
+                                     const RecGeom& g = kRecPlain) {
     const int t = threadIdx.x;
     {   // stage the arms: every load issued before any is used (clamped addresses)
         constexpr int kN = (kGeoRW * kGeoRH + 255) / 256;
@@ -298,7 +308,7 @@ __device__ inline void geometry_tile(const uint32_t* __restrict__ arms, int W, i
         const uint32_t a = (uint32_t)l | (uint32_t)r << 8 | (uint32_t)u << 16 | (uint32_t)dn << 24;
         const uint32_t n1 = S.cp[ty + kLMax + dn + 1][tx] - S.cp[ty + kLMax - u][tx];
         const uint32_t n2 = S.rp[ty][tx + kLMax + r + 1] - S.rp[ty][tx + kLMax - l];
-        write_records(rec, x, y, iters, a, n1, n2);
+        write_records(rec, x, y, iters, a, n1, n2, g);
     }
 }
 
@@ -427,7 +437,7 @@ __device__ inline float div_q20(uint32_t s, float n_scaled, float rcp_scaled) {
 struct AggArgs {
     const float* cost;         // staged: D x H x W raw costs
     const uint4* pixL;         // fused: packed pixels of both views (H x W):
-    const uint4* pixR;         //   census lo, census hi, RGB | 8 L_min << 24, 0
+    const uint4* pixR;         //   census lo, census hi, RGB, 8 L_min
     const float* tabA;         // fused: Eq. 1 tables
     const float* tabC;
     const float* alpha;
@@ -466,6 +476,8 @@ struct AggLane {
 
 struct AggRes {
     rsrc_t rB, rC, rq, rIr, rIp, rOut;
+    uint32_t slice_bytes;  // two-slice kernel: distance between its output slices
+    int nout;              // two-slice kernel: slices that exist (the others are not stored)
 };
 
 template <int ITERS, bool kFused>
@@ -517,14 +529,12 @@ __device__ inline void process_chunk(const AggArgs& A, int yc, int y0, int y1, c
 #pragma unroll
             for (int j = 0; j < kSeg; ++j) {
                 if (kFused) {
-                    // the top bytes hold L_min: shifted out of the SAD
-                    const uint32_t s =
-                        __builtin_amdgcn_sad_u8(in.ref[j].z << 8, in.par[j].z << 8, 0u);
+                    const uint32_t s = __builtin_amdgcn_sad_u8(in.ref[j].z, in.par[j].z, 0u);
                     const uint64_t x = ((uint64_t)in.ref[j].y << 32 | in.ref[j].x) ^
                                        ((uint64_t)in.par[j].y << 32 | in.par[j].x);
                     const uint32_t h = (uint32_t)__popcll(x);
                     const float2 ab = *reinterpret_cast<const float2*>(
-                        reinterpret_cast<const char*>(S.ab) + (in.ref[j].z >> 24));
+                        reinterpret_cast<const char*>(S.ab) + in.ref[j].w);
                     const float qa = __builtin_rintf(ab.x * S.tabA[s]);
                     const float qc = __builtin_rintf(ab.y * S.tabC[h]);
                     uint32_t q = (uint32_t)(qa + qc);
@@ -698,6 +708,386 @@ __device__ inline void agg_stream(const AggArgs& A, int d, int strip, int y0, in
         load_chunk<ITERS, kFused>(A, yc + 2 * kAggK, ln, R, ca);
         process_chunk<ITERS, kFused>(A, yc + kAggK, y0, y1, ln, R, cb, cp1, cp2, s1off, s2off,
                                      S);
+    }
+}
+
+// ===========================================================================
+// Two-slice streaming aggregation with specialised wavefronts (one-call path)
+// ===========================================================================
+//
+// One workgroup of 512 threads streams two adjacent disparity slices of one
+// column strip down the rows, in chunks of kAggK rows as above, with each
+// step done by a fixed set of wavefronts and the steps of three consecutive
+// chunks in flight:
+//   row wavefronts 0-3, phase p: step 3 of chunk p - 2 (its output row,
+//       both slices) and step 1 of chunk p (its row, both slices);
+//   column wavefronts 4-7 (thread 256 + t owns column t), phase p: step 2 of
+//       chunk p - 1 (both slices).
+// One barrier ends a phase.  Each step's reference pixels and records are
+// loaded once for both slices, and every LDS word holds the two slices'
+// values of one column (one 64-bit access serves both).
+//  * Prefix rows are double-buffered by chunk parity: step 1 of chunk p
+//    writes buffer p & 1 while step 2 of chunk p - 1 reads the other one.
+//    Step 3 uses its own wavefront's row of buffer p & 1 as scratch before
+//    step 1 of the same wavefront overwrites it.
+//  * Ring 1 is private to the column thread, which pushes a row and reads
+//    that row's range before the next push, so 2 kLMax + 2 rows suffice.
+//  * Ring 2 is pushed by step 2 of chunk p - 1 while step 3 of chunk p - 2
+//    reads it: it keeps 2 kLMax + 2 + 2 kAggK rows so that no push of the
+//    phase lands on a row still being read.
+constexpr int kWsThreads = 2 * kStripThreads;
+constexpr int kWsSlices = 2;
+static_assert(kWsSlices == 2 && kSeg == 4, "the step-1 register pin lists 2 x 4 values");
+constexpr int kWsRing1 = 2 * kLMax + 2;
+constexpr int kWsRing2 = 2 * kLMax + 2 + 2 * kAggK;
+constexpr uint32_t kWsSlotBytes = kRingStride * 8;  // one ring row of both slices
+// Prefix rows hold P(c) at index c + kWsP0 and P(-1) = 0 at kWsP0 - 1, so
+// that lane l's four columns 4 l .. 4 l + 3 form two aligned 16-byte words.
+constexpr int kWsP0 = 4;
+constexpr int kWsPStride = 260;  // P(-1) .. P(255)
+static_assert(kWsPStride % 2 == 0 && kWsP0 + 256 <= kWsPStride, "prefix row layout");
+// Records for this kernel: ring 1 offsets in bytes, ring 2 offsets in 8-byte
+// words (its byte offsets would not fit 16 bits), arm offsets in 8-byte words.
+constexpr RecGeom kRecWs{kWsRing1, kWsRing2, kWsSlotBytes, kRingStride, 8};
+static_assert((kWsRing1 - 1) * kWsSlotBytes < 65536 && (kWsRing2 - 1) * kRingStride < 65536,
+              "ring offsets are stored in 16 bits");
+
+struct AggLdsWs {
+    float tabA[768];
+    float tabC[68];
+    float2 ab[kLMax + 1];
+    uint32_t guard[32];
+    alignas(16) uint2 prow[2][kAggK][kWsPStride];  // [buffer][row][index]: both slices
+    uint2 ring1[kWsRing1 * kRingStride];            // [slot][column]: both slices
+    uint2 ring2[kWsRing2 * kRingStride];
+};
+static_assert(sizeof(AggLdsWs) <= 160 * 1024, "one workgroup per CU");
+
+__device__ inline uint2 lds_ld2(const uint2* base, uint32_t byte_off) {
+    return *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+__device__ inline void lds_st2(uint2* base, uint32_t byte_off, uint2 v) {
+    *reinterpret_cast<uint2*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
+// Loads of a row wavefront for one phase: the pixels of step 1's row and the
+// c records of step 3's output row.
+struct WsRowIn {
+    uint4 ref[kSeg];
+    uint4 par[kWsSlices][kSeg];
+    uint4 c3[kSeg];
+};
+
+// Loads of a column thread for one phase: the b records of step 2's rows.
+struct WsColIn {
+    uint4 b2[kAggK];
+};
+
+struct WsRowLane {
+    uint32_t img[kSeg], par[kWsSlices][kSeg], inval[kSeg], cbs[kSeg], vout[kSeg], recw;
+    bool pok[kWsSlices][kSeg];
+};
+
+// Row wavefront: loads for phase p (step 1 of chunk p, step 3 of chunk p - 2).
+__device__ inline void ws_row_load(const AggArgs& A, int ys, int p, int w, const WsRowLane& ln,
+                                   const AggRes& R, WsRowIn& in) {
+    const uint32_t W = (uint32_t)A.W, Wp = (uint32_t)A.rec.Wp;
+    const uint32_t yq = (uint32_t)min(ys + kAggK * p + w, A.H - 1);
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j) {
+        in.ref[j] = ld128(R.rIr, ln.img[j], yq * W * 16);
+#pragma unroll
+        for (int s = 0; s < kWsSlices; ++s) in.par[s][j] = ld128(R.rIp, ln.par[s][j], yq * W * 16);
+    }
+    const int y2 = ys + kAggK * (p - 2) + w - 2 * kLMax - 1;
+    const uint32_t rc = (uint32_t)(y2 >= 0 && y2 < A.H ? y2 : A.H);
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j) in.c3[j] = ld128(R.rC, ln.recw * 4 + 1024 * j, rc * Wp * 16);
+}
+
+// Column thread: loads for step 2 of chunk q (b rows ys + kAggK q + k).
+__device__ inline void ws_col_load(const AggArgs& A, int ys, int q, uint32_t reco,
+                                   const AggRes& R, WsColIn& in) {
+    const uint32_t Wp = (uint32_t)A.rec.Wp;
+#pragma unroll
+    for (int k = 0; k < kAggK; ++k) {
+        const uint32_t rb = (uint32_t)min(ys + kAggK * q + k, A.H + kLMax);
+        in.b2[k] = ld128(R.rB, reco * 4, rb * Wp * 16);
+    }
+}
+
+// Inclusive row prefixes of the two rows of 256 values the wavefront holds
+// in segment layout (lane l, segment j: column 64 j + l), written to its own
+// LDS row as P(c) at index c + kWsP0.  The values pass through that row so
+// that lane l takes the four consecutive columns 4 l .. 4 l + 3: it adds them
+// up in order, one wavefront scan of the lane totals (DPP row shifts 1, 2, 4,
+// 8 and row broadcasts 15 and 31) gives each lane the sum of the columns
+// before its four, and the prefixes go back as two 16-byte stores.  Sums are
+// mod 2^32; only differences of them are used.
+__device__ inline void ws_scan_row(const uint32_t (&v)[kWsSlices][kSeg], uint2* row) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j) row[64 * j + lane + kWsP0] = make_uint2(v[0][j], v[1][j]);
+    __builtin_amdgcn_wave_barrier();  // the row is this wavefront's own
+    uint32_t a[kWsSlices][4];
+    uint4 lo, hi;  // columns 4 l, 4 l + 1 and 4 l + 2, 4 l + 3, both slices each
+    __builtin_memcpy(&lo, __builtin_assume_aligned(row + kWsP0 + 4 * lane, 16), 16);
+    __builtin_memcpy(&hi, __builtin_assume_aligned(row + kWsP0 + 4 * lane + 2, 16), 16);
+    a[0][0] = lo.x, a[1][0] = lo.y, a[0][1] = lo.z, a[1][1] = lo.w;
+    a[0][2] = hi.x, a[1][2] = hi.y, a[0][3] = hi.z, a[1][3] = hi.w;
+    uint32_t tot[kWsSlices];
+#pragma unroll
+    for (int s = 0; s < kWsSlices; ++s) {
+        a[s][1] += a[s][0];
+        a[s][2] += a[s][1];
+        a[s][3] += a[s][2];
+        tot[s] = a[s][3];
+    }
+#define DCO_WS_SCAN(CTRL, MASK) \
+    _Pragma("unroll") for (int s = 0; s < kWsSlices; ++s) tot[s] += dpp<CTRL, MASK>(tot[s]);
+    DCO_WS_SCAN(0x111, 0xf)
+    DCO_WS_SCAN(0x112, 0xf)
+    DCO_WS_SCAN(0x114, 0xf)
+    DCO_WS_SCAN(0x118, 0xf)
+    DCO_WS_SCAN(0x142, 0xa)
+    DCO_WS_SCAN(0x143, 0xc)
+#undef DCO_WS_SCAN
+#pragma unroll
+    for (int s = 0; s < kWsSlices; ++s) {
+        const uint32_t before = tot[s] - a[s][3];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[s][i] += before;
+    }
+    lo = make_uint4(a[0][0], a[1][0], a[0][1], a[1][1]);
+    hi = make_uint4(a[0][2], a[1][2], a[0][3], a[1][3]);
+    __builtin_memcpy(__builtin_assume_aligned(row + kWsP0 + 4 * lane, 16), &lo, 16);
+    __builtin_memcpy(__builtin_assume_aligned(row + kWsP0 + 4 * lane + 2, 16), &hi, 16);
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Row wavefront w, phase p: step 3 of chunk p - 2 and step 1 of chunk p.
+__device__ inline void ws_row_phase(const AggArgs& A, int ys, int y0, int y1, int p, int w,
+                                    const WsRowLane& ln, const AggRes& R, const WsRowIn& in,
+                                    AggLdsWs& S) {
+    // Both steps run as one straight block so that their LDS round trips
+    // overlap; in the phases where a step has no chunk its LDS writes land in
+    // rows nobody reads and its stores are skipped.
+    const int lane = threadIdx.x & 63;
+    const int W = A.W;
+    uint2* row = S.prow[p & 1][w];
+    // step 3 of chunk p - 2: vertical range sums of ring 2 (E2)
+    uint32_t e2[kWsSlices][kSeg];
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j) {
+        const uint32_t o = in.c3[j].x;  // ring 2 offsets in 8-byte words
+        const uint2 a = S.ring2[ln.cbs[j] + (o & 0xffff)], b = S.ring2[ln.cbs[j] + (o >> 16)];
+        e2[0][j] = a.x - b.x;
+        e2[1][j] = a.y - b.y;
+    }
+    // step 1 of chunk p: raw costs of Eq. 1 (rows below the image give 0)
+    uint32_t q[kWsSlices][kSeg];
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j) {
+        const uint64_t rc = (uint64_t)in.ref[j].y << 32 | in.ref[j].x;
+        const float2 ab = *reinterpret_cast<const float2*>(
+            reinterpret_cast<const char*>(S.ab) + in.ref[j].w);
+#pragma unroll
+        for (int s = 0; s < kWsSlices; ++s) {
+            const uint32_t sad = __builtin_amdgcn_sad_u8(in.ref[j].z, in.par[s][j].z, 0u);
+            const uint64_t x = rc ^ ((uint64_t)in.par[s][j].y << 32 | in.par[s][j].x);
+            const uint32_t h = (uint32_t)__popcll(x);
+            // RN(x + 2^23) = 2^23 + rint(x) for 0 <= x < 2^22, so the float
+            // bits minus those of 2^23 are rint(x)
+            const float ta = ab.x * S.tabA[sad], tc = ab.y * S.tabC[h];
+            q[s][j] = __builtin_bit_cast(uint32_t, ta + 0x1p23f) +
+                      __builtin_bit_cast(uint32_t, tc + 0x1p23f) - 2u * 0x4B000000u;
+        }
+    }
+    // every lookup stays unconditional; the selects are lane-mask cndmasks
+    asm volatile(""
+                 : "+v"(q[0][0]), "+v"(q[0][1]), "+v"(q[0][2]), "+v"(q[0][3]), "+v"(q[1][0]),
+                   "+v"(q[1][1]), "+v"(q[1][2]), "+v"(q[1][3]));
+    const uint32_t inside = ys + kAggK * p + w < A.H ? ~0u : 0u;  // uniform
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j)
+#pragma unroll
+        for (int s = 0; s < kWsSlices; ++s)
+            q[s][j] = (ln.pok[s][j] ? q[s][j] : ln.inval[j]) & inside;
+    // step 3: row prefixes of E2 in this wavefront's row, then the horizontal
+    // range sums and the final division
+    ws_scan_row(e2, row);
+    float out[kWsSlices][kSeg];
+    const uint32_t pbw = (uint32_t)(lane + kWsP0 - 1) * 8;
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j) {
+        const uint32_t lr = in.c3[j].z;  // arm offsets in 8-byte words
+        const uint2 a = lds_ld2(row, pbw + 512 * j + (lr & 0xff));
+        const uint2 b = lds_ld2(row, pbw + 512 * j - ((lr >> 8) & 0xff));
+        const float nf = __builtin_bit_cast(float, in.c3[j].w);
+        const float rcp = __builtin_bit_cast(float, in.c3[j].y);
+        out[0][j] = div_q20(a.x - b.x, nf, rcp);
+        out[1][j] = div_q20(a.y - b.y, nf, rcp);
+    }
+    // step 1: its row prefixes replace step 3's in the same row (LDS keeps
+    // this wavefront's order, so step 3's reads above see the old values)
+    ws_scan_row(q, row);
+    const int y2 = ys + kAggK * (p - 2) + w - 2 * kLMax - 1;
+    if (p >= 2 && y2 >= y0 && y2 < y1) {  // uniform
+#pragma unroll
+        for (int s = 0; s < kWsSlices; ++s)
+            if (s < R.nout)  // uniform
+#pragma unroll
+                for (int j = 0; j < kSeg; ++j)
+                    st32(out[s][j], R.rOut, ln.vout[j], (uint32_t)(y2 * W) * 4 + s * R.slice_bytes);
+    }
+}
+
+// Column thread ct (its column's ring byte offset cb), step 2 of chunk q.
+__device__ inline void ws_col_phase(int q, int nch, int ct, uint32_t cb, const WsColIn& in,
+                                    uint32_t (&cp1)[kWsSlices], uint32_t (&cp2)[kWsSlices],
+                                    uint32_t& off1, uint32_t& off2, AggLdsWs& S) {
+    if (q >= nch) return;  // uniform
+    const uint2* rows = S.prow[q & 1][0];
+    uint32_t e1[kWsSlices][kAggK];
+#pragma unroll
+    for (int k = 0; k < kAggK; ++k) {
+        const uint32_t a = in.b2[k].z;  // arm offsets in 8-byte words
+        const uint32_t pb = (uint32_t)(k * kWsPStride + ct + kWsP0 - 1) * 8;
+        const uint2 hi = lds_ld2(rows, pb + (a & 0xff)), lo = lds_ld2(rows, pb - ((a >> 8) & 0xff));
+        e1[0][k] = hi.x - lo.x;
+        e1[1][k] = hi.y - lo.y;
+    }
+    // push a row, then read that row's range, before the next push
+    uint32_t s1[kWsSlices][kAggK];
+#pragma unroll
+    for (int k = 0; k < kAggK; ++k) {
+        cp1[0] += e1[0][k];
+        cp1[1] += e1[1][k];
+        lds_st2(S.ring1, cb + off1, make_uint2(cp1[0], cp1[1]));
+        const uint32_t r = in.b2[k].y;  // ring 1 offsets in bytes
+        const uint2 hi = lds_ld2(S.ring1, cb + (r & 0xffff)), lo = lds_ld2(S.ring1, cb + (r >> 16));
+        s1[0][k] = hi.x - lo.x;
+        s1[1][k] = hi.y - lo.y;
+        off1 = off1 + kWsSlotBytes == kWsRing1 * kWsSlotBytes ? 0u : off1 + kWsSlotBytes;
+    }
+#pragma unroll
+    for (int k = 0; k < kAggK; ++k) {
+        const uint4 b = in.b2[k];
+        const uint32_t half = (b.z >> 16) & 1023, sh = b.z >> 26;
+#pragma unroll
+        for (int s = 0; s < kWsSlices; ++s) {
+            const uint64_t n = (uint64_t)(s1[s][k] + half) * b.x;
+            cp2[s] += (uint32_t)(n >> sh);
+        }
+        lds_st2(S.ring2, cb + off2, make_uint2(cp2[0], cp2[1]));
+        off2 = off2 + kWsSlotBytes == kWsRing2 * kWsSlotBytes ? 0u : off2 + kWsSlotBytes;
+    }
+}
+
+// Output rows [y0, y1) of slices d and d + 1 and column strip `strip`
+// (512 threads; two stages, cost fused).  The records must be written with
+// kRecWs.
+__device__ inline void agg_stream_ws(const AggArgs& A, int d, int strip, int y0, int y1,
+                                     AggLdsWs& S) {
+    const int W = A.W, H = A.H;
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int x0 = strip * kStripOut;
+    const size_t slice = (size_t)W * H;
+
+    for (int i = t; i < 766; i += kWsThreads) S.tabA[i] = A.tabA[i];
+    if (t < 65) S.tabC[t] = A.tabC[t];
+    if (t <= kLMax) {
+        const int L = min(t, A.L1);
+        S.ab[t] = make_float2(A.alpha[L], A.beta[L]);
+    }
+    if (t < 2 * kAggK * kWsP0) {  // P(-1) and the entries before it, every row
+        const int r = t / kWsP0;
+        S.prow[r / kAggK][r % kAggK][t % kWsP0] = make_uint2(0u, 0u);
+    }
+    // zero column prefixes: rows before the start contribute nothing
+    for (int i = t; i < kWsRing1 * kRingStride; i += kWsThreads) S.ring1[i] = make_uint2(0u, 0u);
+    for (int i = t; i < kWsRing2 * kRingStride; i += kWsThreads) S.ring2[i] = make_uint2(0u, 0u);
+
+    const uint32_t P4 = (uint32_t)(slice * 4);
+    AggRes R;
+    const uint4* Iref = A.ref == 0 ? A.pixL : A.pixR;
+    const uint4* Ipar = A.ref == 0 ? A.pixR : A.pixL;
+    R.rB = make_rsrc(A.rec.b, (uint32_t)(A.rec.Wp * (H + kLMax + 1)) * 16);
+    R.rC = make_rsrc(A.rec.c, (uint32_t)(A.rec.Wp * (H + 1)) * 16);
+    R.rq = R.rB;
+    R.rIr = make_rsrc(Iref, 4 * P4);
+    R.rIp = make_rsrc(Ipar, 4 * P4);
+    const int nout = min(kWsSlices, A.D - d);  // slices that exist
+    R.rOut = make_rsrc(A.out + (size_t)d * slice, (uint32_t)nout * P4);
+    R.slice_bytes = P4;
+    R.nout = nout;
+
+    const int warm = 2 * kLMax + 1;
+    const int ys = max(0, y0 - warm);
+    const int nch = (y1 + warm - ys + kAggK - 1) / kAggK;
+    const int last = nch + 1;  // phases 0 .. nch + 1
+    __syncthreads();
+
+    if (w < kAggK) {  // row wavefronts
+        WsRowLane ln;
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) {
+            const int i = 64 * j + lane;            // strip column of segment j
+            const int c = x0 - 2 * kLMax + i;       // image column
+            const bool in_img = c >= 0 && c < W;
+            ln.img[j] = in_img ? (uint32_t)c * 16 : kOOB;
+#pragma unroll
+            for (int s = 0; s < kWsSlices; ++s) {
+                const int cp = A.ref == 0 ? c - d - s : c + d + s;
+                const bool pok = in_img && cp >= 0 && cp < W;
+                ln.par[s][j] = pok ? (uint32_t)cp * 16 : kOOB;
+                ln.pok[s][j] = pok;
+            }
+            ln.inval[j] = in_img ? (1u << 20) : 0u;
+            // ring-2 column (kRingCols + 1, never written, for columns without one)
+            const bool rok = i >= kLMax && i < kLMax + kRingCols;
+            ln.cbs[j] = (uint32_t)(rok ? i - kLMax : kRingCols + 1);
+            ln.vout[j] =
+                i >= 2 * kLMax && i < 2 * kLMax + kStripOut && c < W ? (uint32_t)c * 4 : kOOB;
+        }
+        ln.recw = (uint32_t)(x0 - 2 * kLMax + lane + A.rec.apron) * 4;
+        WsRowIn ia, ib;
+        ws_row_load(A, ys, 0, w, ln, R, ia);
+        for (int p = 0;; p += 2) {
+            ws_row_load(A, ys, p + 1, w, ln, R, ib);
+            ws_row_phase(A, ys, y0, y1, p, w, ln, R, ia, S);
+            __syncthreads();
+            if (p + 1 > last) break;
+            ws_row_load(A, ys, p + 2, w, ln, R, ia);
+            ws_row_phase(A, ys, y0, y1, p + 1, w, ln, R, ib, S);
+            __syncthreads();
+            if (p + 2 > last) break;
+        }
+    } else {  // column threads
+        const int ct = t - kStripThreads;
+        const int c = x0 - 2 * kLMax + ct;
+        const int jj = ct - kLMax;
+        // threads without a ring column share one scratch column; column
+        // kRingCols + 1 stays zero
+        const uint32_t cb = (uint32_t)(jj >= 0 && jj < kRingCols ? jj : kRingCols) * 8;
+        const uint32_t reco = (uint32_t)(c + A.rec.apron) * 4;
+        uint32_t cp1[kWsSlices] = {0, 0}, cp2[kWsSlices] = {0, 0};
+        uint32_t off1 = ring_slot(ys, kWsRing1) * kWsSlotBytes;
+        uint32_t off2 = ring_slot(ys - kLMax, kWsRing2) * kWsSlotBytes;
+        WsColIn ja, jb;
+        ws_col_load(A, ys, 0, reco, R, ja);
+        __syncthreads();  // phase 0: no step 2 yet
+        for (int p = 1;; p += 2) {
+            if (p > last) break;
+            ws_col_load(A, ys, p, reco, R, jb);
+            ws_col_phase(p - 1, nch, ct, cb, ja, cp1, cp2, off1, off2, S);
+            __syncthreads();
+            if (p + 1 > last) break;
+            ws_col_load(A, ys, p + 1, reco, R, ja);
+            ws_col_phase(p, nch, ct, cb, jb, cp1, cp2, off1, off2, S);
+            __syncthreads();
+        }
     }
 }
 

@@ -19,7 +19,7 @@ constexpr int kVoteMaxIters = 64;  // passes of one Eq. 4 vote call
 struct dco_scratch {
     uint32_t* arms[2];
     AggRecords rec[2];
-    uint4* pix[2];      // packed pixels of both views: census, RGB | 8 L_min << 24
+    uint4* pix[2];      // packed pixels of both views: census lo, census hi, RGB, 8 L_min
     float* agg[2];      // aggregated volumes of both views (D x H x W)
     int16_t* dint[2];
     float* delta;
@@ -32,7 +32,7 @@ struct dco_scratch {
 struct SoftScratch {
     int cap;               // pairs the buffers hold
     uint4* pix[2];         // packed pixels of left / right views (census lo, census
-                           // hi, RGB | 8 L_min << 24, 0)
+                           // hi, RGB, 8 L_min)
     uint32_t* arms;        // arms of the left views
     uint32_t* arms_r;      // arms of the right views (computed, unused)
     float* n1;             // region counts
@@ -163,7 +163,7 @@ dco_status alloc_records(AggRecords* r, int W, int H);
 
 // ---- kernel launchers (one per .hip file) ----
 // census, rgb_packed (R | G << 8 | B << 16) and pix (census lo, census hi,
-// packed RGB | 8 L_min << 24, 0) are optional outputs
+// packed RGB, 8 L_min) are optional outputs
 hipError_t launch_census_arms(const uint8_t* rgb, int W, int H, int cw, int ch, int L1, int tau1,
                               uint64_t* census, uint32_t* arms, uint32_t* rgb_packed, uint4* pix,
                               hipStream_t st);
@@ -230,11 +230,13 @@ hipError_t launch_census_pairs(const uint8_t* rgbL, const uint8_t* rgbR, int B, 
                                int cw, int ch, int L1, int tau1, uint32_t* armsL, uint32_t* armsR,
                                uint4* pixL, uint4* pixR, hipStream_t st);
 // Census + arms + packed pixels, then region counts + records, of both views
-// (the one-call path): two launches.
+// (the one-call path): two launches.  The records address the LDS of the
+// aggregation kernel that launch_cost_aggregate2 runs (pair_rec_geom).
 hipError_t launch_front2(const uint8_t* rgbL, const uint8_t* rgbR, int W, int H, int cw, int ch,
                          int L1, int tau1, int iters, uint32_t* armsL, uint32_t* armsR,
                          uint4* pixL, uint4* pixR, const AggRecords& recL, const AggRecords& recR,
-                         hipStream_t st);
+                         const RecGeom& g, hipStream_t st);
+RecGeom pair_rec_geom(int iters);
 hipError_t launch_geometry(const uint32_t* arms, int W, int H, int iters, const AggRecords& rec,
                            hipStream_t st);
 hipError_t launch_cost(int ref, const uint8_t* rgbL, const uint8_t* rgbR, const uint64_t* cenL,

@@ -14,8 +14,8 @@ constexpr int kStripThreads = 256;
 constexpr int kStripOut = kStripThreads - 4 * kLMax;
 
 // Packed per-pixel records of one view for the aggregation kernels, written
-// by k_geometry.  Both arrays hold 4-word entries (the fourth is unused: one
-// 16-byte load per pixel is cheaper than a 12-byte one), Wp per row; column x
+// by k_geometry.  Both arrays hold 4-word entries (the fourth of b is unused:
+// one 16-byte load per pixel is cheaper than a 12-byte one), Wp per row; column x
 // sits at x + apron, and the apron columns are zero.  With hw(p) = 4 (r + 1) | 4 l << 8
 // (horizontal arms as byte offsets) and ring offsets rb(p) = the byte offsets
 // of prefix rows y + dn and y - u - 1 in a ring (16 bits each):
@@ -25,7 +25,7 @@ constexpr int kStripOut = kStripThreads - 4 * kLMax;
 //     one stage:  RN(1/N1) 2^-20, rb1, hw(x, r) | N1 << 16
 //     (hw of row r is 0 from row H on; the rest is 0 above row kLMax)
 //   c row y (H + 1 rows; row H is zero), two stages only:
-//     rb2, RN(1/N2) 2^-20, hw | N2 << 16                         of pixel (x, y)
+//     rb2, RN(1/N2) 2^-20, hw | N2 << 16, N2 2^20 (float)        of pixel (x, y)
 struct AggRecords {
     uint32_t* b;
     uint32_t* c;
@@ -33,3 +33,13 @@ struct AggRecords {
 };
 constexpr int kRecApronL = 2 * kLMax;        // left apron of the records
 constexpr int kRecApronR = kStripThreads;    // right apron (covers a strip's overhang)
+
+// How the records address the LDS of the kernel that reads them: the row
+// counts of its two rings, the value stored per ring slot (ring 1 in bytes,
+// ring 2 in bytes or in 8-byte words) and the bytes of one prefix-row entry
+// (the scale of the arm offsets in hw).  Slot value x (rows - 1) and
+// hw x (kLMax + 1) must fit 16 and 8 bits.
+struct RecGeom {
+    int ring1, ring2;
+    uint32_t step1, step2, hw;
+};

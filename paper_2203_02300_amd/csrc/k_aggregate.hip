@@ -77,6 +77,80 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_agg_pair(dco::AggArgs A0, 
     dco::agg_stream<ITERS, true>(A, d, strip, y0, y1, S);
 }
 
+// Two stages: the same items with two adjacent disparities per item, one
+// 512-thread workgroup per CU (dco::agg_stream_ws).
+__global__ __launch_bounds__(dco::kWsThreads, 1) void k_agg_pair_ws(dco::AggArgs A0,
+                                                                    AggRecords rec1, float* out1,
+                                                                    int s8) {
+    __shared__ dco::AggLdsWs S;
+    const int groups = (A0.D + dco::kWsSlices - 1) / dco::kWsSlices;
+    const int per_view = A0.nstrips * groups, N = 2 * per_view;
+    const int x = blockIdx.x % 8, i = blockIdx.x / 8;
+    int start, nx, m;
+    pair_part(N, x, s8, A0.H, start, nx, m);
+    int item, y0 = 0, y1 = A0.H;
+    if (i < nx - m) {
+        item = start + i;
+    } else {
+        const int j = i - (nx - m);
+        if (j >= 2 * m) return;  // uniform: the whole workgroup leaves
+        item = start + nx - m + (j < m ? j : j - m);  // all top halves, then bottoms
+        if (j >= m)
+            y0 = A0.H / 2;
+        else
+            y1 = A0.H / 2;
+    }
+    const int view = item / per_view, rest = item - view * per_view;
+    const int strip = rest / groups, g = rest - strip * groups;
+    dco::AggArgs A = A0;  // left view; the right view differs in three fields
+    if (view) {
+        A.ref = 1;
+        A.rec = rec1;
+        A.out = out1;
+    }
+    dco::agg_stream_ws(A, g * dco::kWsSlices, strip, y0, y1, S);
+}
+
+// Resident workgroups per XCD of a kernel (queried once per device and
+// kernel; concurrent first calls store the same value).
+template <typename K>
+hipError_t xcd_slots(K kernel, int threads, std::atomic<int>* slots, int* s8) {
+    constexpr int kMaxDev = 64;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    int total = dev < kMaxDev ? slots[dev].load(std::memory_order_relaxed) : 0;
+    if (!total) {
+        int cus = 0, nb = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0);
+        if (e != hipSuccess) return e;
+        total = (nb > 0 ? nb : 1) * (cus > 0 ? cus : 1);
+        if (dev < kMaxDev) slots[dev].store(total, std::memory_order_relaxed);
+    }
+    *s8 = total / 8;
+    return hipSuccess;
+}
+
+hipError_t launch_pair_ws(const dco::AggArgs& a0, const AggRecords& rec1, float* out1,
+                          hipStream_t st) {
+    static std::atomic<int> slots[64];
+    int s8 = 0;
+    hipError_t e = xcd_slots(k_agg_pair_ws, dco::kWsThreads, slots, &s8);
+    if (e != hipSuccess) return e;
+    const int N = 2 * a0.nstrips * ((a0.D + dco::kWsSlices - 1) / dco::kWsSlices);
+    int most = 1;
+    for (int x = 0; x < 8; ++x) {
+        int start, nx, m;
+        pair_part(N, x, s8, a0.H, start, nx, m);
+        most = nx + m > most ? nx + m : most;
+    }
+    hipLaunchKernelGGL(k_agg_pair_ws, dim3(8 * most), dim3(dco::kWsThreads), 0, st, a0, rec1,
+                       out1, s8);
+    return hipGetLastError();
+}
+
 template <int ITERS>
 hipError_t launch_pair(const dco::AggArgs& a0, const AggRecords& rec1, float* out1,
                        hipStream_t st) {
@@ -153,8 +227,10 @@ hipError_t launch_cost_aggregate2(const uint4* pixL, const uint4* pixR, const Ag
     a.ref = 0;
     a.rec = recL;
     a.out = outL;
-    return iters == 1 ? launch_pair<1>(a, recR, outR, st) : launch_pair<2>(a, recR, outR, st);
+    return iters == 1 ? launch_pair<1>(a, recR, outR, st) : launch_pair_ws(a, recR, outR, st);
 }
+
+RecGeom pair_rec_geom(int iters) { return iters == 2 ? dco::kRecWs : dco::kRecPlain; }
 
 hipError_t launch_cost_aggregate(int ref, const uint4* pixL, const uint4* pixR,
                                  const AggRecords& rec, int W, int H, int D, int iters,

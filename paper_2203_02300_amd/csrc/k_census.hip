@@ -40,11 +40,11 @@ __global__ __launch_bounds__(256) void k_census_arms2(const uint8_t* __restrict_
 __global__ __launch_bounds__(256) void k_geometry2(const uint32_t* __restrict__ armsL,
                                                    const uint32_t* __restrict__ armsR, int W,
                                                    int H, int iters, AggRecords recL,
-                                                   AggRecords recR) {
+                                                   AggRecords recR, RecGeom g) {
     __shared__ dco::GeomLds S;
     const bool r = blockIdx.z != 0;
     dco::geometry_tile(r ? armsR : armsL, W, H, iters, r ? recR : recL,
-                       blockIdx.x * dco::kGeoTW, blockIdx.y * dco::kGeoTH, S);
+                       blockIdx.x * dco::kGeoTW, blockIdx.y * dco::kGeoTH, S, g);
 }
 
 // Every view of a batch of pairs in one launch (blockIdx.z = 2 * pair + view),
@@ -84,12 +84,13 @@ hipError_t launch_census_pairs(const uint8_t* rgbL, const uint8_t* rgbR, int B, 
 hipError_t launch_front2(const uint8_t* rgbL, const uint8_t* rgbR, int W, int H, int cw, int ch,
                          int L1, int tau1, int iters, uint32_t* armsL, uint32_t* armsR,
                          uint4* pixL, uint4* pixR, const AggRecords& recL, const AggRecords& recR,
-                         hipStream_t st) {
+                         const RecGeom& g, hipStream_t st) {
     dim3 g1((W + dco::kCenTW - 1) / dco::kCenTW, (H + dco::kCenTH - 1) / dco::kCenTH, 2);
     hipLaunchKernelGGL(k_census_arms2, g1, dim3(256), 0, st, rgbL, rgbR, W, H, cw, ch, L1, tau1,
                        armsL, armsR, pixL, pixR);
     dim3 g2((W + dco::kGeoTW - 1) / dco::kGeoTW, (H + dco::kGeoTH - 1) / dco::kGeoTH, 2);
-    hipLaunchKernelGGL(k_geometry2, g2, dim3(256), 0, st, armsL, armsR, W, H, iters, recL, recR);
+    hipLaunchKernelGGL(k_geometry2, g2, dim3(256), 0, st, armsL, armsR, W, H, iters, recL, recR,
+                       g);
     return hipGetLastError();
 }
 

@@ -112,7 +112,7 @@ constexpr size_t kTabLds = (kTabFloats + 32) * sizeof(float);
 
 struct SoftImg {
     const uint4* pixL;   // B x H x W packed pixels: census lo, census hi,
-    const uint4* pixR;   //   RGB | 8 L_min << 24, 0
+    const uint4* pixR;   //   RGB, 8 L_min
     const float* alpha;  // alpha_L, L = 0..kLMax
     const float* tab;    // k_soft_tables output
 };
@@ -129,9 +129,9 @@ __device__ inline void load_tables(const SoftImg& im, float* lds) {
 template <bool kDeriv>
 __device__ inline void cost_px(uint4 a, uint4 b, bool inside, const float* tab, float& c,
                                float& dca, float& dcc) {
-    const uint32_t s = __builtin_amdgcn_sad_u8(a.z << 8, b.z << 8, 0u);  // L_min shifted out
+    const uint32_t s = __builtin_amdgcn_sad_u8(a.z, b.z, 0u);
     const int h = __popcll(((uint64_t)a.y << 32 | a.x) ^ ((uint64_t)b.y << 32 | b.x));
-    const float al = tab[kTabFloats + (a.z >> 27)];
+    const float al = tab[kTabFloats + (a.w >> 3)];
     const float v = al * tab[s] + (1.0f - al) * tab[1536 + h];
     c = inside ? v : 1.0f;
     if (kDeriv) {
