@@ -364,6 +364,27 @@ const char* dco_last_error(void); /* thread-local; "" when none */
  * path's volume element by element.  DCO_ERR_ARG for a bad view or range. */
 dco_status dco_stereo_agg_slices(dco_stereo* h, int view, int d0, int n, float* out);
 
+/* The one-call match without a handle and without any allocation, for
+ * callers that cannot allocate device or host memory: code under HIP stream
+ * capture, tight serving loops, harnesses that forbid allocation.  Same
+ * kernels and same result, bit for bit, as dco_stereo_create(W, H, D, params)
+ * followed by dco_stereo_match on stream (params NULL = defaults; every
+ * parameter, vote_iters included, applies).  Inputs rgbL, rgbR (device, H x W
+ * x 3 uint8) and outputs disp (device, H x W float), valid (device, H x W
+ * uint8) are the caller's; every intermediate buffer (packed pixels, arms,
+ * records, both aggregated volumes, disparity maps, the Eq. 1 tables) lives
+ * in a static device array of 160 MiB that the library holds on each GPU it
+ * has run this call on until the process ends.  Shapes whose buffers do not
+ * fit (beyond about 640 x 360 with D = 64) return DCO_ERR_SHAPE with the
+ * bytes needed in dco_last_error(); argument and shape errors are the same
+ * as dco_stereo_create's and are reported before any launch.  Asynchronous
+ * on stream.  Every call on one GPU uses the same array: calls that overlap
+ * on one GPU (two streams, two threads) race and must be serialised by the
+ * caller; a later call overwrites what an earlier one left there. */
+dco_status dco_stereo_match_noalloc(int W, int H, int D, const dco_params* params, void* stream,
+                                    const uint8_t* rgbL, const uint8_t* rgbR, float* disp,
+                                    uint8_t* valid);
+
 /* Testing hooks for the error paths.  dco_debug_fail_alloc(k) makes the
  * k-th device or pinned allocation made by the library from now on fail
  * with DCO_ERR_OOM (k <= 0 disarms; DCO_FAIL_ALLOC=k in the environment arms

@@ -23,7 +23,7 @@ EXPORTS = (
     "dco_contour_default_params", "dco_contour_create", "dco_contour_destroy",
     "dco_contour_run", "dco_contour_launches",
     "dco_status_string", "dco_last_error", "dco_stereo_agg_slices", "dco_debug_fail_alloc",
-    "dco_debug_live_allocations",
+    "dco_debug_live_allocations", "dco_stereo_match_noalloc",
 )
 
 DCO_OK = 0
@@ -96,6 +96,7 @@ def lib():
         "dco_soft_backward": (st, [P, i, P, P, P, P, P, P, P]),
         "dco_vote_refine": (st, [P, P, P, P, P, i, P, P, P]),
         "dco_stereo_match_half": (st, [P, P, P, i, i, C.c_float, P, P, P]),
+        "dco_stereo_match_noalloc": (st, [i, i, i, C.POINTER(Params), P, P, P, P, P]),
         "dco_densify_default_params": (st, [C.POINTER(DensifyParams)]),
         "dco_densify_create": (st, [C.POINTER(P), i, i, C.POINTER(DensifyParams), P]),
         "dco_densify_destroy": (None, [P]),

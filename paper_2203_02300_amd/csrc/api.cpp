@@ -127,13 +127,10 @@ dco_status check_shape(int W, int H, int D, const dco_params& p) {
 
 // Eq. 1 tables, evaluated in double and rounded once to float.  The AD and
 // census tables are stored scaled by 2^20 (an exact power-of-two scaling), so
-// a kernel's alpha_L * tabA[s] equals RN(alpha_L * TA[s]) * 2^20.
-void build_tables(const dco_params& p, std::vector<float>& tabA, std::vector<float>& tabC,
-                         std::vector<float>& alpha, std::vector<float>& beta) {
-    tabA.assign(768, 0.0f);
-    tabC.assign(65, 0.0f);
-    alpha.assign(kLMax + 1, 0.0f);
-    beta.assign(kLMax + 1, 0.0f);
+// a kernel's alpha_L * tabA[s] equals RN(alpha_L * TA[s]) * 2^20.  Writes
+// tabA[0..767] (765 used), tabC[0..64] and alpha, beta[0..kLMax].
+void build_tables_into(const dco_params& p, float* tabA, float* tabC, float* alpha, float* beta) {
+    for (int s = 0; s < 768; ++s) tabA[s] = 0.0f;
     const double g = p.gamma_L, e = p.eps, la = p.lambda_ad, lc = p.lambda_census;
     for (int L = 0; L <= kLMax; ++L) {
         const double w = std::exp(-g / ((double)L + e));
@@ -143,6 +140,15 @@ void build_tables(const dco_params& p, std::vector<float>& tabA, std::vector<flo
     for (int s = 0; s <= 765; ++s)
         tabA[s] = std::ldexp((float)(-std::expm1(-(double)s / (3.0 * la))), 20);
     for (int h = 0; h <= 64; ++h) tabC[h] = std::ldexp((float)(-std::expm1(-(double)h / lc)), 20);
+}
+
+void build_tables(const dco_params& p, std::vector<float>& tabA, std::vector<float>& tabC,
+                  std::vector<float>& alpha, std::vector<float>& beta) {
+    tabA.assign(768, 0.0f);
+    tabC.assign(65, 0.0f);
+    alpha.assign(kLMax + 1, 0.0f);
+    beta.assign(kLMax + 1, 0.0f);
+    build_tables_into(p, tabA.data(), tabC.data(), alpha.data(), beta.data());
 }
 
 static void free_handle_memory(dco_stereo* h) {

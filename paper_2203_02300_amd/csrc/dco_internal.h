@@ -157,6 +157,7 @@ dco_status need(const void* ptr, const char* what);
 dco_status need_align(const void* ptr, size_t a, const char* what);
 dco_status check_params(const dco_params& p);
 dco_status check_shape(int W, int H, int D, const dco_params& p);
+void build_tables_into(const dco_params& p, float* tabA, float* tabC, float* alpha, float* beta);
 void build_tables(const dco_params& p, std::vector<float>& tabA, std::vector<float>& tabC,
                   std::vector<float>& alpha, std::vector<float>& beta);
 dco_status alloc_records(AggRecords* r, int W, int H);

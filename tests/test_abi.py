@@ -143,3 +143,21 @@ def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         _lib.lib()
+
+
+def test_noalloc_match_checks_arguments_before_any_launch(L):
+    """dco_stereo_match_noalloc rejects bad arguments and shapes whose buffers
+    do not fit its static scratch on the host, before touching a GPU."""
+    p = _lib.Params()
+    L.dco_default_params(C.byref(p))
+    buf = C.create_string_buffer(16)
+    ptr = C.cast(buf, C.c_void_p)
+    assert L.dco_stereo_match_noalloc(64, 48, 16, C.byref(p), None, None, ptr, ptr, ptr) == -1
+    assert L.dco_stereo_match_noalloc(64, 48, 64, C.byref(p), None, ptr, ptr, ptr, ptr) == -2
+    # 1280 x 720 with D = 128 needs about 1 GB: more than the 160 MiB array
+    assert L.dco_stereo_match_noalloc(1280, 720, 128, C.byref(p), None, ptr, ptr, ptr, ptr) == -2
+    assert b"static scratch" in L.dco_last_error()
+    bad = _lib.Params()
+    L.dco_default_params(C.byref(bad))
+    bad.agg_iters = 3
+    assert L.dco_stereo_match_noalloc(64, 48, 16, C.byref(bad), None, ptr, ptr, ptr, ptr) == -1
