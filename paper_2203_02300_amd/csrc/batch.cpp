@@ -247,9 +247,11 @@ std::string cache_path() {
     return std::string(home ? home : "/tmp") + "/.cache/dco_stereo_autotune.txt";
 }
 
+// The key names the stage-2 kernel generation too ("s2" = two disparities
+// per pass), so tiles timed with another kernel are not reused.
 std::string class_key(int W, int H, int D, int iters, const char* arch) {
     char buf[160];
-    snprintf(buf, sizeof buf, "%dx%dx%d:%s:iters%d", W, H, D, arch, iters);
+    snprintf(buf, sizeof buf, "%dx%dx%d:%s:iters%d:s2", W, H, D, arch, iters);
     return buf;
 }
 
@@ -286,14 +288,20 @@ void write_cache(const std::map<std::string, Tile>& m) {
     fclose(f);
 }
 
-std::vector<Tile> candidates(int H, int D) {
+// Row bands and disparity chunks to time.  With two aggregation stages the
+// kernel takes two disparities per pass, so chunks are even (a range of one
+// disparity keeps a chunk of one).
+std::vector<Tile> candidates(int H, int D, int iters) {
     std::vector<Tile> out;
     const int bands[] = {H, 256, 128};
-    const int chunks[] = {1, 2, 4};
+    const int chunks1[] = {1, 2, 4}, chunks2[] = {2, 4, 8};
+    const int* chunks = iters == 2 ? chunks2 : chunks1;
     for (int band : bands) {
         if (band > H || (band != H && band * 2 > H)) continue;
-        for (int dc : chunks)
-            if (dc <= D) out.push_back(Tile{band, dc});
+        for (int k = 0; k < 3; ++k) {
+            const int dc = chunks[k];
+            if (dc <= D || (k == 0 && D < dc)) out.push_back(Tile{band, std::min(dc, D)});
+        }
     }
     return out;
 }
@@ -350,8 +358,8 @@ dco_status tune_class(const dco_params& p, int W, int H, int D, hipStream_t st, 
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     float best_ms = 1e30f;
-    *best = Tile{H, 1};
-    for (const Tile& c : candidates(H, D)) {
+    *best = Tile{H, p.agg_iters == 2 ? std::min(2, D) : 1};
+    for (const Tile& c : candidates(H, D, p.agg_iters)) {
         if (e != hipSuccess) break;
         for (BatchPair& pr : tb.pairs) {
             pr.band = c.band;
@@ -430,7 +438,7 @@ extern "C" dco_status dco_batch_create(dco_batch** out, int n, const int* W, con
     for (int i = 0; i < n; ++i) {
         const std::string key = class_key(W[i], H[i], D[i], prm.agg_iters, arch);
         if (!tune) {
-            tiles[i] = Tile{H[i], 1};
+            tiles[i] = Tile{H[i], prm.agg_iters == 2 ? std::min(2, D[i]) : 1};
             continue;
         }
         auto it = cache.find(key);

@@ -985,9 +985,9 @@ __device__ inline void ws_col_phase(int q, int nch, int ct, uint32_t cb, const W
 }
 
 // Output rows [y0, y1) of slices d and d + 1 and column strip `strip`
-// (512 threads; two stages, cost fused).  The records must be written with
-// kRecWs.
-__device__ inline void agg_stream_ws(const AggArgs& A, int d, int strip, int y0, int y1,
+// (512 threads; two stages, cost fused); slices at or past dend are computed
+// but not stored.  The records must be written with kRecWs.
+__device__ inline void agg_stream_ws(const AggArgs& A, int d, int dend, int strip, int y0, int y1,
                                      AggLdsWs& S) {
     const int W = A.W, H = A.H;
     const int t = threadIdx.x, lane = t & 63;
@@ -1018,7 +1018,7 @@ __device__ inline void agg_stream_ws(const AggArgs& A, int d, int strip, int y0,
     R.rq = R.rB;
     R.rIr = make_rsrc(Iref, 4 * P4);
     R.rIp = make_rsrc(Ipar, 4 * P4);
-    const int nout = min(kWsSlices, A.D - d);  // slices that exist
+    const int nout = min(kWsSlices, min(A.D, dend) - d);  // slices to store
     R.rOut = make_rsrc(A.out + (size_t)d * slice, (uint32_t)nout * P4);
     R.slice_bytes = P4;
     R.nout = nout;

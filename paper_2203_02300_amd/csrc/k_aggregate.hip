@@ -108,7 +108,7 @@ __global__ __launch_bounds__(dco::kWsThreads, 1) void k_agg_pair_ws(dco::AggArgs
         A.rec = rec1;
         A.out = out1;
     }
-    dco::agg_stream_ws(A, g * dco::kWsSlices, strip, y0, y1, S);
+    dco::agg_stream_ws(A, g * dco::kWsSlices, A.D, strip, y0, y1, S);
 }
 
 // Resident workgroups per XCD of a kernel (queried once per device and

@@ -24,6 +24,40 @@ struct NoLds {
     int unused;
 };
 
+// Stage 2 with two aggregation stages: slices a .. a + dchunk - 1 of strip b,
+// row band c, two adjacent disparities per pass of dco::agg_stream_ws (512
+// threads, one workgroup per CU).  The workgroups of XCD x take that XCD's
+// contiguous part of the list, one item each.
+__global__ __launch_bounds__(dco::kWsThreads, 1) void k_batch_agg_ws(BatchArgs B, int first) {
+    __shared__ dco::AggLdsWs S;
+    const int x = blockIdx.x % kXcds;
+    const int k = B.xsplit[x] - first + blockIdx.x / kXcds;
+    if (k >= B.xsplit[x + 1] - first) return;  // uniform
+    const BatchItem I = B.items[first + k];
+    const BatchPair& pr = B.pairs[I.pair];
+    dco::AggArgs A{};
+    A.pixL = pr.pix[0];
+    A.pixR = pr.pix[1];
+    A.tabA = B.tabA;
+    A.tabC = B.tabC;
+    A.alpha = B.alpha;
+    A.beta = B.beta;
+    A.rec = pr.rec[I.view];
+    A.out = pr.agg[I.view];
+    A.W = pr.W;
+    A.H = pr.H;
+    A.D = pr.D;
+    A.nstrips = pr.nstrips;
+    A.ref = I.view;
+    A.L1 = B.L1;
+    const int y0 = I.c * pr.band, y1 = min(pr.H, y0 + pr.band);
+    const int dend = min(pr.D, I.a + pr.dchunk);
+    for (int d = I.a; d < dend; d += dco::kWsSlices) {
+        dco::agg_stream_ws(A, d, dend, I.b, y0, y1, S);
+        __syncthreads();
+    }
+}
+
 // LDS of each stage kernel: census tiles, aggregation rings, or none.
 template <int ITERS, int STAGE>
 using StageLds = typename std::conditional<
@@ -66,7 +100,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BatchArgs B, int first, 
                 const int y0 = I.b * 64 + r * dco::kGeoTH;
                 if (y0 >= H) break;
                 dco::geometry_tile(pr.arms[I.view], W, H, ITERS, pr.rec[I.view], I.a * dco::kGeoTW,
-                                   y0, S);
+                                   y0, S, ITERS == 2 ? dco::kRecWs : dco::kRecPlain);
                 __syncthreads();
             }
         } else if constexpr (STAGE == 2) {  // slices a .. a+dchunk-1, strip b, row band c
@@ -133,8 +167,12 @@ hipError_t launch_all(const BatchArgs& a, const int* first, const int* grid, hip
                        first[1] - first[0]);
     hipLaunchKernelGGL((k_batch_stage<ITERS, 1>), dim3(grid[1]), dim3(256), 0, st, a, first[1],
                        first[2] - first[1]);
-    hipLaunchKernelGGL((k_batch_stage<ITERS, 2>), dim3(grid[2]), dim3(256), 0, st, a, first[2],
-                       first[3] - first[2]);
+    if constexpr (ITERS == 2)
+        hipLaunchKernelGGL(k_batch_agg_ws, dim3(grid[2]), dim3(dco::kWsThreads), 0, st, a,
+                           first[2]);
+    else
+        hipLaunchKernelGGL((k_batch_stage<ITERS, 2>), dim3(grid[2]), dim3(256), 0, st, a,
+                           first[2], first[3] - first[2]);
     hipLaunchKernelGGL((k_batch_stage<ITERS, 3>), dim3(grid[3]), dim3(256), 0, st, a, first[3],
                        first[4] - first[3]);
     hipLaunchKernelGGL((k_batch_stage<ITERS, 4>), dim3(grid[4]), dim3(256), 0, st, a, first[4],
@@ -146,7 +184,14 @@ template <int ITERS>
 void blocks_per_cu(int* per_stage) {
     per_stage[0] = stage_blocks_per_cu<ITERS, 0>();
     per_stage[1] = stage_blocks_per_cu<ITERS, 1>();
-    per_stage[2] = stage_blocks_per_cu<ITERS, 2>();
+    if constexpr (ITERS == 2) {
+        int nb = 0;
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, k_batch_agg_ws, dco::kWsThreads, 0);
+        per_stage[2] = e == hipSuccess && nb > 0 ? nb : 1;
+    } else {
+        per_stage[2] = stage_blocks_per_cu<ITERS, 2>();
+    }
     per_stage[3] = stage_blocks_per_cu<ITERS, 3>();
     per_stage[4] = stage_blocks_per_cu<ITERS, 4>();
 }
