@@ -23,10 +23,11 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_agg_stream(dco::AggArgs A)
 }
 
 // Blocks of XCD x in the two-view launch: its nx items (a contiguous,
-// strip-major run), the last m of them split into a top and a bottom half so
-// that the final round of workgroups is not left part-empty.  The top halves
-// of the m items run before their bottom halves: workgroups resident together
-// then walk the same rows of one strip, which the XCD's L2 serves once.
+// strip-major run), the last m = nx mod s8 of them split into a top and a
+// bottom half, so that the final round of workgroups is one round of half
+// items instead of a part-empty round of whole ones.  The top halves of the
+// m items run before their bottom halves: workgroups resident together then
+// walk the same rows of one strip, which the XCD's L2 serves once.
 // s8 = resident workgroups per XCD.
 __host__ __device__ inline void pair_part(int N, int x, int s8, int H, int& start, int& nx,
                                           int& m) {
@@ -38,8 +39,7 @@ __host__ __device__ inline void pair_part(int N, int x, int s8, int H, int& star
     if (nx <= s8) {
         m = 2 * nx <= s8 ? nx : 0;
     } else {
-        const int r = nx % s8;
-        m = r ? (r + s8 < nx ? r + s8 : nx) : 0;
+        m = nx % s8;
     }
 }
 
