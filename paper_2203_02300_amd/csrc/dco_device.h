@@ -27,6 +27,14 @@ struct CensusLds {
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// DPP move of v (lanes without a source read 0): row shifts 0x111..0x118,
+// row broadcasts 0x142 (lane 15 of each row to the next row) and 0x143
+// (lane 31 to rows 2 and 3).
+template <unsigned Ctrl, unsigned RowMask>
+__device__ inline uint32_t dpp(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, Ctrl, RowMask, 0xf, false);
+}
+
 __device__ inline uint32_t grey_of(uint32_t c) {
     uint32_t r = c & 0xffu, g = (c >> 8) & 0xffu, b = (c >> 16) & 0xffu;
     return (77u * r + 150u * g + 29u * b + 128u) >> 8;
@@ -82,23 +90,26 @@ __device__ inline uint64_t census_code_any(const CensusLds& S, int tx, int ty, i
     return code;
 }
 
-// One 64 x 16 tile at (x0, y0), 256 threads.  The tile plus a kLMax apron
-// (edge-clamped) is staged in LDS as packed RGB words; grey levels of the
-// tile plus the census apron go to a second array.
+// One 64 x 16 tile at (x0, y0), NT threads (256: four pixels per thread;
+// 1024: one).  The tile plus a kLMax apron (edge-clamped) is staged in LDS as
+// packed RGB words; grey levels of the tile plus the census apron go to a
+// second array.
 //   grey:   Y = (77 R + 150 G + 29 B + 128) >> 8
 //   census: bit k = Y(q_k) < Y(p), neighbours row-major without the centre
 //   arms:   steps j = 1.. while inside, j <= L1 and max channel |diff| < tau1
+template <int NT = 256>
 __device__ inline void census_tile(const uint8_t* __restrict__ rgb, int W, int H, int cw, int ch,
                                    int L1, int tau1, uint64_t* __restrict__ census,
                                    uint32_t* __restrict__ arms, uint32_t* __restrict__ rgb_packed,
                                    uint4* __restrict__ pix, int x0, int y0, CensusLds& S) {
+    static_assert(NT % 64 == 0 && (kCenTW * kCenTH) % NT == 0, "whole rows per pass");
     const int t = threadIdx.x;
     {   // stage the region: every load issued before any is stored
-        constexpr int kN = (kCenRW * kCenRH + 255) / 256;
+        constexpr int kN = (kCenRW * kCenRH + NT - 1) / NT;
         uint32_t v[kN];
 #pragma unroll
         for (int k = 0; k < kN; ++k) {
-            const int i = min(t + 256 * k, kCenRW * kCenRH - 1);
+            const int i = min(t + NT * k, kCenRW * kCenRH - 1);
             const int ry = i / kCenRW, rx = i - ry * kCenRW;
             const int gx = clampi(x0 - kLMax + rx, 0, W - 1), gy = clampi(y0 - kLMax + ry, 0, H - 1);
             const uint8_t* p = rgb + 3 * ((size_t)gy * W + gx);
@@ -106,7 +117,7 @@ __device__ inline void census_tile(const uint8_t* __restrict__ rgb, int W, int H
         }
 #pragma unroll
         for (int k = 0; k < kN; ++k) {
-            const int i = t + 256 * k;
+            const int i = t + NT * k;
             if (i < kCenRW * kCenRH) {
                 const int ry = i / kCenRW;
                 S.rgb[ry][i - ry * kCenRW] = v[k];
@@ -114,7 +125,7 @@ __device__ inline void census_tile(const uint8_t* __restrict__ rgb, int W, int H
         }
     }
     __syncthreads();
-    for (int i = t; i < kCenGW * kCenGH; i += 256) {
+    for (int i = t; i < kCenGW * kCenGH; i += NT) {
         int gy = i / kCenGW, gx = i - gy * kCenGW;
         S.grey[gy][gx] = grey_of(S.rgb[gy + kLMax - kCenHH][gx + kLMax - kCenHW]);
     }
@@ -122,8 +133,8 @@ __device__ inline void census_tile(const uint8_t* __restrict__ rgb, int W, int H
 
     const int hw = cw >> 1, hh = ch >> 1;
     const int tx = t & 63;
-    for (int k = 0; k < kCenTH / 4; ++k) {
-        const int ty = (t >> 6) + 4 * k;
+    for (int k = 0; k < kCenTH / (NT / 64); ++k) {
+        const int ty = (t >> 6) + (NT / 64) * k;
         const int x = x0 + tx, y = y0 + ty;
         if (x >= W || y >= H) continue;
         const uint64_t code = cw == 9 && ch == 7
@@ -246,23 +257,28 @@ struct GeomLds {
     uint32_t rp[kGeoTH][kGeoRW + 1];   // row prefixes of v (column 0 = 0)
 };
 
+// NT = 256 threads sum the prefixes with one thread per column or row;
+// NT = 1024 threads use DPP scans (16 lanes per column, one wavefront per
+// row) and take one pixel each.
+template <int NT = 256>
 __device__ inline void geometry_tile(const uint32_t* __restrict__ arms, int W, int H, int iters,
                                      const AggRecords& rec, int x0, int y0, GeomLds& S,
                                      const RecGeom& g = kRecPlain) {
+    static_assert(NT == 256 || NT == 1024, "256 or 1024 threads");
     const int t = threadIdx.x;
     {   // stage the arms: every load issued before any is used (clamped addresses)
-        constexpr int kN = (kGeoRW * kGeoRH + 255) / 256;
+        constexpr int kN = (kGeoRW * kGeoRH + NT - 1) / NT;
         uint32_t v[kN];
 #pragma unroll
         for (int k = 0; k < kN; ++k) {
-            const int i = min(t + 256 * k, kGeoRW * kGeoRH - 1);
+            const int i = min(t + NT * k, kGeoRW * kGeoRH - 1);
             const int ry = i / kGeoRW, rx = i - ry * kGeoRW;
             const int x = clampi(x0 - kLMax + rx, 0, W - 1), y = clampi(y0 - kLMax + ry, 0, H - 1);
             v[k] = arms[(size_t)y * W + x];
         }
 #pragma unroll
         for (int k = 0; k < kN; ++k) {
-            const int i = t + 256 * k;
+            const int i = t + NT * k;
             if (i < kGeoRW * kGeoRH) {
                 const int ry = i / kGeoRW, rx = i - ry * kGeoRW;
                 const int x = x0 - kLMax + rx, y = y0 - kLMax + ry;
@@ -275,29 +291,72 @@ __device__ inline void geometry_tile(const uint32_t* __restrict__ arms, int W, i
         }
     }
     __syncthreads();
-    if (t < kGeoTW) {  // column prefixes of h
-        uint32_t acc = 0;
-        S.cp[0][t] = 0;
+    if constexpr (NT == 256) {
+        if (t < kGeoTW) {  // column prefixes of h
+            uint32_t acc = 0;
+            S.cp[0][t] = 0;
 #pragma unroll 10
-        for (int ry = 0; ry < kGeoRH; ++ry) {
-            acc += S.hv[ry][t + kLMax] & 0xffff;
-            S.cp[ry + 1][t] = acc;
-        }
-    } else if (t < kGeoTW + kGeoTH) {  // row prefixes of v
-        const int ty = t - kGeoTW;
-        uint32_t acc = 0;
-        S.rp[ty][0] = 0;
+            for (int ry = 0; ry < kGeoRH; ++ry) {
+                acc += S.hv[ry][t + kLMax] & 0xffff;
+                S.cp[ry + 1][t] = acc;
+            }
+        } else if (t < kGeoTW + kGeoTH) {  // row prefixes of v
+            const int ty = t - kGeoTW;
+            uint32_t acc = 0;
+            S.rp[ty][0] = 0;
 #pragma unroll 14
-        for (int rx = 0; rx < kGeoRW; ++rx) {
-            acc += S.hv[ty + kLMax][rx] >> 16;
-            S.rp[ty][rx + 1] = acc;
+            for (int rx = 0; rx < kGeoRW; ++rx) {
+                acc += S.hv[ty + kLMax][rx] >> 16;
+                S.rp[ty][rx + 1] = acc;
+            }
+        }
+    } else {
+        {   // column prefixes of h: column c = t / 16, rows 4 s .. 4 s + 3 with
+            // s = t % 16 (16 lanes = one DPP row per column)
+            const int c = t >> 4, sg = t & 15;
+            uint32_t a[4], tot = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ry = 4 * sg + i;
+                tot += ry < kGeoRH ? S.hv[ry][c + kLMax] & 0xffff : 0u;
+                a[i] = tot;
+            }
+            uint32_t inc = tot;
+            inc += dpp<0x111, 0xf>(inc);
+            inc += dpp<0x112, 0xf>(inc);
+            inc += dpp<0x114, 0xf>(inc);
+            inc += dpp<0x118, 0xf>(inc);
+            const uint32_t before = inc - tot;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ry = 4 * sg + i;
+                if (ry < kGeoRH) S.cp[ry + 1][c] = before + a[i];
+            }
+            if (sg == 0) S.cp[0][c] = 0;
+        }
+        {   // row prefixes of v: wavefront w takes row w, lane l columns 2 l, 2 l + 1
+            const int ty = t >> 6, l = t & 63;
+            const uint32_t v0 = 2 * l < kGeoRW ? S.hv[ty + kLMax][2 * l] >> 16 : 0u;
+            const uint32_t v1 = 2 * l + 1 < kGeoRW ? S.hv[ty + kLMax][2 * l + 1] >> 16 : 0u;
+            const uint32_t tot = v0 + v1;
+            uint32_t inc = tot;
+            inc += dpp<0x111, 0xf>(inc);
+            inc += dpp<0x112, 0xf>(inc);
+            inc += dpp<0x114, 0xf>(inc);
+            inc += dpp<0x118, 0xf>(inc);
+            inc += dpp<0x142, 0xa>(inc);
+            inc += dpp<0x143, 0xc>(inc);
+            const uint32_t before = inc - tot;
+            if (2 * l < kGeoRW) S.rp[ty][2 * l + 1] = before + v0;
+            if (2 * l + 1 < kGeoRW) S.rp[ty][2 * l + 2] = before + tot;
+            if (l == 0) S.rp[ty][0] = 0;
         }
     }
     __syncthreads();
     const int tx = t & 63;
     const int x = x0 + tx;
-    for (int k = 0; k < kGeoTH / 4; ++k) {
-        const int ty = (t >> 6) + 4 * k;
+    for (int k = 0; k < kGeoTH / (NT / 64); ++k) {
+        const int ty = (t >> 6) + (NT / 64) * k;
         const int y = y0 + ty;
         if (x >= W || y >= H) continue;
         // arms from census_tile never exceed kLMax; the clamp only keeps an
@@ -380,11 +439,6 @@ __device__ inline uint4 ld128(rsrc_t r, uint32_t voff, uint32_t soff) {
 // HBM and read once by WTA), so they do not evict reused inputs from L2.
 __device__ inline void st32(float v, rsrc_t r, uint32_t voff, uint32_t soff) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 2);
-}
-
-template <unsigned Ctrl, unsigned RowMask>
-__device__ inline uint32_t dpp(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, Ctrl, RowMask, 0xf, false);
 }
 
 // Inclusive prefix sums of the kSeg segments across the wavefront: DPP row

@@ -23,8 +23,9 @@ __global__ __launch_bounds__(256) void k_geometry(const uint32_t* __restrict__ a
                        S);
 }
 
-// Both views of the one-call path in one launch each (blockIdx.z = view).
-__global__ __launch_bounds__(256) void k_census_arms2(const uint8_t* __restrict__ rgbL,
+// Both views of the one-call path in one launch each (blockIdx.z = view);
+// one thread per pixel of a tile.
+__global__ __launch_bounds__(1024) void k_census_arms2(const uint8_t* __restrict__ rgbL,
                                                       const uint8_t* __restrict__ rgbR, int W,
                                                       int H, int cw, int ch, int L1, int tau1,
                                                       uint32_t* __restrict__ armsL,
@@ -33,18 +34,18 @@ __global__ __launch_bounds__(256) void k_census_arms2(const uint8_t* __restrict_
                                                       uint4* __restrict__ pixR) {
     __shared__ dco::CensusLds S;
     const bool r = blockIdx.z != 0;
-    dco::census_tile(r ? rgbR : rgbL, W, H, cw, ch, L1, tau1, nullptr, r ? armsR : armsL, nullptr,
+    dco::census_tile<1024>(r ? rgbR : rgbL, W, H, cw, ch, L1, tau1, nullptr, r ? armsR : armsL, nullptr,
                      r ? pixR : pixL, blockIdx.x * dco::kCenTW, blockIdx.y * dco::kCenTH, S);
 }
 
-__global__ __launch_bounds__(256) void k_geometry2(const uint32_t* __restrict__ armsL,
+__global__ __launch_bounds__(1024) void k_geometry2(const uint32_t* __restrict__ armsL,
                                                    const uint32_t* __restrict__ armsR, int W,
                                                    int H, int iters, AggRecords recL,
                                                    AggRecords recR, RecGeom g) {
     __shared__ dco::GeomLds S;
     const bool r = blockIdx.z != 0;
-    dco::geometry_tile(r ? armsR : armsL, W, H, iters, r ? recR : recL,
-                       blockIdx.x * dco::kGeoTW, blockIdx.y * dco::kGeoTH, S, g);
+    dco::geometry_tile<1024>(r ? armsR : armsL, W, H, iters, r ? recR : recL,
+                             blockIdx.x * dco::kGeoTW, blockIdx.y * dco::kGeoTH, S, g);
 }
 
 // Every view of a batch of pairs in one launch (blockIdx.z = 2 * pair + view),
@@ -86,10 +87,10 @@ hipError_t launch_front2(const uint8_t* rgbL, const uint8_t* rgbR, int W, int H,
                          uint4* pixL, uint4* pixR, const AggRecords& recL, const AggRecords& recR,
                          const RecGeom& g, hipStream_t st) {
     dim3 g1((W + dco::kCenTW - 1) / dco::kCenTW, (H + dco::kCenTH - 1) / dco::kCenTH, 2);
-    hipLaunchKernelGGL(k_census_arms2, g1, dim3(256), 0, st, rgbL, rgbR, W, H, cw, ch, L1, tau1,
+    hipLaunchKernelGGL(k_census_arms2, g1, dim3(1024), 0, st, rgbL, rgbR, W, H, cw, ch, L1, tau1,
                        armsL, armsR, pixL, pixR);
     dim3 g2((W + dco::kGeoTW - 1) / dco::kGeoTW, (H + dco::kGeoTH - 1) / dco::kGeoTH, 2);
-    hipLaunchKernelGGL(k_geometry2, g2, dim3(256), 0, st, armsL, armsR, W, H, iters, recL, recR,
+    hipLaunchKernelGGL(k_geometry2, g2, dim3(1024), 0, st, armsL, armsR, W, H, iters, recL, recR,
                        g);
     return hipGetLastError();
 }
