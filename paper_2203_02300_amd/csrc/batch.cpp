@@ -75,9 +75,9 @@ dco_status alloc_pair(dco_batch* b, BatchPair& pr, int W, int H, int D) {
     return DCO_OK;
 }
 
-// Stage-ordered work list.  Stage 2 keeps pair, view, strip, band,
-// disparity order (no sort by length: neighbouring items share inputs) and
-// is cut into kXcds contiguous parts of about equal cost.
+// Stage-ordered work list.  Stage 2 is built in pair, view, strip, band,
+// disparity order (neighbouring items share inputs), cut into kXcds
+// contiguous parts of about equal cost, and each part ordered longest first.
 std::vector<BatchItem> make_items(std::vector<BatchPair>& pairs, int* xsplit) {
     std::vector<BatchItem> st[kBatchStages];
     for (int i = 0; i < (int)pairs.size(); ++i) {
@@ -124,6 +124,13 @@ std::vector<BatchItem> make_items(std::vector<BatchPair>& pairs, int* xsplit) {
         while (x < kXcds && acc * kXcds >= total * x) xsplit[x++] = s2 + (int)k + 1;
     }
     while (x <= kXcds) xsplit[x++] = s2 + (int)st[2].size();
+    // within each XCD's part, longest items first (stable, so the items of
+    // one strip and band keep their neighbouring disparities together): the
+    // part's last round then holds its shortest items instead of leaving
+    // resident slots idle behind a long one
+    for (int k = 0; k < kXcds; ++k)
+        std::stable_sort(st[2].begin() + (xsplit[k] - s2), st[2].begin() + (xsplit[k + 1] - s2),
+                         [&](const BatchItem& a, const BatchItem& b) { return cost(a) > cost(b); });
     std::vector<BatchItem> all;
     for (auto& s : st) all.insert(all.end(), s.begin(), s.end());
     return all;
@@ -288,20 +295,19 @@ void write_cache(const std::map<std::string, Tile>& m) {
     fclose(f);
 }
 
-// Row bands and disparity chunks to time.  With two aggregation stages the
-// kernel takes two disparities per pass, so chunks are even (a range of one
-// disparity keeps a chunk of one).
+// Disparity chunks to time, with full-height bands.  A batch fills the GPU
+// with items already, and every band of a split would start 2 L1 + 1 rows
+// early: on the 32-pair workload, tiles with bands of H / 2 chosen on copies
+// of one size class made the batch 3 % slower than full-height items.  With
+// two aggregation stages the kernel takes two disparities per pass, so
+// chunks are even (a range of one disparity keeps a chunk of one).
 std::vector<Tile> candidates(int H, int D, int iters) {
     std::vector<Tile> out;
-    const int bands[] = {H, 256, 128};
     const int chunks1[] = {1, 2, 4}, chunks2[] = {2, 4, 8};
     const int* chunks = iters == 2 ? chunks2 : chunks1;
-    for (int band : bands) {
-        if (band > H || (band != H && band * 2 > H)) continue;
-        for (int k = 0; k < 3; ++k) {
-            const int dc = chunks[k];
-            if (dc <= D || (k == 0 && D < dc)) out.push_back(Tile{band, std::min(dc, D)});
-        }
+    for (int k = 0; k < 3; ++k) {
+        const int dc = chunks[k];
+        if (dc <= D || (k == 0 && D < dc)) out.push_back(Tile{H, std::min(dc, D)});
     }
     return out;
 }

@@ -3,13 +3,13 @@
 //
 // The host builds a work list ordered by stage (0 census + arms of a 64 x 64
 // block, 1 region counts and records of a 64 x 64 block, 2 cost +
-// aggregation of d-chunk x column strip x row band, in pair, view, strip,
-// band, disparity order and cut into one contiguous part per XCD, 3 WTA of
-// a pixel block, 4 LR check of a row block) over every pair of the batch.
-// The kernel of stage s runs a grid sized to the GPU's resident capacity; its
-// workgroup w takes the stage's items w, w + G, w + 2G, ...  The kernel
-// boundary is the barrier between stages, so workgroups never wait on each
-// other and need no atomics.
+// aggregation of d-chunk x column strip x row band, cut into one contiguous
+// part per XCD and ordered longest first within it, 3 WTA of a pixel block,
+// 4 LR check of a row block) over every pair of the batch.  The kernels of
+// stages 0, 1, 3 and 4 run a grid sized to the GPU's resident capacity;
+// workgroup w takes the stage's items w, w + G, w + 2G, ...  Stage 2 runs one
+// workgroup per item.  The kernel boundary is the barrier between stages, so
+// workgroups never wait on each other and need no atomics.
 //
 // Each stage runs the same device function as the one-call matcher
 // (dco_device.h), so per-pair results are bit-identical to dco_stereo_match.
@@ -58,13 +58,43 @@ __global__ __launch_bounds__(dco::kWsThreads, 1) void k_batch_agg_ws(BatchArgs B
     }
 }
 
-// LDS of each stage kernel: census tiles, aggregation rings, or none.
+// Stages 0 and 1 with one thread per pixel of a tile (1024 threads), the
+// same tiles as the one-call front end: census + arms + packed pixels, then
+// region counts and records, of 64 x 64 blocks; persistent over the items.
 template <int ITERS, int STAGE>
-using StageLds = typename std::conditional<
-    STAGE == 0, dco::CensusLds,
-    typename std::conditional<
-        STAGE == 1, dco::GeomLds,
-        typename std::conditional<STAGE == 2, dco::AggLds<ITERS, true>, NoLds>::type>::type>::type;
+__global__ __launch_bounds__(1024) void k_batch_front(BatchArgs B, int first, int count) {
+    __shared__ typename std::conditional<STAGE == 0, dco::CensusLds, dco::GeomLds>::type S;
+    for (int k = blockIdx.x; k < count; k += gridDim.x) {
+        const BatchItem I = B.items[first + k];
+        const BatchPair& pr = B.pairs[I.pair];
+        const int W = pr.W, H = pr.H;
+        if constexpr (STAGE == 0) {
+            const uint8_t* img = I.view == 0 ? B.io[I.pair].L : B.io[I.pair].R;
+            for (int r = 0; r < 64 / dco::kCenTH; ++r) {
+                const int y0 = I.b * 64 + r * dco::kCenTH;
+                if (y0 >= H) break;
+                dco::census_tile<1024>(img, W, H, B.cw, B.ch, B.L1, B.tau1, nullptr,
+                                       pr.arms[I.view], nullptr, pr.pix[I.view],
+                                       I.a * dco::kCenTW, y0, S);
+                __syncthreads();
+            }
+        } else {
+            for (int r = 0; r < 64 / dco::kGeoTH; ++r) {
+                const int y0 = I.b * 64 + r * dco::kGeoTH;
+                if (y0 >= H) break;
+                dco::geometry_tile<1024>(pr.arms[I.view], W, H, ITERS, pr.rec[I.view],
+                                         I.a * dco::kGeoTW, y0, S,
+                                         ITERS == 2 ? dco::kRecWs : dco::kRecPlain);
+                __syncthreads();
+            }
+        }
+    }
+}
+
+// LDS of stages 2 (one aggregation stage), 3 and 4: aggregation rings or none.
+template <int ITERS, int STAGE>
+using StageLds =
+    typename std::conditional<STAGE == 2, dco::AggLds<ITERS, true>, NoLds>::type;
 
 template <int ITERS, int STAGE>
 __global__ __launch_bounds__(256, 2) void k_batch_stage(BatchArgs B, int first, int count) {
@@ -86,24 +116,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BatchArgs B, int first, 
         const BatchPair& pr = B.pairs[I.pair];
         const BatchIO& io = B.io[I.pair];
         const int W = pr.W, H = pr.H;
-        if constexpr (STAGE == 0) {  // census + arms + packed RGB of a 64 x 64 block of one view
-            const uint8_t* img = I.view == 0 ? io.L : io.R;
-            for (int r = 0; r < 4; ++r) {
-                const int y0 = I.b * 64 + r * dco::kCenTH;
-                if (y0 >= H) break;
-                dco::census_tile(img, W, H, B.cw, B.ch, B.L1, B.tau1, nullptr, pr.arms[I.view],
-                                 nullptr, pr.pix[I.view], I.a * dco::kCenTW, y0, S);
-                __syncthreads();
-            }
-        } else if constexpr (STAGE == 1) {  // region counts and records of a 64 x 64 block
-            for (int r = 0; r < 64 / dco::kGeoTH; ++r) {
-                const int y0 = I.b * 64 + r * dco::kGeoTH;
-                if (y0 >= H) break;
-                dco::geometry_tile(pr.arms[I.view], W, H, ITERS, pr.rec[I.view], I.a * dco::kGeoTW,
-                                   y0, S, ITERS == 2 ? dco::kRecWs : dco::kRecPlain);
-                __syncthreads();
-            }
-        } else if constexpr (STAGE == 2) {  // slices a .. a+dchunk-1, strip b, row band c
+        if constexpr (STAGE == 2) {  // slices a .. a+dchunk-1, strip b, row band c
             dco::AggArgs A{};
             A.pixL = pr.pix[0];
             A.pixR = pr.pix[1];
@@ -163,9 +176,9 @@ int stage_blocks_per_cu() {
 
 template <int ITERS>
 hipError_t launch_all(const BatchArgs& a, const int* first, const int* grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_batch_stage<ITERS, 0>), dim3(grid[0]), dim3(256), 0, st, a, first[0],
+    hipLaunchKernelGGL((k_batch_front<ITERS, 0>), dim3(grid[0]), dim3(1024), 0, st, a, first[0],
                        first[1] - first[0]);
-    hipLaunchKernelGGL((k_batch_stage<ITERS, 1>), dim3(grid[1]), dim3(256), 0, st, a, first[1],
+    hipLaunchKernelGGL((k_batch_front<ITERS, 1>), dim3(grid[1]), dim3(1024), 0, st, a, first[1],
                        first[2] - first[1]);
     if constexpr (ITERS == 2)
         hipLaunchKernelGGL(k_batch_agg_ws, dim3(grid[2]), dim3(dco::kWsThreads), 0, st, a,
@@ -182,8 +195,12 @@ hipError_t launch_all(const BatchArgs& a, const int* first, const int* grid, hip
 
 template <int ITERS>
 void blocks_per_cu(int* per_stage) {
-    per_stage[0] = stage_blocks_per_cu<ITERS, 0>();
-    per_stage[1] = stage_blocks_per_cu<ITERS, 1>();
+    for (int k = 0; k < 2; ++k) {
+        int nb = 0;
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, k ? k_batch_front<ITERS, 1> : k_batch_front<ITERS, 0>, 1024, 0);
+        per_stage[k] = e == hipSuccess && nb > 0 ? nb : 1;
+    }
     if constexpr (ITERS == 2) {
         int nb = 0;
         const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
