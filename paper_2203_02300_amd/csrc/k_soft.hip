@@ -461,96 +461,182 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_seed_adj(
 // columns per workgroup, rows in batches of kSoftPre.  FP64 running sums in an
 // LDS ring of kSoftRing rows per column keep every range sum exact to FP32
 // rounding of the final value, and each thread touches only its own column,
-// so the result does not depend on scheduling.  The ring keeps kSoftPre - 1
-// rows more than a range needs, so a batch's ring writes can all go before its
-// ring reads: one LDS round trip per batch instead of one per row.
+// so the result does not depend on scheduling.  A batch makes all its ring
+// writes before its ring reads: one LDS round trip per batch, not per row.
+//
+// The ring (20 KB per workgroup) bounds a CU to eight such workgroups, so
+// the loads of one wavefront have to cover the memory latency by themselves:
+// each thread keeps kSoftDepth batches of inputs in registers and loads
+// kSoftDepth - 1 batches ahead of the one it processes.  The row loop is
+// unrolled over one turn of the ring (kSoftTurn batches), so every ring slot
+// and every buffer index is a compile-time constant: slots are immediate LDS
+// offsets, and the wrap of a per-pixel range end around the ring is tested
+// only in the batches where it can happen.  The loop body has no branch:
+// loads read clamped rows, stores of rows outside the image get an
+// out-of-range buffer offset (the hardware drops them), and the row count is
+// rounded up to whole turns.
 constexpr int kSoftCols = 64;
-constexpr int kSoftPre = 8;                          // rows per batch
-constexpr int kSoftRing = 2 * kLMax + 1 + kSoftPre;  // 43
+constexpr int kSoftPre = 5;                       // rows per batch
+constexpr int kSoftRing = 2 * kLMax + 1 + kSoftPre;  // 40 rows
+constexpr int kSoftTurn = kSoftRing / kSoftPre;   // batches per turn of the ring
+constexpr int kSoftDepth = 4;                     // batches held per thread
+constexpr int kSoftLead = (kSoftDepth - 1) * kSoftPre;  // rows streamed before row 0
+constexpr uint32_t kSoftDrop = 0x80000000u;       // buffer offset past any plane (W H <= 2^27)
+static_assert(kSoftRing % kSoftPre == 0 && kSoftTurn % kSoftDepth == 0,
+              "a turn of the ring is a whole number of batches and of buffer rotations");
+static_assert(kSoftLead < kSoftRing, "the lead-in rows fit in the ring");
 
-// kSoftPre rows of a column pass's per-row inputs, loaded one batch ahead of
-// the rows being processed (clamped rows: every load is unconditional).
+// kSoftPre rows of a column pass's per-row inputs.
 struct ColBatch {
     float v[kSoftPre];     // input of row y
     uint32_t a[kSoftPre];  // arms of row y (adjoint) or of row y - kLMax (forward)
     float s[kSoftPre];     // scale of row y - kLMax
 };
 
+// Per-column state of a column pass: buffer resources over one plane of the
+// input, output, arms and scale, and the running state.
+struct ColPass {
+    double (*ring)[kSoftCols];  // the workgroup's LDS ring
+    __amdgpu_buffer_rsrc_t src, arms, sc, dst;
+    uint32_t x4, W4;  // byte offset of the (clamped) column, bytes per row
+    int t, H, rows;
+    bool ok;
+    double acc;  // running prefix (forward) or running sum of differences (adjoint)
+};
+
 template <bool kScale, bool kAdj>
-__device__ inline void col_load(const float* src, const uint32_t* arms, const float* sc, int W,
-                                int H, int y0, ColBatch& c) {
+__device__ inline void col_load(const ColPass& c, int y0, ColBatch& b) {
 #pragma unroll
     for (int k = 0; k < kSoftPre; ++k) {
         const int y = y0 + k, yo = y - kLMax;
-        const size_t yq = (size_t)min(y, H - 1), oq = (size_t)min(max(yo, 0), H - 1);
-        c.v[k] = src[yq * W];
-        c.a[k] = arms[(kAdj ? yq : oq) * W];
-        c.s[k] = kScale ? sc[oq * W] : 1.0f;
+        const uint32_t yq = (uint32_t)min(y, c.H - 1);  // y >= 0
+        const uint32_t oq = (uint32_t)min(max(yo, 0), c.H - 1);
+        b.v[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(c.src, c.x4,
+                                                                                 yq * c.W4, 0));
+        b.a[k] = __builtin_amdgcn_raw_buffer_load_b32(c.arms, c.x4, (kAdj ? yq : oq) * c.W4, 0);
+        b.s[k] = kScale ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                        c.sc, c.x4, oq * c.W4, 0))
+                        : 1.0f;
     }
 }
 
-// Ring slot `back` rows before slot s (0 <= back < kSoftRing).
-__device__ inline int ring_back(int s, int back) {
-    const int r = s - back;
-    return r < 0 ? r + kSoftRing : r;
+// Stores r as row yo of the column; dropped for rows outside the image and
+// for lanes past the last column.
+__device__ inline void col_store(const ColPass& c, int yo, float r) {
+    const bool in = c.ok && yo >= 0 && yo < c.H;
+    const uint32_t off = in ? (uint32_t)yo * c.W4 + c.x4 : kSoftDrop;
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, r), c.dst, off, 0, 0);
 }
-__device__ inline int ring_fwd(int s, int fwd) {
-    const int r = s + fwd;
-    return r >= kSoftRing ? r - kSoftRing : r;
+
+// Ring slot `base + v` and `base - v` (mod kSoftRing) for a compile-time
+// base in [0, kSoftRing) and a per-pixel 0 <= v <= kLMax + 1 (arm lengths
+// never exceed kLMax): the wrap test folds away where it cannot happen.
+__device__ inline int ring_up(int base, int v) {
+    const int r = base + v;
+    return base + kLMax + 1 < kSoftRing ? r : (r >= kSoftRing ? r - kSoftRing : r);
+}
+__device__ inline int ring_down(int base, int v) {
+    const int r = base - v;
+    return base >= kLMax + 1 ? r : (r < 0 ? r + kSoftRing : r);
+}
+constexpr int ring_mod(int s) { return ((s % kSoftRing) + kSoftRing) % kSoftRing; }
+
+template <bool kScale>
+__device__ inline ColPass col_setup(const SoftGeom& g, const float* in, const float* scale,
+                                    float* out, double (*ring)[kSoftCols]) {
+    ColPass c;
+    c.t = threadIdx.x;
+    const int x = blockIdx.x * kSoftCols + c.t;
+    const int bd = blockIdx.y, b = bd / g.D;
+    c.ok = x < g.W;
+    const size_t P = (size_t)g.W * g.H;
+    const int bytes = (int)(P * 4);
+    c.src = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(in + (size_t)bd * P), (short)0,
+                                              bytes, 0x00020000);
+    c.arms = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(g.arms + (size_t)b * P),
+                                               (short)0, bytes, 0x00020000);
+    c.sc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>((kScale ? scale : in) + (size_t)b * P), (short)0, bytes, 0x00020000);
+    c.dst = __builtin_amdgcn_make_buffer_rsrc(out + (size_t)bd * P, (short)0, bytes, 0x00020000);
+    c.x4 = 4u * (uint32_t)(c.ok ? x : 0);
+    c.W4 = 4u * (uint32_t)g.W;
+    c.ring = ring;
+    c.H = g.H;
+    c.rows = g.H + kLMax;
+    c.acc = 0.0;
+    return c;
+}
+
+// Streams the column through `step(c, batch, y0, s0)`: rows y0 .. y0 +
+// kSoftPre - 1, whose first row sits in ring slot s0 (a compile-time
+// constant once unrolled).  The stream starts kSoftLead rows before row 0
+// on zeroed buffers, so the loop needs no prologue of loads (whose registers
+// the compiler would copy, and wait for, at the loop's entry); those rows
+// add zero and store nothing, and row 0 sits in slot 0.
+template <bool kScale, bool kAdj, typename Step>
+__device__ inline void col_stream(ColPass& c, Step step) {
+    ColBatch buf[kSoftDepth];
+#pragma unroll
+    for (int j = 0; j < kSoftDepth; ++j)
+#pragma unroll
+        for (int k = 0; k < kSoftPre; ++k) {
+            buf[j].v[k] = 0.0f;
+            buf[j].a[k] = 0u;
+            buf[j].s[k] = 1.0f;
+        }
+    for (int y0 = -kSoftLead; y0 < c.rows; y0 += kSoftRing) {
+#pragma unroll
+        for (int j = 0; j < kSoftTurn; ++j) {
+            const int yb = y0 + j * kSoftPre;
+            col_load<kScale, kAdj>(c, yb + kSoftLead, buf[(j + kSoftDepth - 1) % kSoftDepth]);
+            ColBatch& cur = buf[j % kSoftDepth];
+            // The batch's values are used from here on: without this pin the
+            // compiler starts converting a later batch early, which waits for
+            // loads that should still be in flight.
+#pragma unroll
+            for (int k = 0; k < kSoftPre; ++k) {
+                asm volatile("" : "+v"(cur.v[k]), "+v"(cur.a[k]));
+                if (kScale) asm volatile("" : "+v"(cur.s[k]));
+            }
+            step(c, cur, yb, ring_mod(j * kSoftPre - kSoftLead));
+        }
+    }
 }
 
 // out(y) = (sum of in over the vertical range of pixel y) [/ scale(y)], with
-// the running column prefix P: out(y) = P(y + dn) - P(y - u - 1).  Row y of a
-// batch reads prefixes back to row y - 2 kLMax - 1; the batch's writes reach
-// row y0 + kSoftPre - 1, whose slot last held row y0 + kSoftPre - 1 - kSoftRing
-// = y0 - 2 kLMax - 2: older than any row the batch reads.
+// the running column prefix P: out(y) = P(y + dn) - P(y - u - 1).  The batch
+// of rows y0 .. y0 + kSoftPre - 1 (outputs kLMax rows behind) reads prefixes
+// from row y0 - 2 kLMax - 1 on; its writes land in the slots of rows
+// y0 - kSoftRing ... y0 + kSoftPre - 1 - kSoftRing, which are older.  The
+// lead-in rows hold P = 0, which is the prefix before row 0 (read as row -1
+// by a range that starts at row 0); rows past the image only feed outputs
+// that are dropped.
 template <bool kScale>
 __global__ __launch_bounds__(kSoftCols) void k_soft_vs(SoftGeom g, const float* __restrict__ in,
                                                        const float* __restrict__ scale,
                                                        float* __restrict__ out) {
     __shared__ double ring[kSoftRing][kSoftCols];
-    const int t = threadIdx.x, x = blockIdx.x * kSoftCols + t;
-    const int bd = blockIdx.y, b = bd / g.D;
-    const bool ok = x < g.W;
-    const int xc = ok ? x : 0;
-    const size_t P = (size_t)g.W * g.H;
-    const float* src = in + (size_t)bd * P + xc;
-    const uint32_t* arms = g.arms + (size_t)b * P + xc;
-    const float* sc = (kScale ? scale : in) + (size_t)b * P + xc;
-    float* dst = out + (size_t)bd * P + xc;
-    const int rows = g.H + kLMax;
-    double acc = 0.0;
-    int slot = 0;  // ring slot of row y0 (y0 mod kSoftRing)
-    ColBatch cur, nxt;
-    col_load<kScale, false>(src, arms, sc, g.W, g.H, 0, cur);
-    for (int y0 = 0; y0 < rows; y0 += kSoftPre) {
-        if (y0 + kSoftPre < rows)  // uniform: the next batch is in flight meanwhile
-            col_load<kScale, false>(src, arms, sc, g.W, g.H, y0 + kSoftPre, nxt);
+    ColPass c = col_setup<kScale>(g, in, scale, out, ring);
+    col_stream<kScale, false>(c, [](ColPass& c, const ColBatch& cur, int y0, int s0) {
+        const int t = c.t;
 #pragma unroll
         for (int k = 0; k < kSoftPre; ++k) {
-            acc += y0 + k < g.H ? (double)cur.v[k] : 0.0;
-            ring[ring_fwd(slot, k)][t] = acc;
+            c.acc += (double)cur.v[k];
+            c.ring[ring_mod(s0 + k)][t] = c.acc;
         }
-        // Rows whose output row yo is outside [0, H) read slots not yet (or
-        // no longer) meaningful; their results are discarded.
         double hi[kSoftPre], lo[kSoftPre];
 #pragma unroll
         for (int k = 0; k < kSoftPre; ++k) {
             const int u = arm(cur.a[k], 2), dn = arm(cur.a[k], 3);
-            const int sk = ring_fwd(slot, k);
-            hi[k] = ring[ring_back(sk, kLMax - dn)][t];
-            lo[k] = ring[ring_back(sk, kLMax + u + 1)][t];
+            hi[k] = c.ring[ring_up(ring_mod(s0 + k - kLMax), dn)][t];
+            lo[k] = c.ring[ring_down(ring_mod(s0 + k - kLMax - 1), u)][t];
         }
 #pragma unroll
         for (int k = 0; k < kSoftPre; ++k) {
-            const int yo = y0 + k - kLMax;
-            const int u = arm(cur.a[k], 2);
-            const float r = (float)(hi[k] - (yo - u - 1 >= 0 ? lo[k] : 0.0));
-            if (ok && yo >= 0 && yo < g.H) dst[(size_t)yo * g.W] = kScale ? r / cur.s[k] : r;
+            const float r = (float)(hi[k] - lo[k]);
+            col_store(c, y0 + k - kLMax, kScale ? r / cur.s[k] : r);
         }
-        slot = ring_fwd(slot, kSoftPre);
-        cur = nxt;
-    }
+    });
 }
 
 // Adjoint of k_soft_vs: out(y') = sum over pixels y whose vertical range
@@ -558,64 +644,45 @@ __global__ __launch_bounds__(kSoftCols) void k_soft_vs(SoftGeom g, const float* 
 // subtracts it after row y + dn in a ring of differences (LDS FP64 adds that
 // return nothing, in program order per column); row y' is final kLMax rows
 // later and its running sum is the output.  A batch first makes all its
-// adds, then finishes its rows y0 - kLMax ... y0 + kSoftPre - 1 - kLMax: the
-// adds of a later row of the batch start at or after the row it finishes next
-// and end at most kSoftRing - 1 rows after it, so none lands in a slot that
-// is still to be read as that row.
+// adds, into rows y0 - kLMax ... y0 + kSoftPre + kLMax, then finishes (reads
+// and clears) rows y0 - kLMax ... y0 + kSoftPre - 1 - kLMax: that span is
+// kSoftRing rows, so no add lands in the slot of a row still to be finished,
+// and every slot it lands in was cleared when its previous row finished.
+// Rows outside the image add zero.
 template <bool kScale>
 __global__ __launch_bounds__(kSoftCols) void k_soft_vsa(SoftGeom g, const float* __restrict__ in,
                                                         const float* __restrict__ scale,
                                                         float* __restrict__ out) {
     __shared__ double ring[kSoftRing][kSoftCols];
-    const int t = threadIdx.x, x = blockIdx.x * kSoftCols + t;
-    const int bd = blockIdx.y, b = bd / g.D;
-    const bool ok = x < g.W;
-    const int xc = ok ? x : 0;
-    const size_t P = (size_t)g.W * g.H;
-    const float* src = in + (size_t)bd * P + xc;
-    const uint32_t* arms = g.arms + (size_t)b * P + xc;
-    const float* sc = (kScale ? scale : in) + (size_t)b * P + xc;
-    float* dst = out + (size_t)bd * P + xc;
-    for (int i = 0; i < kSoftRing; ++i) ring[i][t] = 0.0;
-    const int rows = g.H + kLMax;
-    double run = 0.0;
-    int slot = 0;  // ring slot of row y0
-    ColBatch cur, nxt;
-    col_load<kScale, true>(src, arms, sc, g.W, g.H, 0, cur);
-    for (int y0 = 0; y0 < rows; y0 += kSoftPre) {
-        if (y0 + kSoftPre < rows)  // uniform: the next batch is in flight meanwhile
-            col_load<kScale, true>(src, arms, sc, g.W, g.H, y0 + kSoftPre, nxt);
+    ColPass c = col_setup<kScale>(g, in, scale, out, ring);
+    for (int i = 0; i < kSoftRing; ++i) ring[i][c.t] = 0.0;
+    col_stream<kScale, true>(c, [](ColPass& c, const ColBatch& cur, int y0, int s0) {
+        const int t = c.t;
 #pragma unroll
         for (int k = 0; k < kSoftPre; ++k) {
-            if (y0 + k < g.H) {  // uniform
-                const int u = arm(cur.a[k], 2), dn = arm(cur.a[k], 3);
-                const int sk = ring_fwd(slot, k);
-                const double v = (double)cur.v[k];
-                __hip_atomic_fetch_add(&ring[ring_back(sk, u)][t], v, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-                __hip_atomic_fetch_add(&ring[ring_fwd(sk, dn + 1)][t], -v, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
+            const int u = arm(cur.a[k], 2), dn = arm(cur.a[k], 3);
+            const float vf = (unsigned)(y0 + k) < (unsigned)c.H ? cur.v[k] : 0.0f;
+            const double v = (double)vf;
+            __hip_atomic_fetch_add(&c.ring[ring_down(ring_mod(s0 + k), u)][t], v,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(&c.ring[ring_up(ring_mod(s0 + k + 1), dn)][t], -v,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         double dv[kSoftPre];
 #pragma unroll
-        for (int k = 0; k < kSoftPre; ++k) {
-            const int so = ring_back(ring_fwd(slot, k), kLMax);
-            dv[k] = __hip_atomic_exchange(&ring[so][t], 0.0, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
+        for (int k = 0; k < kSoftPre; ++k)
+            dv[k] = __hip_atomic_exchange(&c.ring[ring_mod(s0 + k - kLMax)][t], 0.0,
+                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        // all the batch's exchanges in flight together (one LDS round trip)
+#pragma unroll
+        for (int k = 0; k < kSoftPre; ++k) asm volatile("" : "+v"(dv[k]));
 #pragma unroll
         for (int k = 0; k < kSoftPre; ++k) {
-            const int yo = y0 + k - kLMax;
-            if (yo >= 0) {  // uniform: row yo is final
-                run += dv[k];
-                if (ok && yo < g.H)
-                    dst[(size_t)yo * g.W] = kScale ? (float)run / cur.s[k] : (float)run;
-            }
+            c.acc += dv[k];
+            const float r = (float)c.acc;
+            col_store(c, y0 + k - kLMax, kScale ? r / cur.s[k] : r);
         }
-        slot = ring_fwd(slot, kSoftPre);
-        cur = nxt;
-    }
+    });
 }
 
 
