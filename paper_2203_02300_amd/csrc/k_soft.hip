@@ -143,18 +143,20 @@ __device__ inline void cost_px(uint4 a, uint4 b, bool inside, const float* tab, 
 
 // Row passes: one wavefront per image row, kRowWaves wavefronts per
 // workgroup, each with its own LDS slice (no workgroup barriers after the
-// table load) and kRowsPerWave rows in turn.  Row ids run over (b, d, y)
-// with y fastest.  Lane `lane` handles columns lane + 64 k; loads are issued
+// table load) and kRowsPerWave rows in turn.  Row ids run over (b, y, d)
+// with d fastest, so the rows that run together share one image row (its
+// pixels, arms and counts stay in cache across the disparities).  Outside the prefix phase (which has its own layout, see
+// prefix_row) lane `lane` handles columns lane + 64 k; loads are issued
 // kRowBatch columns at a time with clamped (always valid) addresses.
 constexpr int kRowWaves = 4;
 constexpr int kRowsPerWave = 4;
 constexpr int kRowBatch = 8;
 
 __device__ inline void row_of(int rid, int D, int H, int& b, int& d, int& y) {
-    y = rid % H;
-    const int bd = rid / H;
-    d = bd % D;
-    b = bd / D;
+    d = rid % D;
+    const int by = rid / D;
+    y = by % H;
+    b = by / H;
 }
 
 template <unsigned Ctrl, unsigned RowMask>
@@ -186,66 +188,112 @@ __device__ inline double wave_scan_f64(double v) {
     return v;
 }
 
+// The prefix phase of a row pass works on 256-column chunks in which lane
+// `lane` owns the four consecutive columns x0 + 4 lane .. x0 + 4 lane + 3:
+// a lane prefixes its four values in FP64, one wavefront scan over the lane
+// totals places them, so a chunk costs one FP64 scan per four columns instead
+// of one per column.
+constexpr int kPreChunk = 256;
+
+// Writes P[x + k + 1] (x = the lane's first column, k < 4, x + k < W) for one
+// chunk from the lane's four values (zero past the row's end), given the
+// row's sum before the chunk; returns the row's sum up to the chunk's end.
+__device__ inline double chunk_prefix(const float (&v)[4], int x, int W, double carry, double* P) {
+    double s[4];
+    s[0] = (double)v[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) s[k] = s[k - 1] + (double)v[k];
+    const double inc = wave_scan_f64(s[3]);
+    const double base = carry + (inc - s[3]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (x + k < W) P[x + k + 1] = base + s[k];
+    return carry + readlane_f64(inc, 63);
+}
+
+// Moves the chunk's values c (lane `lane` holding columns x0 + 64 j + lane)
+// through the wavefront's LDS stage into the four-consecutive-columns layout.
+__device__ inline void restage(const float (&c)[4], float* stage, float (&v)[4]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) stage[64 * j + lane] = c[j];
+    __builtin_amdgcn_wave_barrier();
+    const float4 q = *reinterpret_cast<const float4*>(stage + 4 * lane);
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+    __builtin_amdgcn_wave_barrier();  // the stage is rewritten next
+}
+
 // FP64 prefixes of the wavefront's row (W <= 2048): P[0] = 0 and
 // P[x + 1] = v(0) + ... + v(x), where v is (kCost) the raw cost of Eq. 1 of
 // row y for disparity d, or (kDeriv) its lambda_AD derivative, with the
-// lambda_census derivative prefixed into P2, or else the row of `src`.  The
-// columns go in 64-wide chunks: a wavefront scan per chunk plus the total of
-// the chunks before it; fixed order, bit-reproducible.
+// lambda_census derivative prefixed into P2, or else the row of `src`.  Raw
+// costs are computed with lane `lane` on columns x0 + 64 j + lane (coalesced
+// pixel loads) and restaged through `stage` (kPreChunk floats); `src` is read
+// directly in the four-column layout.  Fixed order, bit-reproducible.
 template <bool kCost, bool kDeriv>
 __device__ inline void prefix_row(const uint4* pl, const uint4* pr, const float* src, int W, int d,
-                                  const float* tab, double* P, double* P2) {
+                                  const float* tab, float* stage, double* P, double* P2) {
     const int lane = threadIdx.x & 63;
     double carry = 0.0, carry2 = 0.0;
     if (lane == 0) {
         P[0] = 0.0;
         if (kDeriv) P2[0] = 0.0;
     }
-    for (int x0 = 0; x0 < W; x0 += 64 * kRowBatch) {
-        float v[kRowBatch], v2[kRowBatch];
+    const bool vec = (W & 3) == 0;  // 16-byte aligned rows
+    for (int x0 = 0; x0 < W; x0 += kPreChunk) {
+        const int x = x0 + 4 * lane;
+        float v[4], v2[4];
         if (kCost) {
-            uint4 a[kRowBatch], b[kRowBatch];
+            uint4 a[4], b[4];
 #pragma unroll
-            for (int j = 0; j < kRowBatch; ++j) {
+            for (int j = 0; j < 4; ++j) {
                 const int xc = min(x0 + 64 * j + lane, W - 1);
                 a[j] = pl[xc];
                 b[j] = pr[max(xc - d, 0)];
             }
+            float c[4], c2[4];
 #pragma unroll
-            for (int j = 0; j < kRowBatch; ++j) {
-                const int x = x0 + 64 * j + lane;
-                float c, dca, dcc;
-                cost_px<kDeriv>(a[j], b[j], x - d >= 0, tab, c, dca, dcc);
-                v[j] = kDeriv ? dca : c;
-                v2[j] = dcc;
+            for (int j = 0; j < 4; ++j) {
+                float cv, dca, dcc;
+                cost_px<kDeriv>(a[j], b[j], x0 + 64 * j + lane - d >= 0, tab, cv, dca, dcc);
+                c[j] = kDeriv ? dca : cv;
+                c2[j] = dcc;
             }
+            restage(c, stage, v);
+            if (kDeriv) restage(c2, stage, v2);
+        } else if (vec) {
+            const float4 q = *reinterpret_cast<const float4*>(src + min(x, W - 4));
+            v[0] = q.x;
+            v[1] = q.y;
+            v[2] = q.z;
+            v[3] = q.w;
         } else {
 #pragma unroll
-            for (int j = 0; j < kRowBatch; ++j) v[j] = src[min(x0 + 64 * j + lane, W - 1)];
+            for (int k = 0; k < 4; ++k) v[k] = src[min(x + k, W - 1)];
         }
 #pragma unroll
-        for (int j = 0; j < kRowBatch; ++j) {
-            if (x0 + 64 * j >= W) break;  // uniform
-            const int x = x0 + 64 * j + lane;
-            const double inc = wave_scan_f64(x < W ? (double)v[j] : 0.0);
-            if (x < W) P[x + 1] = carry + inc;
-            carry += readlane_f64(inc, 63);
-            if (kDeriv) {
-                const double inc2 = wave_scan_f64(x < W ? (double)v2[j] : 0.0);
-                if (x < W) P2[x + 1] = carry2 + inc2;
-                carry2 += readlane_f64(inc2, 63);
-            }
+        for (int k = 0; k < 4; ++k) {
+            v[k] = x + k < W ? v[k] : 0.0f;
+            if (kDeriv) v2[k] = x + k < W ? v2[k] : 0.0f;
         }
+        carry = chunk_prefix(v, x, W, carry, P);
+        if (kDeriv) carry2 = chunk_prefix(v2, x, W, carry2, P2);
     }
     __builtin_amdgcn_wave_barrier();
 }
 
-// Bytes of dynamic LDS per wavefront: forward (one FP64 prefix), gradient
-// (two) and adjoint (64-bit difference array, the row, its arms).
+// Bytes of dynamic LDS per wavefront: forward (one FP64 prefix, and the
+// stage when it computes raw costs), gradient (two and the stage) and
+// adjoint (64-bit difference array, the row, its arms).
 __host__ __device__ inline size_t row_bytes(int W) { return ((size_t)W * 4 + 15) / 16 * 16; }
 __host__ __device__ inline size_t prefix_bytes(int W) { return ((size_t)(W + 1) * 8 + 15) / 16 * 16; }
+constexpr size_t kStageBytes = kPreChunk * sizeof(float);
 inline size_t row_lds_fwd(int W) { return prefix_bytes(W); }
-inline size_t row_lds_grad(int W) { return 2 * prefix_bytes(W); }
+inline size_t row_lds_cost(int W) { return prefix_bytes(W) + kStageBytes; }
+inline size_t row_lds_grad(int W) { return 2 * prefix_bytes(W) + kStageBytes; }
 inline size_t row_lds_adj(int W) {
     return ((size_t)(W + 1) * 8 + 15) / 16 * 16 + row_bytes(W) + ((size_t)W * 2 + 15) / 16 * 16;
 }
@@ -271,6 +319,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hrow(SoftGeom g, SoftIm
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, W = g.W;
     float* tab = reinterpret_cast<float*>(dyn);
     double* Pf = reinterpret_cast<double*>(dyn + (kCost ? kTabLds : 0) + w * lds_wave);
+    float* stage = reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(Pf) + prefix_bytes(W));
     if (kCost) load_tables(im, tab);
     const size_t P = (size_t)W * g.H;
     const int nrows = g.B * g.D * g.H;
@@ -280,7 +329,8 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hrow(SoftGeom g, SoftIm
         row_of(rid, g.D, g.H, b, d, y);
         const size_t base = ((size_t)b * g.D + d) * P + (size_t)y * W;
         const size_t pix = b * P + (size_t)y * W;
-        prefix_row<kCost, false>(im.pixL + pix, im.pixR + pix, in + base, W, d, tab, Pf, nullptr);
+        prefix_row<kCost, false>(im.pixL + pix, im.pixR + pix, in + base, W, d, tab, stage, Pf,
+                                 nullptr);
         for (int x0 = 0; x0 < W; x0 += 64 * kRowBatch) {
             uint32_t a[kRowBatch];
             float n[kRowBatch];
@@ -318,6 +368,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hgrad(SoftGeom g, SoftI
     unsigned char* mine = dyn + kTabLds + w * lds_wave;
     double* Pa = reinterpret_cast<double*>(mine);
     double* Pc = reinterpret_cast<double*>(mine + prefix_bytes(W));
+    float* stage = reinterpret_cast<float*>(mine + 2 * prefix_bytes(W));
     load_tables(im, tab);
     const size_t P = (size_t)W * g.H;
     const int nrows = g.B * g.D * g.H;
@@ -327,7 +378,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hgrad(SoftGeom g, SoftI
         row_of(rid, g.D, g.H, b, d, y);
         const size_t base = ((size_t)b * g.D + d) * P + (size_t)y * W;
         const size_t pix = b * P + (size_t)y * W;
-        prefix_row<true, true>(im.pixL + pix, im.pixR + pix, nullptr, W, d, tab, Pa, Pc);
+        prefix_row<true, true>(im.pixL + pix, im.pixR + pix, nullptr, W, d, tab, stage, Pa, Pc);
         double sa = 0.0, sc = 0.0;
         for (int x0 = 0; x0 < W; x0 += 64 * kRowBatch) {
             uint32_t a[kRowBatch];
@@ -802,14 +853,14 @@ hipError_t soft_aggregate(const SoftBuffers& s, int B, int W, int H, int D, floa
     SoftImg im{s.pixL, s.pixR, s.alpha, s.tab};
     const int nrows = B * D * H;
     const dim3 gr((nrows + kRowWaves * kRowsPerWave - 1) / (kRowWaves * kRowsPerWave));
-    const size_t lf = row_lds_fwd(W);
+    const size_t lf = row_lds_fwd(W), lc = row_lds_cost(W);
     hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_soft_hrow<true>),
-                             kTabLds + kRowWaves * lf);
+                             kTabLds + kRowWaves * lc);
     if (e == hipSuccess)
         e = allow_lds(reinterpret_cast<const void*>(&k_soft_hrow<false>), kRowWaves * lf);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_soft_hrow<true>, gr, dim3(64 * kRowWaves), kTabLds + kRowWaves * lf, st, g,
-                       im, (const float*)nullptr, t1, lf);                                   // E1
+    hipLaunchKernelGGL(k_soft_hrow<true>, gr, dim3(64 * kRowWaves), kTabLds + kRowWaves * lc, st, g,
+                       im, (const float*)nullptr, t1, lc);                                   // E1
     const dim3 gv((W + kSoftCols - 1) / kSoftCols, B * D);
     hipLaunchKernelGGL(k_soft_vs<true>, gv, dim3(kSoftCols), 0, st, g, t1, s.n1, t2);      // a1
     hipLaunchKernelGGL(k_soft_vs<false>, gv, dim3(kSoftCols), 0, st, g, t2,
