@@ -31,6 +31,8 @@
 // packed pixels (census, RGB, L_min) are per pair B x H x W.  Row passes run
 // one wavefront per image row with its FP64 prefix in LDS; column passes one
 // thread per column, streaming down the rows with a ring of FP64 sums in LDS.
+#include <type_traits>
+
 #include "dco_internal.h"
 
 namespace {
@@ -151,6 +153,18 @@ __device__ inline void cost_px(uint4 a, uint4 b, bool inside, const float* tab, 
 constexpr int kRowWaves = 4;
 constexpr int kRowsPerWave = 4;
 constexpr int kRowBatch = 8;
+
+// Runs body(nb, x0) over a row of W columns in batches of 64 NB columns
+// (NB = decltype(nb)::value): batches of kMax while they fit, then of 2, then
+// of 1 (the last may run past W; the body masks those lanes).  A row of 640
+// columns takes one batch of 8 and one of 2, not two of 8.
+template <int kMax = kRowBatch, typename Body>
+__device__ inline void over_row(int W, Body body) {
+    int x0 = 0;
+    for (; x0 + 64 * kMax <= W; x0 += 64 * kMax) body(std::integral_constant<int, kMax>{}, x0);
+    for (; x0 + 64 * 2 <= W; x0 += 64 * 2) body(std::integral_constant<int, 2>{}, x0);
+    for (; x0 < W; x0 += 64) body(std::integral_constant<int, 1>{}, x0);
+}
 
 __device__ inline void row_of(int rid, int D, int H, int& b, int& d, int& y) {
     d = rid % D;
@@ -331,24 +345,25 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hrow(SoftGeom g, SoftIm
         const size_t pix = b * P + (size_t)y * W;
         prefix_row<kCost, false>(im.pixL + pix, im.pixR + pix, in + base, W, d, tab, stage, Pf,
                                  nullptr);
-        for (int x0 = 0; x0 < W; x0 += 64 * kRowBatch) {
-            uint32_t a[kRowBatch];
-            float n[kRowBatch];
+        over_row(W, [&](auto nb, int x0) {
+            constexpr int NB = decltype(nb)::value;
+            uint32_t a[NB];
+            float n[NB];
 #pragma unroll
-            for (int j = 0; j < kRowBatch; ++j) {
+            for (int j = 0; j < NB; ++j) {
                 const int xc = min(x0 + 64 * j + lane, W - 1);
                 a[j] = g.arms[pix + xc];
                 n[j] = kCost ? 1.0f : g.n2[pix + xc];
             }
 #pragma unroll
-            for (int j = 0; j < kRowBatch; ++j) {
+            for (int j = 0; j < NB; ++j) {
                 const int x = x0 + 64 * j + lane;
                 if (x < W) {
                     const float v = (float)(Pf[x + arm(a[j], 1) + 1] - Pf[x - arm(a[j], 0)]);
                     out[base + x] = kCost ? v : v / n[j];
                 }
             }
-        }
+        });
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -380,17 +395,18 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hgrad(SoftGeom g, SoftI
         const size_t pix = b * P + (size_t)y * W;
         prefix_row<true, true>(im.pixL + pix, im.pixR + pix, nullptr, W, d, tab, stage, Pa, Pc);
         double sa = 0.0, sc = 0.0;
-        for (int x0 = 0; x0 < W; x0 += 64 * kRowBatch) {
-            uint32_t a[kRowBatch];
-            float gv[kRowBatch];
+        over_row(W, [&](auto nb, int x0) {
+            constexpr int NB = decltype(nb)::value;
+            uint32_t a[NB];
+            float gv[NB];
 #pragma unroll
-            for (int j = 0; j < kRowBatch; ++j) {
+            for (int j = 0; j < NB; ++j) {
                 const int xc = min(x0 + 64 * j + lane, W - 1);
                 a[j] = g.arms[pix + xc];
                 gv[j] = G[base + xc];
             }
 #pragma unroll
-            for (int j = 0; j < kRowBatch; ++j) {
+            for (int j = 0; j < NB; ++j) {
                 const int x = x0 + 64 * j + lane;
                 if (x < W) {
                     const int hi = x + arm(a[j], 1) + 1, lo = x - arm(a[j], 0);
@@ -398,7 +414,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hgrad(SoftGeom g, SoftI
                     sc += (double)gv[j] * (Pc[hi] - Pc[lo]);
                 }
             }
-        }
+        });
         for (int off = 32; off > 0; off >>= 1) {  // fixed-order wavefront reduction
             sa += __shfl_down(sa, off, 64);
             sc += __shfl_down(sc, off, 64);
@@ -444,11 +460,12 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_seed_adj(
         const size_t pix = b * P + (size_t)y * W;
         double acc = 0.0;
         float gmax = 0.0f;
-        for (int x0 = 0; x0 < W; x0 += 64 * kRowBatch) {
-            float a2[kRowBatch], gp[kRowBatch], dh[kRowBatch], l[kRowBatch], n2[kRowBatch];
-            uint32_t a[kRowBatch];
+        over_row<4>(W, [&](auto nb, int x0) {
+            constexpr int NB = decltype(nb)::value;
+            float a2[NB], gp[NB], dh[NB], l[NB], n2[NB];
+            uint32_t a[NB];
 #pragma unroll
-            for (int j = 0; j < kRowBatch; ++j) {
+            for (int j = 0; j < NB; ++j) {
                 const size_t xc = (size_t)min(x0 + 64 * j + lane, W - 1);
                 a2[j] = A2[base + xc];
                 gp[j] = gdhat[pix + xc];
@@ -458,7 +475,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_seed_adj(
                 a[j] = g.arms[pix + xc];
             }
 #pragma unroll
-            for (int j = 0; j < kRowBatch; ++j) {
+            for (int j = 0; j < NB; ++j) {
                 const int x = x0 + 64 * j + lane;
                 if (x < W) {
                     const float wgt = expf(-a2[j] * invT - l[j]);
@@ -470,7 +487,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_seed_adj(
                     gmax = fmaxf(gmax, fabsf(G));
                 }
             }
-        }
+        });
         for (int o = 32; o > 0; o >>= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, o, 64));
         for (int x = lane; x <= W; x += 64) Dq[x] = 0;
         __builtin_amdgcn_wave_barrier();
@@ -478,13 +495,28 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_seed_adj(
         // a pixel sums at most 2 kLMax + 1 of them: far below 2^63
         const int e = gmax > 0.0f ? ilogbf(gmax) : 0;
         const double up = ldexp(1.0, 44 - e), down = ldexp(1.0, e - 44);
-        for (int x = lane; x < W; x += 64) {
-            const long long q = llrint((double)row[x] * up);
-            const uchar2 a = lr[x];
-            atomicAdd(reinterpret_cast<unsigned long long*>(&Dq[x - a.x]), (unsigned long long)q);
-            atomicAdd(reinterpret_cast<unsigned long long*>(&Dq[x + a.y + 1]),
-                      (unsigned long long)(-q));
-        }
+        over_row(W, [&](auto nb, int x0) {
+            constexpr int NB = decltype(nb)::value;
+            float gx[NB];
+            uchar2 ax[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {  // the batch's reads first, then its adds
+                const int xc = min(x0 + 64 * j + lane, W - 1);
+                gx[j] = row[xc];
+                ax[j] = lr[xc];
+            }
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int x = x0 + 64 * j + lane;
+                if (x < W) {
+                    const long long q = llrint((double)gx[j] * up);
+                    atomicAdd(reinterpret_cast<unsigned long long*>(&Dq[x - ax[j].x]),
+                              (unsigned long long)q);
+                    atomicAdd(reinterpret_cast<unsigned long long*>(&Dq[x + ax[j].y + 1]),
+                              (unsigned long long)(-q));
+                }
+            }
+        });
         __builtin_amdgcn_wave_barrier();
         // prefix of the difference array: each lane a contiguous run, run
         // totals scanned across the wavefront (exact integers)
