@@ -152,10 +152,12 @@ def test_soft_rejects_oversized_batches(torch_mod):
         assert L.dco_soft_backward(m._h, 1, None, None, None, None, None, None, None) == -2
 
 
-@pytest.mark.parametrize("W,H,D,B", [(2048, 9, 6, 1), (23, 11, 5, 3)])
+@pytest.mark.parametrize("W,H,D,B", [(2048, 9, 6, 1), (23, 11, 5, 3), (333, 53, 9, 2)])
 def test_soft_widest_and_smallest_frames(torch_mod, W, H, D, B):
-    """The widest frame the row passes' LDS takes (W = 2048) and a small
-    ragged batch: dhat, lse and the theta gradient against the FP64 oracle."""
+    """The widest frame the row passes' LDS takes (W = 2048), a small ragged
+    batch, and rows that end inside a 256-column chunk with W not a multiple
+    of 4 over more rows than one turn of the column passes' ring: dhat, lse
+    and the theta gradient against the FP64 oracle."""
     torch = torch_mod
     from paper_2203_02300_amd import StereoMatcher
     from paper_2203_02300_amd.soft import soft_backward, soft_forward
