@@ -353,6 +353,20 @@ dco_status dco_soft_backward(dco_stereo* h, int B, const uint8_t* L, const uint8
                              const float* theta, const float* dhat, const float* lse,
                              const float* grad_dhat, float* grad_theta);
 
+/* The same backward, without the recomputation when it can be skipped: the
+ * handle keeps the costs, region counts and aggregated volume of its last
+ * soft aggregation (that of dco_soft_forward, or of a recomputing backward),
+ * and the backward kernels do not overwrite them.  If that aggregation was
+ * made with this B and these same L, R and theta pointers on the handle's
+ * current stream, they are used as they are; otherwise the aggregation is
+ * recomputed first, as in dco_soft_backward.  The caller guarantees that the
+ * contents of L, R and theta have not changed since that aggregation (an
+ * autograd engine's saved tensors do); under that guarantee the result is
+ * bit-identical to dco_soft_backward's.  Same arguments and errors. */
+dco_status dco_soft_backward_reuse(dco_stereo* h, int B, const uint8_t* L, const uint8_t* R,
+                                   const float* theta, const float* dhat, const float* lse,
+                                   const float* grad_dhat, float* grad_theta);
+
 /* ---- Diagnostics ---- */
 const char* dco_status_string(dco_status s);
 const char* dco_last_error(void); /* thread-local; "" when none */

@@ -17,7 +17,8 @@ EXPORTS = (
     "dco_census", "dco_cost_volume", "dco_aggregate", "dco_wta_lrcheck", "dco_stereo_match",
     "dco_stereo_last_disparities", "dco_stereo_profile", "dco_stereo_stage_times",
     "dco_batch_create", "dco_batch_destroy", "dco_batch_match",
-    "dco_batch_tile", "dco_soft_forward", "dco_soft_backward", "dco_vote_refine",
+    "dco_batch_tile", "dco_soft_forward", "dco_soft_backward", "dco_soft_backward_reuse",
+    "dco_vote_refine",
     "dco_stereo_match_half", "dco_densify_default_params", "dco_densify_create",
     "dco_densify_destroy", "dco_densify_run", "dco_densify_stats",
     "dco_contour_default_params", "dco_contour_create", "dco_contour_destroy",
@@ -94,6 +95,7 @@ def lib():
         "dco_batch_tile": (st, [P, i, P, P, P]),
         "dco_soft_forward": (st, [P, i, P, P, P, P, P]),
         "dco_soft_backward": (st, [P, i, P, P, P, P, P, P, P]),
+        "dco_soft_backward_reuse": (st, [P, i, P, P, P, P, P, P, P]),
         "dco_vote_refine": (st, [P, P, P, P, P, i, P, P, P]),
         "dco_stereo_match_half": (st, [P, P, P, i, i, C.c_float, P, P, P]),
         "dco_stereo_match_noalloc": (st, [i, i, i, C.POINTER(Params), P, P, P, P, P]),

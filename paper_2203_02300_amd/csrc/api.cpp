@@ -579,12 +579,19 @@ static dco_status soft_front(dco_stereo* h, int B, const uint8_t* L, const uint8
                              const float* theta, SoftBuffers* sb) {
     SoftScratch& f = h->soft;
     const dco_params& p = h->p;
+    f.held = false;
     DCO_HIP_CHECK(launch_census_pairs(L, R, B, h->W, h->H, p.census_w, p.census_h, p.arm_L1,
                                       p.arm_tau1, f.arms, f.arms_r, f.pix[0], f.pix[1],
                                       h->stream));
     DCO_HIP_CHECK(soft_prepare(theta, f.tab, f.arms, B, h->W, h->H, h->D, f.n1, f.n2, h->stream));
     *sb = SoftBuffers{f.arms, f.n1, f.n2, f.pix[0], f.pix[1], h->alpha, f.tab};
     DCO_HIP_CHECK(soft_aggregate(*sb, B, h->W, h->H, h->D, f.vol[0], f.vol[1], f.vol[2], h->stream));
+    f.held = true;
+    f.held_B = B;
+    f.held_L = L;
+    f.held_R = R;
+    f.held_theta = theta;
+    f.held_stream = h->stream;
     return DCO_OK;
 }
 
@@ -637,6 +644,33 @@ extern "C" dco_status dco_soft_backward(dco_stereo* h, int B, const uint8_t* L, 
     SoftBuffers sb;
     DCO_TRY(soft_front(h, B, L, R, theta, &sb));  // recompute the aggregation
     SoftScratch& f = h->soft;
+    DCO_HIP_CHECK(soft_backward(sb, B, h->W, h->H, h->D, f.vol[0], theta, dhat, lse, grad_dhat,
+                                f.vol[1], f.vol[2], f.partAC, f.partT, grad_theta, h->stream));
+    return DCO_OK;
+}
+
+extern "C" dco_status dco_soft_backward_reuse(dco_stereo* h, int B, const uint8_t* L,
+                                              const uint8_t* R, const float* theta,
+                                              const float* dhat, const float* lse,
+                                              const float* grad_dhat, float* grad_theta) {
+    DCO_TRY(soft_check(h, B));
+    DCO_TRY(need(L, "L"));
+    DCO_TRY(need(R, "R"));
+    DCO_TRY(need(theta, "theta"));
+    DCO_TRY(need(dhat, "dhat"));
+    DCO_TRY(need(lse, "lse"));
+    DCO_TRY(need(grad_dhat, "grad_dhat"));
+    DCO_TRY(need(grad_theta, "grad_theta"));
+    DCO_TRY(soft_reserve(h, B));
+    SoftScratch& f = h->soft;
+    SoftBuffers sb;
+    // the backward kernels leave the held aggregation, tables, counts, arms
+    // and pixels as they are, so any number of backward calls can reuse them
+    if (f.held && f.held_B == B && f.held_L == L && f.held_R == R && f.held_theta == theta &&
+        f.held_stream == h->stream)
+        sb = SoftBuffers{f.arms, f.n1, f.n2, f.pix[0], f.pix[1], h->alpha, f.tab};
+    else
+        DCO_TRY(soft_front(h, B, L, R, theta, &sb));
     DCO_HIP_CHECK(soft_backward(sb, B, h->W, h->H, h->D, f.vol[0], theta, dhat, lse, grad_dhat,
                                 f.vol[1], f.vol[2], f.partAC, f.partT, grad_theta, h->stream));
     return DCO_OK;

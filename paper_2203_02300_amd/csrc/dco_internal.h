@@ -42,6 +42,15 @@ struct SoftScratch {
     double* partAC;        // per-row partial sums of the lambda gradients
     double* partT;         // per-row partial sums of the temperature gradient, then
                            // 3 x 256 block totals of the final reduction
+    // The inputs whose costs and aggregation the buffers above hold (set by
+    // the last complete aggregation, cleared when the buffers change): B, the
+    // device pointers L, R, theta and the stream it ran on.
+    bool held;
+    int held_B;
+    const void* held_L;
+    const void* held_R;
+    const void* held_theta;
+    hipStream_t held_stream;
 };
 
 // Read-only view of the soft-path inputs handed to the kernels.

@@ -166,6 +166,15 @@ __device__ inline void over_row(int W, Body body) {
     for (; x0 < W; x0 += 64) body(std::integral_constant<int, 1>{}, x0);
 }
 
+// Workgroup index in the row order of workgroup b of n: the workgroups one
+// XCD runs (round-robin dispatch, b mod 8) take a contiguous run, so the
+// workgroups that share an image row share that XCD's L2.
+__device__ inline int xcd_block(int b, int n) {
+    const int xcd = b & 7, i = b >> 3;
+    const int per = n >> 3, rem = n & 7;
+    return xcd < rem ? xcd * (per + 1) + i : rem * (per + 1) + (xcd - rem) * per + i;
+}
+
 __device__ inline void row_of(int rid, int D, int H, int& b, int& d, int& y) {
     d = rid % D;
     const int by = rid / D;
@@ -337,7 +346,11 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hrow(SoftGeom g, SoftIm
     if (kCost) load_tables(im, tab);
     const size_t P = (size_t)W * g.H;
     const int nrows = g.B * g.D * g.H;
-    const int r0 = (blockIdx.x * kRowWaves + w) * kRowsPerWave;
+    // raw costs: the workgroups of one image row on one XCD (its pixels are
+    // the shared input); the other passes stream volumes and keep the
+    // round-robin order
+    const int blk = kCost ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int r0 = (blk * kRowWaves + w) * kRowsPerWave;
     for (int rid = r0; rid < min(nrows, r0 + kRowsPerWave); ++rid) {
         int b, d, y;
         row_of(rid, g.D, g.H, b, d, y);

@@ -3,9 +3,10 @@
 ``DcoSoftArgmin.apply(matcher, L, R, theta) -> dhat`` runs the library's
 soft forward (Eq. 1 costs with theta = (lambda_AD, lambda_census, T), the
 two-stage region means of Eq. 2, softmax over d) and, on ``backward``, its
-hand-written backward kernels, which recompute the aggregation and return
-d loss / d theta.  Census codes and arm lengths are integer and are not
-differentiated; only (dhat, lse) are kept between the two passes.
+hand-written backward kernels, which return d loss / d theta.  The backward
+uses the aggregation the handle still holds from the forward (or recomputes
+it when another soft call has replaced it).  Census codes and arm lengths are
+integer and are not differentiated.
 """
 from __future__ import annotations
 
@@ -35,8 +36,10 @@ def soft_forward(m: StereoMatcher, L, R, theta):
     return dhat, lse
 
 
-def soft_backward(m: StereoMatcher, L, R, theta, dhat, lse, grad_dhat):
-    """d loss / d theta (3 float32) for grad_dhat = d loss / d dhat."""
+def soft_backward(m: StereoMatcher, L, R, theta, dhat, lse, grad_dhat, reuse=False):
+    """d loss / d theta (3 float32) for grad_dhat = d loss / d dhat.  With
+    reuse, the aggregation the handle holds from the forward on these same
+    L, R, theta tensors (unchanged since) is used instead of recomputed."""
     L, R, B = _pairs(m, L, R)
     shape = (B, m.H, m.W)
     _need(theta, "theta", torch.float32, (3,))
@@ -44,8 +47,9 @@ def soft_backward(m: StereoMatcher, L, R, theta, dhat, lse, grad_dhat):
         _need(t, n, torch.float32, shape)
     m._begin()
     g = m._empty((3,), torch.float32)
-    check(lib().dco_soft_backward(m._h, B, _ptr(L), _ptr(R), _ptr(theta), _ptr(dhat), _ptr(lse),
-                                  _ptr(grad_dhat), _ptr(g)))
+    fn = lib().dco_soft_backward_reuse if reuse else lib().dco_soft_backward
+    check(fn(m._h, B, _ptr(L), _ptr(R), _ptr(theta), _ptr(dhat), _ptr(lse), _ptr(grad_dhat),
+             _ptr(g)))
     return g
 
 
@@ -62,9 +66,12 @@ class DcoSoftArgmin(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_dhat):
+        # saved tensors cannot have changed in place since the forward
+        # (autograd checks their versions), so the handle's aggregation of
+        # that forward can be reused if nothing has replaced it
         L, R, theta, dhat, lse = ctx.saved_tensors
         g = soft_backward(ctx.matcher, L, R, theta, dhat, lse,
-                          grad_dhat.reshape(dhat.shape).contiguous().float())
+                          grad_dhat.reshape(dhat.shape).contiguous().float(), reuse=True)
         return None, None, None, g.to(theta.dtype)
 
 

@@ -82,6 +82,37 @@ def test_soft_forward_and_gradient_match_oracle(torch_mod, T):
     assert np.all(np.abs(g_gpu - g_ref) <= 1e-3 * scale), (g_gpu, g_ref)
 
 
+def test_soft_backward_reuse_is_bit_identical(torch_mod):
+    """dco_soft_backward_reuse right after its forward (the held aggregation
+    is used), twice in a row, after a forward on another theta (recomputed),
+    and after a recomputing backward: the same bits as dco_soft_backward."""
+    torch = torch_mod
+    from paper_2203_02300_amd import StereoMatcher
+    from paper_2203_02300_amd.soft import soft_backward, soft_forward
+    W, H, D, B = 160, 48, 24, 2
+    ps = pairs(320, W, H, D, B)
+    rng = np.random.default_rng(7)
+    with StereoMatcher(W, H, D) as m:
+        L = dev(np.stack([p["left"] for p in ps]))
+        R = dev(np.stack([p["right"] for p in ps]))
+        th1 = torch.tensor([10.0, 30.0, 1.0], dtype=torch.float32, device="cuda")
+        th2 = torch.tensor([12.0, 25.0, 0.5], dtype=torch.float32, device="cuda")
+        gd = dev(rng.normal(0, 1e-3, (B, H, W)).astype(np.float32))
+        dh1, lse1 = soft_forward(m, L, R, th1)
+        g_ref = host(soft_backward(m, L, R, th1, dh1, lse1, gd))
+        dh1, lse1 = soft_forward(m, L, R, th1)
+        g1 = host(soft_backward(m, L, R, th1, dh1, lse1, gd, reuse=True))
+        g2 = host(soft_backward(m, L, R, th1, dh1, lse1, gd, reuse=True))
+        dh2, lse2 = soft_forward(m, L, R, th2)  # replaces the held aggregation
+        g3 = host(soft_backward(m, L, R, th1, dh1, lse1, gd, reuse=True))
+        g4 = host(soft_backward(m, L, R, th2, dh2, lse2, gd))
+        g5 = host(soft_backward(m, L, R, th2, dh2, lse2, gd, reuse=True))
+    for g in (g1, g2, g3):
+        assert np.array_equal(g.view(np.int32), g_ref.view(np.int32)), (g, g_ref)
+    assert np.array_equal(g5.view(np.int32), g4.view(np.int32)), (g5, g4)
+    assert not np.array_equal(g4, g_ref)
+
+
 def test_soft_small_temperature_approaches_wta(torch_mod):
     torch = torch_mod
     from paper_2203_02300_amd import StereoMatcher
