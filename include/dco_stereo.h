@@ -147,9 +147,12 @@ dco_status dco_wta_lrcheck(dco_stereo* h, const float* aggL, const float* aggR, 
  *  2. the raw cost of Eq. 1 computed on the fly inside the two-stage
  *     aggregation of both views (one launch): no raw cost volume exists,
  *     but the two aggregated volumes (D x H x W float each, 2 x 472 MB at
- *     1280 x 720, D = 128) are written to the handle's scratch;
+ *     1280 x 720, D = 128) are written to the handle's scratch; with two
+ *     stages each pair of slices (2g, 2g + 1) is stored with its smaller
+ *     cost and that cost's slice in slice 2g and the other cost in 2g + 1;
  *  3. WTA with sub-pixel refinement of both views, reading those volumes
- *     (a separate pass), then the LR check;
+ *     (a separate pass; with two stages only the even slices, plus the
+ *     costs at d - 1 and d + 1 for the parabola), then the LR check;
  *  4. when vote_iters > 0, the Eq. 4 vote of dco_vote_refine.
  * With vote_iters = 0 the results are bit-identical to dco_census ->
  * dco_cost_volume -> dco_aggregate -> dco_wta_lrcheck; with vote_iters = n
@@ -373,9 +376,11 @@ const char* dco_last_error(void); /* thread-local; "" when none */
 
 /* Aggregated costs A2 (Eq. 2 applied as two stages) of disparities
  * d0 .. d0 + n - 1 of one view (0 = left reference, 1 = right), as left in
- * the handle's scratch by the last dco_stereo_match: copied on the handle's
- * stream into out (device, n x H x W float).  Lets a test compare the fused
- * path's volume element by element.  DCO_ERR_ARG for a bad view or range. */
+ * the handle's scratch by the last dco_stereo_match: copied (and, when that
+ * volume is in the paired slice order of two-stage aggregation, put back in
+ * slice order) on the handle's stream into out (device, n x H x W float).
+ * Lets a test compare the fused path's volume element by element.
+ * DCO_ERR_ARG for a bad view or range. */
 dco_status dco_stereo_agg_slices(dco_stereo* h, int view, int d0, int n, float* out);
 
 /* The one-call match without a handle and without any allocation, for

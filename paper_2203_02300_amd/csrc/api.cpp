@@ -432,11 +432,16 @@ extern "C" dco_status dco_stereo_match(dco_stereo* h, const uint8_t* rgbL, const
     DCO_TRY(prof_mark(h));
     DCO_HIP_CHECK(launch_cost_aggregate2(s.pix[0], s.pix[1], s.rec[0], s.rec[1], h->W, h->H, h->D,
                                          p.agg_iters, h->tabA, h->tabC, h->alpha, h->beta,
-                                         p.arm_L1, s.agg[0], s.agg[1], h->stream));
+                                         p.arm_L1, s.agg[0], s.agg[1], true, h->stream));
+    s.agg_paired = p.agg_iters == 2;
     DCO_TRY(prof_mark(h));
     DCO_TRY(prof_mark(h));
-    DCO_HIP_CHECK(launch_wta2(s.agg[0], s.agg[1], h->W, h->H, h->D, p.subpixel, s.dint[0],
-                              s.delta, s.dint[1], h->stream));
+    if (s.agg_paired)  // WTA from the even slices (each pair's minimum)
+        DCO_HIP_CHECK(launch_wta_pairs(s.agg[0], s.agg[1], h->W, h->H, h->D, p.subpixel,
+                                       s.dint[0], s.delta, s.dint[1], h->stream));
+    else
+        DCO_HIP_CHECK(launch_wta2(s.agg[0], s.agg[1], h->W, h->H, h->D, p.subpixel, s.dint[0],
+                                  s.delta, s.dint[1], h->stream));
     DCO_TRY(prof_mark(h));
     DCO_TRY(prof_mark(h));
     DCO_HIP_CHECK(launch_lrcheck(s.dint[0], s.delta, s.dint[1], h->W, h->H, p.lr_max_diff, disp,
@@ -447,8 +452,8 @@ extern "C" dco_status dco_stereo_match(dco_stereo* h, const uint8_t* rgbL, const
         const int16_t* dv = nullptr;
         DCO_HIP_CHECK(launch_vote(s.dint[0], valid, s.arms[0], h->W, h->H, h->D, p.vote_iters,
                                   s.vote[0], s.vote[1], &dv, h->stream));
-        DCO_HIP_CHECK(launch_vote_finish(dv, nullptr, s.agg[0], h->W, h->H, h->D, p.subpixel, disp,
-                                         valid, nullptr, h->stream));
+        DCO_HIP_CHECK(launch_vote_finish(dv, nullptr, s.agg[0], s.agg_paired, h->W, h->H, h->D,
+                                         p.subpixel, disp, valid, nullptr, h->stream));
     }
     DCO_TRY(prof_mark(h));
     return DCO_OK;
@@ -508,7 +513,7 @@ extern "C" dco_status dco_vote_refine(dco_stereo* h, const uint8_t* armsL, const
                                   h->D, iters, h->s.vote[0], h->s.vote[1], &dv, h->stream));
         mask = nullptr;
     }
-    DCO_HIP_CHECK(launch_vote_finish(dv, mask, aggL, h->W, h->H, h->D, h->p.subpixel, disp,
+    DCO_HIP_CHECK(launch_vote_finish(dv, mask, aggL, false, h->W, h->H, h->D, h->p.subpixel, disp,
                                      valid_out, dvote, h->stream));
     return DCO_OK;
 }
@@ -529,8 +534,12 @@ extern "C" dco_status dco_stereo_agg_slices(dco_stereo* h, int view, int d0, int
         return DCO_ERR_STATE;
     }
     const size_t P = (size_t)h->W * h->H;
-    DCO_HIP_CHECK(hipMemcpyAsync(out, h->s.agg[view] + (size_t)d0 * P, (size_t)n * P * sizeof(float),
-                                 hipMemcpyDeviceToDevice, h->stream));
+    if (h->s.agg_paired)
+        DCO_HIP_CHECK(launch_unpair(h->s.agg[view], h->W, h->H, h->D, d0, n, out, h->stream));
+    else
+        DCO_HIP_CHECK(hipMemcpyAsync(out, h->s.agg[view] + (size_t)d0 * P,
+                                     (size_t)n * P * sizeof(float), hipMemcpyDeviceToDevice,
+                                     h->stream));
     return DCO_OK;
 }
 

@@ -498,8 +498,24 @@ struct AggArgs {
     const float* beta;
     AggRecords rec;            // padded per-pixel records of the reference view
     float* out;                // D x H x W
+    // two-slice kernel: store `out` in the paired layout (see paired_at)
+    bool paired;
     int W, H, D, nstrips, ref, L1;
 };
+
+// Paired layout of a D-slice cost volume: for each pixel and pair of slices
+// (2g, 2g + 1), slice 2g holds the bits of the smaller cost (the first on a
+// tie; costs are >= 0, so bit 31 is free) with bit 31 set when that is slice
+// 2g + 1's, and slice 2g + 1 holds the other cost.  A last slice without a
+// partner (odd D) holds its cost as it is.  Winner-take-all then reads only
+// the even slices.  paired_at returns the cost of slice s at pixel i.
+__device__ inline float paired_at(const float* __restrict__ vol, int P, int D, int s, int i) {
+    const int e = s & ~1;
+    const uint32_t w = __builtin_bit_cast(uint32_t, vol[(size_t)e * P + i]);
+    if (e + 1 >= D || (s & 1) == (int)(w >> 31))
+        return __builtin_bit_cast(float, w & 0x7fffffffu);
+    return vol[(size_t)(e + 1) * P + i];
+}
 
 // Loads of one chunk.  Step 1 and step 3 loads are for this lane's four
 // segment columns of its wavefront's row; step 2 loads are for the owned
@@ -532,6 +548,7 @@ struct AggRes {
     rsrc_t rB, rC, rq, rIr, rIp, rOut;
     uint32_t slice_bytes;  // two-slice kernel: distance between its output slices
     int nout;              // two-slice kernel: slices that exist (the others are not stored)
+    bool paired;           // two-slice kernel: paired layout (AggArgs::paired)
 };
 
 template <int ITERS, bool kFused>
@@ -987,6 +1004,17 @@ __device__ inline void ws_row_phase(const AggArgs& A, int ys, int y0, int y1, in
     ws_scan_row(q, row);
     const int y2 = ys + kAggK * (p - 2) + w - 2 * kLMax - 1;
     if (p >= 2 && y2 >= y0 && y2 < y1) {  // uniform
+        if (R.paired && R.nout == kWsSlices) {  // uniform: the pair's minimum first
+#pragma unroll
+            for (int j = 0; j < kSeg; ++j) {
+                const bool second = out[1][j] < out[0][j];
+                const float lo = second ? out[1][j] : out[0][j], hi = second ? out[0][j] : out[1][j];
+                out[0][j] = __builtin_bit_cast(
+                    float, (__builtin_bit_cast(uint32_t, lo) & 0x7fffffffu) |
+                               (second ? 0x80000000u : 0u));
+                out[1][j] = hi;
+            }
+        }
 #pragma unroll
         for (int s = 0; s < kWsSlices; ++s)
             if (s < R.nout)  // uniform
@@ -1076,6 +1104,7 @@ __device__ inline void agg_stream_ws(const AggArgs& A, int d, int dend, int stri
     R.rOut = make_rsrc(A.out + (size_t)d * slice, (uint32_t)nout * P4);
     R.slice_bytes = P4;
     R.nout = nout;
+    R.paired = A.paired;
 
     const int warm = 2 * kLMax + 1;
     const int ys = max(0, y0 - warm);
@@ -1268,6 +1297,91 @@ __device__ inline void wta_quad(const float* __restrict__ agg, int P, int D, int
             del.y = subpixel_delta(m[1], best[1], pl[1], bd[1], D);
             del.z = subpixel_delta(m[2], best[2], pl[2], bd[2], D);
             del.w = subpixel_delta(m[3], best[3], pl[3], bd[3], D);
+        }
+        *reinterpret_cast<float4*>(delta_out + i4) = del;
+    }
+}
+
+// Winner-take-all on a volume in the paired layout: the same rule and the
+// same result as wta_pixel / wta_quad, since each even slice holds the
+// smaller cost of its pair (the first on a tie) and the pairs are visited in
+// order with a strict comparison; only the G = ceil(D / 2) even slices are
+// read.  The sub-pixel step gathers the costs at d - 1 and d + 1, which is
+// exactly where wta_pixel's m and pl come from when 0 < d < D - 1 (the only
+// case in which subpixel_delta uses them).
+__device__ inline void wta_pair_step(uint32_t s, int g, float& best, int& bd) {
+    const float v = __builtin_bit_cast(float, s & 0x7fffffffu);
+    if (v < best) {
+        best = v;
+        bd = 2 * g + (int)(s >> 31);
+    }
+}
+
+__device__ inline float wta_pair_delta(const float* __restrict__ vol, int P, int D, int i,
+                                       float best, int bd) {
+    if (bd <= 0 || bd >= D - 1) return 0.f;
+    return subpixel_delta(paired_at(vol, P, D, bd - 1, i), best, paired_at(vol, P, D, bd + 1, i),
+                          bd, D);
+}
+
+__device__ inline void wta_pairs_pixel(const float* __restrict__ vol, int P, int D, int i,
+                                       int subpixel, int16_t* dout, float* delta_out) {
+    const uint32_t* __restrict__ u = reinterpret_cast<const uint32_t*>(vol);
+    const int G = (D + 1) / 2;
+    float best = __builtin_bit_cast(float, u[i] & 0x7fffffffu);
+    int bd = (int)(u[i] >> 31);
+    for (int g = 1; g < G; ++g) wta_pair_step(u[(size_t)2 * g * P + i], g, best, bd);
+    *dout = (int16_t)bd;
+    if (delta_out) *delta_out = subpixel ? wta_pair_delta(vol, P, D, i, best, bd) : 0.f;
+}
+
+// Four consecutive pixels (P % 4 == 0): one 16-byte load per even slice,
+// eight slices in flight.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline void wta_pairs_quad(const float* __restrict__ vol, int P, int D, int i4,
+                                      int subpixel, int16_t* __restrict__ dout,
+                                      float* __restrict__ delta_out) {
+    const int G = (D + 1) / 2;
+    const u32x4* __restrict__ s4 = reinterpret_cast<const u32x4*>(vol + i4);
+    const size_t st = (size_t)P / 2;  // two slices, in 16-byte words
+    const u32x4 w0 = __builtin_nontemporal_load(s4);
+    float best[4] = {__builtin_bit_cast(float, w0.x & 0x7fffffffu),
+                     __builtin_bit_cast(float, w0.y & 0x7fffffffu),
+                     __builtin_bit_cast(float, w0.z & 0x7fffffffu),
+                     __builtin_bit_cast(float, w0.w & 0x7fffffffu)};
+    int bd[4] = {(int)(w0.x >> 31), (int)(w0.y >> 31), (int)(w0.z >> 31), (int)(w0.w >> 31)};
+    constexpr int U = 8;
+    int g = 1;
+    for (; g + U <= G; g += U) {
+        u32x4 v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) v[k] = __builtin_nontemporal_load(s4 + (size_t)(g + k) * st);
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            wta_pair_step(v[k].x, g + k, best[0], bd[0]);
+            wta_pair_step(v[k].y, g + k, best[1], bd[1]);
+            wta_pair_step(v[k].z, g + k, best[2], bd[2]);
+            wta_pair_step(v[k].w, g + k, best[3], bd[3]);
+        }
+    }
+    for (; g < G; ++g) {
+        const u32x4 v = __builtin_nontemporal_load(s4 + (size_t)g * st);
+        wta_pair_step(v.x, g, best[0], bd[0]);
+        wta_pair_step(v.y, g, best[1], bd[1]);
+        wta_pair_step(v.z, g, best[2], bd[2]);
+        wta_pair_step(v.w, g, best[3], bd[3]);
+    }
+    const uint32_t lo = (uint32_t)(uint16_t)bd[0] | (uint32_t)(uint16_t)bd[1] << 16;
+    const uint32_t hi = (uint32_t)(uint16_t)bd[2] | (uint32_t)(uint16_t)bd[3] << 16;
+    *reinterpret_cast<uint2*>(dout + i4) = make_uint2(lo, hi);
+    if (delta_out) {
+        float4 del = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (subpixel) {
+            del.x = wta_pair_delta(vol, P, D, i4, best[0], bd[0]);
+            del.y = wta_pair_delta(vol, P, D, i4 + 1, best[1], bd[1]);
+            del.z = wta_pair_delta(vol, P, D, i4 + 2, best[2], bd[2]);
+            del.w = wta_pair_delta(vol, P, D, i4 + 3, best[3], bd[3]);
         }
         *reinterpret_cast<float4*>(delta_out + i4) = del;
     }

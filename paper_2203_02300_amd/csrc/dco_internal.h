@@ -21,6 +21,7 @@ struct dco_scratch {
     AggRecords rec[2];
     uint4* pix[2];      // packed pixels of both views: census lo, census hi, RGB, 8 L_min
     float* agg[2];      // aggregated volumes of both views (D x H x W)
+    bool agg_paired;    // ... written in the paired layout (two-stage aggregation)
     int16_t* dint[2];
     float* delta;
     int16_t* vote[2];   // ping-pong maps of the Eq. 4 vote passes
@@ -185,9 +186,9 @@ hipError_t launch_census_arms(const uint8_t* rgb, int W, int H, int cw, int ch, 
 hipError_t launch_vote(const int16_t* dL, const uint8_t* valid, const uint32_t* arms, int W, int H,
                        int D, int iters, int16_t* buf0, int16_t* buf1, const int16_t** result,
                        hipStream_t st);
-hipError_t launch_vote_finish(const int16_t* dv, const uint8_t* valid_in, const float* agg, int W,
-                              int H, int D, int subpixel, float* disp, uint8_t* valid,
-                              int16_t* dv_out, hipStream_t st);
+hipError_t launch_vote_finish(const int16_t* dv, const uint8_t* valid_in, const float* agg,
+                              bool paired, int W, int H, int D, int subpixel, float* disp,
+                              uint8_t* valid, int16_t* dv_out, hipStream_t st);
 // Quarter-size front end: 2 x 2 block means of both full images (row length
 // W2 pixels) into W x H x 3 outputs; then disp = 2 disp where valid (else 0)
 // in place, and depth = fB / disp where > 0 (depth optional).
@@ -255,18 +256,27 @@ hipError_t launch_cost(int ref, const uint8_t* rgbL, const uint8_t* rgbR, const 
                        const float* beta, int L1, float* cost, hipStream_t st);
 hipError_t launch_aggregate(const float* cost, const AggRecords& rec, int W, int H, int D,
                             int iters, float* out, hipStream_t st);
-// Both views in one launch (the one-call path).
+// Both views in one launch (the one-call path).  With two stages and
+// `paired`, the volumes are written in the paired layout (dco::paired_at);
+// with one stage they are always plain.
 hipError_t launch_cost_aggregate2(const uint4* pixL, const uint4* pixR, const AggRecords& recL,
                                   const AggRecords& recR, int W, int H, int D, int iters,
                                   const float* tabA, const float* tabC, const float* alpha,
                                   const float* beta, int L1, float* outL, float* outR,
-                                  hipStream_t st);
+                                  bool paired, hipStream_t st);
 hipError_t launch_cost_aggregate(int ref, const uint4* pixL, const uint4* pixR,
                                  const AggRecords& rec, int W, int H, int D, int iters,
                                  const float* tabA, const float* tabC, const float* alpha,
                                  const float* beta, int L1, float* out, hipStream_t st);
 hipError_t launch_wta2(const float* aggL, const float* aggR, int W, int H, int D, int subpixel,
                        int16_t* dL, float* deltaL, int16_t* dR, hipStream_t st);
+// The same outputs from volumes in the paired layout (even slices only).
+hipError_t launch_wta_pairs(const float* aggL, const float* aggR, int W, int H, int D,
+                            int subpixel, int16_t* dL, float* deltaL, int16_t* dR,
+                            hipStream_t st);
+// Slices d0 .. d0 + n - 1 of a paired-layout volume, decoded into out (n x H x W).
+hipError_t launch_unpair(const float* vol, int W, int H, int D, int d0, int n, float* out,
+                         hipStream_t st);
 hipError_t launch_lrcheck(const int16_t* dL, const float* deltaL, const int16_t* dR, int W,
                           int H, int maxdiff, float* disp, uint8_t* valid, hipStream_t st);
 

@@ -211,7 +211,7 @@ hipError_t launch_cost_aggregate2(const uint4* pixL, const uint4* pixR, const Ag
                                   const AggRecords& recR, int W, int H, int D, int iters,
                                   const float* tabA, const float* tabC, const float* alpha,
                                   const float* beta, int L1, float* outL, float* outR,
-                                  hipStream_t st) {
+                                  bool paired, hipStream_t st) {
     dco::AggArgs a{};
     a.pixL = pixL;
     a.pixR = pixR;
@@ -227,6 +227,7 @@ hipError_t launch_cost_aggregate2(const uint4* pixL, const uint4* pixR, const Ag
     a.ref = 0;
     a.rec = recL;
     a.out = outL;
+    a.paired = paired && iters == 2;
     return iters == 1 ? launch_pair<1>(a, recR, outR, st) : launch_pair_ws(a, recR, outR, st);
 }
 

@@ -50,6 +50,9 @@ __global__ __launch_bounds__(dco::kWsThreads, 1) void k_batch_agg_ws(BatchArgs B
     A.nstrips = pr.nstrips;
     A.ref = I.view;
     A.L1 = B.L1;
+    // with an even chunk every pass starts at an even slice, so the passes'
+    // slice pairs are the layout's pairs; stage 3 reads the even slices
+    A.paired = pr.dchunk % 2 == 0;
     const int y0 = I.c * pr.band, y1 = min(pr.H, y0 + pr.band);
     const int dend = min(pr.D, I.a + pr.dchunk);
     for (int d = I.a; d < dend; d += dco::kWsSlices) {
@@ -139,21 +142,39 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BatchArgs B, int first, 
                 __syncthreads();
             }
         } else if constexpr (STAGE == 3) {  // WTA of both views for pixels [a, a + kWtaPx)
+            // two stages with an even chunk write the volumes in the paired
+            // layout (even slices hold each pair's minimum), else plain
             const int P = W * H;
+            const bool paired = ITERS == 2 && pr.dchunk % 2 == 0;
             if (P % 4 == 0) {  // 16-byte loads (the pair's buffers are 256-byte aligned)
                 for (int r = 0; r < kWtaPx / 1024; ++r) {
                     const int i4 = I.a + (r * 256 + t) * 4;
                     if (i4 >= P) break;
-                    dco::wta_quad(pr.agg[0], P, pr.D, i4, B.subpixel, pr.dint[0], pr.delta);
-                    dco::wta_quad(pr.agg[1], P, pr.D, i4, B.subpixel, pr.dint[1], nullptr);
+                    if (paired) {
+                        dco::wta_pairs_quad(pr.agg[0], P, pr.D, i4, B.subpixel, pr.dint[0],
+                                            pr.delta);
+                        dco::wta_pairs_quad(pr.agg[1], P, pr.D, i4, B.subpixel, pr.dint[1],
+                                            nullptr);
+                    } else {
+                        dco::wta_quad(pr.agg[0], P, pr.D, i4, B.subpixel, pr.dint[0], pr.delta);
+                        dco::wta_quad(pr.agg[1], P, pr.D, i4, B.subpixel, pr.dint[1], nullptr);
+                    }
                 }
             } else {
                 for (int r = 0; r < kWtaPx / 256; ++r) {
                     const int i = I.a + r * 256 + t;
                     if (i >= P) break;
-                    dco::wta_pixel(pr.agg[0], P, pr.D, i, B.subpixel, pr.dint[0] + i,
-                                   pr.delta + i);
-                    dco::wta_pixel(pr.agg[1], P, pr.D, i, B.subpixel, pr.dint[1] + i, nullptr);
+                    if (paired) {
+                        dco::wta_pairs_pixel(pr.agg[0], P, pr.D, i, B.subpixel, pr.dint[0] + i,
+                                             pr.delta + i);
+                        dco::wta_pairs_pixel(pr.agg[1], P, pr.D, i, B.subpixel, pr.dint[1] + i,
+                                             nullptr);
+                    } else {
+                        dco::wta_pixel(pr.agg[0], P, pr.D, i, B.subpixel, pr.dint[0] + i,
+                                       pr.delta + i);
+                        dco::wta_pixel(pr.agg[1], P, pr.D, i, B.subpixel, pr.dint[1] + i,
+                                       nullptr);
+                    }
                 }
             }
         } else {  // LR check of rows [a, a + kLrRows)

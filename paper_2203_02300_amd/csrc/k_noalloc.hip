@@ -194,17 +194,22 @@ extern "C" dco_status dco_stereo_match_noalloc(int W, int H, int D, const dco_pa
                                 b.rec[1], pair_rec_geom(p.agg_iters), st));
     DCO_HIP_CHECK(launch_cost_aggregate2(b.pix[0], b.pix[1], b.rec[0], b.rec[1], W, H, D,
                                          p.agg_iters, b.tabA, b.tabC, b.alpha, b.beta, p.arm_L1,
-                                         b.agg[0], b.agg[1], st));
-    DCO_HIP_CHECK(launch_wta2(b.agg[0], b.agg[1], W, H, D, p.subpixel, b.dint[0], b.delta,
-                              b.dint[1], st));
+                                         b.agg[0], b.agg[1], true, st));
+    const bool paired = p.agg_iters == 2;
+    if (paired)
+        DCO_HIP_CHECK(launch_wta_pairs(b.agg[0], b.agg[1], W, H, D, p.subpixel, b.dint[0],
+                                       b.delta, b.dint[1], st));
+    else
+        DCO_HIP_CHECK(launch_wta2(b.agg[0], b.agg[1], W, H, D, p.subpixel, b.dint[0], b.delta,
+                                  b.dint[1], st));
     DCO_HIP_CHECK(launch_lrcheck(b.dint[0], b.delta, b.dint[1], W, H, p.lr_max_diff, disp, valid,
                                  st));
     if (p.vote_iters > 0) {
         const int16_t* dv = nullptr;
         DCO_HIP_CHECK(launch_vote(b.dint[0], valid, b.arms[0], W, H, D, p.vote_iters, b.vote[0],
                                   b.vote[1], &dv, st));
-        DCO_HIP_CHECK(launch_vote_finish(dv, nullptr, b.agg[0], W, H, D, p.subpixel, disp, valid,
-                                         nullptr, st));
+        DCO_HIP_CHECK(launch_vote_finish(dv, nullptr, b.agg[0], paired, W, H, D, p.subpixel, disp,
+                                         valid, nullptr, st));
     }
     return DCO_OK;
 }

@@ -187,9 +187,10 @@ __global__ __launch_bounds__(kVThreads) void k_vote(const int16_t* __restrict__ 
 // [0, D) (and valid_in, when given, is set); else disp = 0, valid = 0.
 // valid may alias valid_in; dv_out (optional) gets dv, or -1 where invalid.
 __global__ __launch_bounds__(256) void k_vote_finish(const int16_t* dv, const uint8_t* valid_in,
-                                                     const float* __restrict__ agg, int P, int D,
-                                                     int subpixel, float* __restrict__ disp,
-                                                     uint8_t* valid, int16_t* dv_out) {
+                                                     const float* __restrict__ agg, int paired,
+                                                     int P, int D, int subpixel,
+                                                     float* __restrict__ disp, uint8_t* valid,
+                                                     int16_t* dv_out) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= P) return;
     const int d = dv[i];
@@ -197,9 +198,15 @@ __global__ __launch_bounds__(256) void k_vote_finish(const int16_t* dv, const ui
     float out = 0.0f;
     if (ok) {
         float del = 0.0f;
-        if (subpixel && d > 0 && d < D - 1)
-            del = dco::subpixel_delta(agg[(size_t)(d - 1) * P + i], agg[(size_t)d * P + i],
-                                      agg[(size_t)(d + 1) * P + i], d, D);
+        if (subpixel && d > 0 && d < D - 1) {
+            if (paired)
+                del = dco::subpixel_delta(dco::paired_at(agg, P, D, d - 1, i),
+                                          dco::paired_at(agg, P, D, d, i),
+                                          dco::paired_at(agg, P, D, d + 1, i), d, D);
+            else
+                del = dco::subpixel_delta(agg[(size_t)(d - 1) * P + i], agg[(size_t)d * P + i],
+                                          agg[(size_t)(d + 1) * P + i], d, D);
+        }
         out = (float)d + del;
     }
     disp[i] = out;
@@ -226,11 +233,11 @@ hipError_t launch_vote(const int16_t* dL, const uint8_t* valid, const uint32_t* 
     return hipGetLastError();
 }
 
-hipError_t launch_vote_finish(const int16_t* dv, const uint8_t* valid_in, const float* agg, int W,
-                              int H, int D, int subpixel, float* disp, uint8_t* valid,
-                              int16_t* dv_out, hipStream_t st) {
+hipError_t launch_vote_finish(const int16_t* dv, const uint8_t* valid_in, const float* agg,
+                              bool paired, int W, int H, int D, int subpixel, float* disp,
+                              uint8_t* valid, int16_t* dv_out, hipStream_t st) {
     const int P = W * H;
     hipLaunchKernelGGL(k_vote_finish, dim3((P + 255) / 256), dim3(256), 0, st, dv, valid_in, agg,
-                       P, D, subpixel, disp, valid, dv_out);
+                       (int)paired, P, D, subpixel, disp, valid, dv_out);
     return hipGetLastError();
 }

@@ -1,5 +1,8 @@
 // k_wta.hip -- winner-take-all over the aggregated volumes (Eq. 3) with
 // parabola sub-pixel refinement, and the left-right consistency check.
+// k_wta_pairs* take the same decision on volumes in the paired layout
+// (dco::paired_at): they read only the even slices and gather d - 1 and d + 1
+// for the sub-pixel step.
 // One thread per pixel (or per four pixels, with 16-byte loads, when W * H is
 // a multiple of four) walks d = 0 .. D-1; loads of one slice are coalesced
 // across the block, so each volume is read exactly once.  The stage bodies
@@ -34,6 +37,41 @@ __global__ __launch_bounds__(256) void k_wta4(const float* __restrict__ aggL,
         dco::wta_quad(aggR, P, D, i4, subpixel, dR, nullptr);
 }
 
+__global__ __launch_bounds__(256) void k_wta_pairs(const float* __restrict__ aggL,
+                                                   const float* __restrict__ aggR, int P, int D,
+                                                   int subpixel, int16_t* __restrict__ dL,
+                                                   float* __restrict__ deltaL,
+                                                   int16_t* __restrict__ dR) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= P) return;
+    if (blockIdx.y == 0)
+        dco::wta_pairs_pixel(aggL, P, D, i, subpixel, dL + i, deltaL + i);
+    else
+        dco::wta_pairs_pixel(aggR, P, D, i, subpixel, dR + i, nullptr);
+}
+
+__global__ __launch_bounds__(256) void k_wta_pairs4(const float* __restrict__ aggL,
+                                                    const float* __restrict__ aggR, int P, int D,
+                                                    int subpixel, int16_t* __restrict__ dL,
+                                                    float* __restrict__ deltaL,
+                                                    int16_t* __restrict__ dR) {
+    const int i4 = (blockIdx.x * 256 + threadIdx.x) * 4;
+    if (i4 >= P) return;
+    if (blockIdx.y == 0)
+        dco::wta_pairs_quad(aggL, P, D, i4, subpixel, dL, deltaL);
+    else
+        dco::wta_pairs_quad(aggR, P, D, i4, subpixel, dR, nullptr);
+}
+
+// Slices d0 .. d0 + n - 1 of a paired-layout volume, decoded to n x P.
+__global__ __launch_bounds__(256) void k_unpair(const float* __restrict__ vol, int P, int D,
+                                                int d0, int n, float* __restrict__ out) {
+    const size_t k = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= (size_t)n * P) return;
+    const int s = (int)(k / P), i = (int)(k - (size_t)s * P);
+    out[k] = dco::paired_at(vol, P, D, d0 + s, i);
+}
+
 __global__ __launch_bounds__(256) void k_lrcheck(const int16_t* __restrict__ dL,
                                                  const float* __restrict__ deltaL,
                                                  const int16_t* __restrict__ dR, int W, int H,
@@ -59,6 +97,32 @@ hipError_t launch_wta2(const float* aggL, const float* aggR, int W, int H, int D
         hipLaunchKernelGGL(k_wta, grid, dim3(256), 0, st, aggL, aggR, P, D, subpixel, dL, deltaL,
                            dR);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_wta_pairs(const float* aggL, const float* aggR, int W, int H, int D,
+                            int subpixel, int16_t* dL, float* deltaL, int16_t* dR,
+                            hipStream_t st) {
+    const int P = W * H;
+    const bool aligned = ((uintptr_t)aggL | (uintptr_t)aggR | (uintptr_t)deltaL) % 16 == 0 &&
+                         ((uintptr_t)dL | (uintptr_t)dR) % 8 == 0;
+    if (P % 4 == 0 && aligned) {
+        dim3 grid((P / 4 + 255) / 256, 2);
+        hipLaunchKernelGGL(k_wta_pairs4, grid, dim3(256), 0, st, aggL, aggR, P, D, subpixel, dL,
+                           deltaL, dR);
+    } else {
+        dim3 grid((P + 255) / 256, 2);
+        hipLaunchKernelGGL(k_wta_pairs, grid, dim3(256), 0, st, aggL, aggR, P, D, subpixel, dL,
+                           deltaL, dR);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_unpair(const float* vol, int W, int H, int D, int d0, int n, float* out,
+                         hipStream_t st) {
+    const size_t total = (size_t)n * W * H;
+    hipLaunchKernelGGL(k_unpair, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, vol,
+                       W * H, D, d0, n, out);
     return hipGetLastError();
 }
 
