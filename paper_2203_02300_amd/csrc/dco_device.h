@@ -1005,14 +1005,15 @@ __device__ inline void ws_row_phase(const AggArgs& A, int ys, int y0, int y1, in
     const int y2 = ys + kAggK * (p - 2) + w - 2 * kLMax - 1;
     if (p >= 2 && y2 >= y0 && y2 < y1) {  // uniform
         if (R.paired && R.nout == kWsSlices) {  // uniform: the pair's minimum first
+            // div_q20 of an unsigned sum is never negative nor -0, so the bits
+            // order like the values, and bit 31 of b1 - b0 is set exactly when
+            // b1 < b0 (the second slice strictly smaller)
 #pragma unroll
             for (int j = 0; j < kSeg; ++j) {
-                const bool second = out[1][j] < out[0][j];
-                const float lo = second ? out[1][j] : out[0][j], hi = second ? out[0][j] : out[1][j];
-                out[0][j] = __builtin_bit_cast(
-                    float, (__builtin_bit_cast(uint32_t, lo) & 0x7fffffffu) |
-                               (second ? 0x80000000u : 0u));
-                out[1][j] = hi;
+                const uint32_t b0 = __builtin_bit_cast(uint32_t, out[0][j]);
+                const uint32_t b1 = __builtin_bit_cast(uint32_t, out[1][j]);
+                out[0][j] = __builtin_bit_cast(float, ((b1 - b0) & 0x80000000u) | min(b0, b1));
+                out[1][j] = __builtin_bit_cast(float, max(b0, b1));
             }
         }
 #pragma unroll
