@@ -6,8 +6,9 @@
   Eq. 4 vote passes.
 * The aggregated volumes the one-call match leaves in its scratch (Eq. 2 as
   two stages, cost fused into the aggregation), element by element: every
-  slice of both views at 640x480 D = 64, and bands of rows at 1280x720
-  D = 128 (top, middle, bottom) against the oracle run on the band.
+  slice of both views at 640x480 D = 64 and at 437x93 with an odd D = 37,
+  and bands of rows at 1280x720 D = 128 (top, middle, bottom) against the
+  oracle run on the band.
 * All 32 pairs of the batched workload against the oracle (not only against
   the one-call match).
 Tolerance 0 everywhere: the parity contract of this path is bit-exact.
@@ -86,6 +87,33 @@ def test_fused_volume_c2_every_slice():
     st = oracle.stages(L, R, D)
     assert _diff(_bits(aL), _bits(st["aggL"])) == 0
     assert _diff(_bits(aR), _bits(st["aggR"])) == 0
+
+
+def test_fused_volume_odd_range_every_slice():
+    """An odd disparity range: the last slice has no partner in the paired
+    slice order of the scratch volumes.  Every slice of both views (decoded by
+    the slice export), dL, dR, disp and valid against the oracle."""
+    import torch
+    from paper_2203_02300_amd import StereoMatcher
+    L, R, _ = case("ragged")
+    H, W = L.shape[:2]
+    D = 37
+    print(f"fused volume {W}x{H} D={D}: GPU", flush=True)
+    with StereoMatcher(W, H, D) as m:
+        disp, valid = m.match(dev(L), dev(R))
+        dL, dR = m.last_disparities()
+        aL, aR = host(m.agg_slices(0)), host(m.agg_slices(1))
+        last = host(m.agg_slices(0, D - 1, 1))
+        torch.cuda.synchronize()
+        gd, gv, gdl, gdr = host(disp), host(valid), host(dL), host(dR)
+    print(f"fused volume {W}x{H} D={D}: oracle", flush=True)
+    st = oracle.stages(L, R, D)
+    assert _diff(_bits(aL), _bits(st["aggL"])) == 0
+    assert _diff(_bits(aR), _bits(st["aggR"])) == 0
+    assert _diff(_bits(last[0]), _bits(st["aggL"][D - 1])) == 0
+    assert _diff(gdl, st["dL"]) == 0 and _diff(gdr, st["dR"]) == 0
+    assert _diff(gv, st["valid"]) == 0
+    assert _diff(_bits(gd), _bits(st["disp"])) == 0
 
 
 def test_fused_volume_c3_bands():
