@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void k_geometry(const uint32_t* __restrict__ a
 
 // Both views of the one-call path in one launch each (blockIdx.z = view);
 // one thread per pixel of a tile.
-__global__ __launch_bounds__(1024) void k_census_arms2(const uint8_t* __restrict__ rgbL,
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_census_arms2(const uint8_t* __restrict__ rgbL,
                                                       const uint8_t* __restrict__ rgbR, int W,
                                                       int H, int cw, int ch, int L1, int tau1,
                                                       uint32_t* __restrict__ armsL,
