@@ -211,6 +211,34 @@ __device__ inline double wave_scan_f64(double v) {
     return v;
 }
 
+// The same scan and lane read on exact 64-bit integers.
+template <unsigned Ctrl, unsigned RowMask>
+__device__ inline long long dpp_i64(long long v) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, Ctrl, RowMask,
+                                                              0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), Ctrl,
+                                                              RowMask, 0xf, false);
+    return (long long)((uint64_t)hi << 32 | lo);
+}
+
+__device__ inline long long wave_scan_i64(long long v) {
+    v += dpp_i64<0x111, 0xf>(v);
+    v += dpp_i64<0x112, 0xf>(v);
+    v += dpp_i64<0x114, 0xf>(v);
+    v += dpp_i64<0x118, 0xf>(v);
+    v += dpp_i64<0x142, 0xa>(v);
+    v += dpp_i64<0x143, 0xc>(v);
+    return v;
+}
+
+__device__ inline long long readlane_i64(long long v, int l) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return (long long)((uint64_t)hi << 32 | lo);
+}
+
 // The prefix phase of a row pass works on 256-column chunks in which lane
 // `lane` owns the four consecutive columns x0 + 4 lane .. x0 + 4 lane + 3:
 // a lane prefixes its four values in FP64, one wavefront scan over the lane
@@ -465,7 +493,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_seed_adj(
     const size_t P = (size_t)W * g.H;
     const int nrows = g.B * g.D * g.H;
     const int r0 = (blockIdx.x * kRowWaves + w) * kRowsPerWave;
-    const int c = (W + 63) / 64, x0r = lane * c, nr = max(0, min(c, W - x0r));
+    const bool vec = (W & 3) == 0;  // 16-byte aligned rows
     for (int rid = r0; rid < min(nrows, r0 + kRowsPerWave); ++rid) {
         int b, d, y;
         row_of(rid, g.D, g.H, b, d, y);
@@ -531,22 +559,34 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_seed_adj(
             }
         });
         __builtin_amdgcn_wave_barrier();
-        // prefix of the difference array: each lane a contiguous run, run
-        // totals scanned across the wavefront (exact integers)
-        long long run = 0;
-        for (int k = 0; k < nr; ++k) run += Dq[x0r + k];
-        long long inc = run;
-        for (int off = 1; off < 64; off <<= 1) {
-            const long long v = __shfl_up(inc, off, 64);
-            if (lane >= off) inc += v;
-        }
-        long long p = inc - run;
-        for (int k = 0; k < nr; ++k) {
-            p += Dq[x0r + k];
-            row[x0r + k] = (float)((double)p * down);
+        // prefix of the difference array (exact integers) in 256-column
+        // chunks, a lane owning four consecutive columns: a local prefix, one
+        // wavefront scan of the lane totals, and the outputs stored straight
+        // from registers (16-byte stores when rows are 16-byte aligned)
+        long long carry = 0;
+        for (int x0 = 0; x0 < W; x0 += kPreChunk) {
+            const int x = x0 + 4 * lane;
+            long long sk[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sk[k] = x + k < W ? Dq[min(x + k, W - 1)] : 0;
+#pragma unroll
+            for (int k = 1; k < 4; ++k) sk[k] += sk[k - 1];
+            const long long inc = wave_scan_i64(sk[3]);
+            const long long before = carry + (inc - sk[3]);
+            float o[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) o[k] = (float)((double)(before + sk[k]) * down);
+            if (vec) {
+                if (x < W)
+                    *reinterpret_cast<float4*>(out + base + x) = make_float4(o[0], o[1], o[2], o[3]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (x + k < W) out[base + x + k] = o[k];
+            }
+            carry += readlane_i64(inc, 63);
         }
         __builtin_amdgcn_wave_barrier();
-        for (int x = lane; x < W; x += 64) out[base + x] = row[x];
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
         if (lane == 0) partT[rid] = acc;
         __builtin_amdgcn_wave_barrier();
