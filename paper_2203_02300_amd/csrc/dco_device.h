@@ -955,7 +955,10 @@ __device__ inline void ws_row_phase(const AggArgs& A, int ys, int y0, int y1, in
         e2[0][j] = a.x - b.x;
         e2[1][j] = a.y - b.y;
     }
-    // step 1 of chunk p: raw costs of Eq. 1 (rows below the image give 0)
+    // step 1 of chunk p: raw costs of Eq. 1.  Rows below the image load row
+    // H - 1 and are not masked: prefixes are modular and every range of a
+    // stored output ends inside the image (arms stop at the border), so those
+    // rows only change prefixes past the last row any stored output reads.
     uint32_t q[kWsSlices][kSeg];
 #pragma unroll
     for (int j = 0; j < kSeg; ++j) {
@@ -978,12 +981,10 @@ __device__ inline void ws_row_phase(const AggArgs& A, int ys, int y0, int y1, in
     asm volatile(""
                  : "+v"(q[0][0]), "+v"(q[0][1]), "+v"(q[0][2]), "+v"(q[0][3]), "+v"(q[1][0]),
                    "+v"(q[1][1]), "+v"(q[1][2]), "+v"(q[1][3]));
-    const uint32_t inside = ys + kAggK * p + w < A.H ? ~0u : 0u;  // uniform
 #pragma unroll
     for (int j = 0; j < kSeg; ++j)
 #pragma unroll
-        for (int s = 0; s < kWsSlices; ++s)
-            q[s][j] = (ln.pok[s][j] ? q[s][j] : ln.inval[j]) & inside;
+        for (int s = 0; s < kWsSlices; ++s) q[s][j] = ln.pok[s][j] ? q[s][j] : ln.inval[j];
     // step 3: row prefixes of E2 in this wavefront's row, then the horizontal
     // range sums and the final division
     ws_scan_row(e2, row);
