@@ -862,16 +862,6 @@ __global__ __launch_bounds__(256) void k_soft_argmin(SoftGeom g, const float* __
     lse[(size_t)b * P + i] = m + logf(z);
 }
 
-// Adjoint of a row range sum: out(x') = sum over x with x' in [x - l(x), x + r(x)]
-// of in(x).  The candidates are x in [x' - kLMax, x' + kLMax].
-
-// Adjoint of a column range sum, then an optional per-pixel scale:
-// out(x, y') = scale(x, y') * sum over y with y' in [y - u(y), y + dn(y)] of in(x, y).
-
-// Last adjoint (row direction, onto the raw costs) fused with the lambda
-// derivatives: per-block partial sums of G_c dc/dlambda_AD and G_c dc/dlambda_c.
-
-// Final fixed-order reduction of the partial sums into grad_theta (float).
 // Two-level fixed-order reduction of the gradient partial sums: block k of
 // kRedBlocks sums a contiguous chunk of the per-row lambda partials and of
 // the per-block temperature partials; then one block sums the block totals.
