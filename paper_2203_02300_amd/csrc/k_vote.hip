@@ -10,16 +10,20 @@
 // thread per pixel.  The tile's votes plus a kLMax apron on every side
 // (50 x 50 int16) and the horizontal arms of the tile columns over the apron
 // rows go to LDS, and each staged row is run-length coded once (runs of equal
-// votes: start column, value, and the run of each column).  Every thread then
-// counts its own region into its own counters: a segment adds, for each run
-// it meets, the overlap length to the run's value.  Counters cover a window
-// of kVBins disparities at a time (16-bit, one set per wavefront,
-// lane-interleaved so that the 64 lanes' counters of one disparity are 128
-// contiguous bytes: no bank conflicts whatever the disparities); the windows
-// step from the smallest to the largest vote staged for the tile, and the
-// running maximum keeps the smallest disparity among equal counts.  All
-// counts are integers, so the result does not depend on the order of the
-// additions.
+// votes: start column, value, and the run of each column).  A pixel's region
+// is the union of the horizontal segments of the rows on its vertical arm,
+// and the segment of (column, row) is the same for every pixel whose arm
+// covers that row; so the votes are counted once per segment: for a window
+// of kVBins disparities at a time, each of the 50 x 16 segments adds, for
+// every run it meets, the overlap length to its own counters; the counters
+// are then prefix-summed down each tile column, and a pixel reads its counts
+// as the difference of two prefix rows (the ends of its vertical arm).
+// Counters are 16-bit, two per 32-bit word (a count is at most 51 rows x 35
+// columns, so packed sums and differences never carry between the halves).
+// The windows step from the smallest to the largest vote staged for the
+// tile; a strict running maximum keeps the smallest disparity among equal
+// counts.  All counts are integers, so the result does not depend on the
+// order of the additions.
 #include "dco_device.h"
 
 namespace {
@@ -30,18 +34,24 @@ constexpr int kVWaves = kVThreads / 64;
 constexpr int kVR = kVT + 2 * kLMax;        // staged side
 constexpr int kVStride = kVR + 2;
 
-constexpr int kVBins = 64;  // disparities per counter window
+constexpr int kVBins = 16;               // disparities per counter window
+constexpr int kVWords = kVBins / 2;      // two 16-bit counters per word
+constexpr int kVWordStride = kVWords + 1;  // per tile column (odd: no bank conflicts)
+constexpr int kVSegs = kVR * kVT;        // segments: staged rows x tile columns
 constexpr int kVStage = (kVR * kVR + kVThreads - 1) / kVThreads;
 constexpr int kVArms = (kVR * kVT + kVThreads - 1) / kVThreads;
+static_assert(kVBins % 2 == 0 && kVR * 35 < 65536, "packed 16-bit counters");
 
 struct VoteLds {
-    __align__(16) uint16_t hist[kVWaves][kVBins * 64];  // per wavefront: [bin][lane]
-    int16_t d[kVR][kVStride];                           // votes of the staged region (-1: none)
-    int16_t rv[kVR][kVR];                               // value of run k of each staged row
-    uint8_t rs[kVR][kVR + 2];                           // run of each column
-    uint8_t st[kVR][kVR + 2];                           // start column of run k; st[nruns] = kVR
-    uint8_t l[kVR][kVT], r[kVR][kVT];                   // horizontal arms of the tile columns
-    int lo[kVWaves], hi[kVWaves];                       // vote range seen by each wavefront
+    // cnt[r][c][k]: for tile column c and the window's bins 2k, 2k + 1, the
+    // votes over the segments of staged rows 0 .. r - 1 (row 0: none)
+    uint32_t cnt[kVR + 1][kVT][kVWordStride];
+    int16_t d[kVR][kVStride];   // votes of the staged region (-1: none)
+    int16_t rv[kVR][kVR];       // value of run k of each staged row
+    uint8_t rs[kVR][kVR + 2];   // run of each column
+    uint8_t st[kVR][kVR + 2];   // start column of run k; st[nruns] = kVR
+    uint8_t l[kVR][kVT], r[kVR][kVT];  // horizontal arms of the tile columns
+    int lo[kVWaves], hi[kVWaves];      // vote range seen by each wavefront
 };
 
 __device__ inline int wave_min(int v) {
@@ -147,33 +157,55 @@ __global__ __launch_bounds__(kVThreads) void k_vote(const int16_t* __restrict__ 
     const int mine = S.d[ty + kLMax][tx + kLMax];
     const uint32_t a = in ? arms[(size_t)y * W + x] : 0u;
     const int u = min((int)((a >> 16) & 0xff), kLMax), dn = min((int)(a >> 24), kLMax);
-    uint16_t* hist = S.hist[w];
+    // this pixel's vertical arm in staged rows: prefix rows r0 (before it)
+    // and r1 (through its last row)
+    const int r0 = ty + kLMax - u, r1 = ty + kLMax + dn + 1;
     int best = 0, bc = -1;
     for (int base = vlo; base <= vhi; base += kVBins) {  // uniform
-        // bins past vhi get no votes: clear and scan only the nb in range
-        const int nb = min(kVBins, vhi - base + 1);
-        for (int i = lane; i < nb * 64 / 8; i += 64)
-            reinterpret_cast<uint4*>(hist)[i] = make_uint4(0, 0, 0, 0);
-        __syncthreads();
-        if (mine >= 0) {
-            for (int k = -u; k <= dn; ++k) {
-                const int ry = ty + kLMax + k;
-                const int lo = tx + kLMax - S.l[ry][tx], hi = tx + kLMax + S.r[ry][tx];
-                const int k1 = S.rs[ry][hi];
-                for (int j = S.rs[ry][lo]; j <= k1; ++j) {
-                    const int b = S.rv[ry][j] - base;
-                    if (b >= 0 && b < nb) {
-                        const int s0 = max((int)S.st[ry][j], lo);
-                        const int s1 = min((int)S.st[ry][j + 1] - 1, hi);
-                        hist[b * 64 + lane] += (uint16_t)(s1 - s0 + 1);
-                    }
+        const int nb = min(kVBins, vhi - base + 1);      // bins past vhi get no votes
+        // 1. each segment's counts (one thread per segment; row 0 is zero)
+        for (int i = tid; i < kVT * kVWords; i += kVThreads) S.cnt[0][i / kVWords][i % kVWords] = 0u;
+        for (int sg = tid; sg < kVSegs; sg += kVThreads) {
+            const int ry = sg / kVT, cx = sg - ry * kVT;
+            uint32_t* c = S.cnt[ry + 1][cx];
+#pragma unroll
+            for (int k = 0; k < kVWords; ++k) c[k] = 0u;
+            uint16_t* c16 = reinterpret_cast<uint16_t*>(c);
+            const int lo = cx + kLMax - S.l[ry][cx], hi = cx + kLMax + S.r[ry][cx];
+            const int k1 = S.rs[ry][hi];
+            for (int j = S.rs[ry][lo]; j <= k1; ++j) {
+                const int b = S.rv[ry][j] - base;
+                if (b >= 0 && b < nb) {
+                    const int s0 = max((int)S.st[ry][j], lo);
+                    const int s1 = min((int)S.st[ry][j + 1] - 1, hi);
+                    c16[b] = (uint16_t)(c16[b] + (s1 - s0 + 1));
                 }
             }
-            for (int b = 0; b < nb; ++b) {
-                const int c = hist[b * 64 + lane];
-                if (c > bc) {
-                    bc = c;
-                    best = base + b;
+        }
+        __syncthreads();
+        // 2. prefix sums down each tile column, a (column, word) per thread
+        for (int i = tid; i < kVT * kVWords; i += kVThreads) {
+            const int cx = i / kVWords, k = i % kVWords;
+            uint32_t run = 0u;
+#pragma unroll 10
+            for (int ry = 1; ry <= kVR; ++ry) {
+                run += S.cnt[ry][cx][k];
+                S.cnt[ry][cx][k] = run;
+            }
+        }
+        __syncthreads();
+        // 3. this pixel's counts: two prefix rows per word
+        if (mine >= 0) {
+            for (int k = 0; 2 * k < nb; ++k) {
+                const uint32_t w = S.cnt[r1][tx][k] - S.cnt[r0][tx][k];
+                const int c0 = (int)(w & 0xffffu), c1 = (int)(w >> 16);
+                if (c0 > bc) {
+                    bc = c0;
+                    best = base + 2 * k;
+                }
+                if (2 * k + 1 < nb && c1 > bc) {
+                    bc = c1;
+                    best = base + 2 * k + 1;
                 }
             }
         }
