@@ -111,9 +111,10 @@ static int lmin_of(const uint8_t* a) {
 }
 
 /* Raw matching cost, Eq. 1, in fixed point.
- * READING: each term is an IEEE float product (no fused multiply-add), scaled
- * by 2^20 and rounded to the nearest integer (ties to even):
+ * READING: each term is the exact product of its two FP32 factors, scaled by
+ * 2^20 and rounded once to the nearest integer (ties to even):
  *   q = rint(alpha[Lmin] * TA[s] * 2^20) + rint(beta[Lmin] * TC[h] * 2^20).
+ * The product of two floats is exact in double, and so is the scaling.
  * The stored cost is q * 2^-20.  ref = 0: reference = left view, partner at
  * x - d in the right view; ref = 1: reference = right view, partner at x + d
  * in the left view.  A partner outside the image costs q = 2^20 (cost 1, the
@@ -142,10 +143,8 @@ void orc_cost(int ref, const uint8_t* rgbL, const uint8_t* rgbR, const uint64_t*
                     int h = 0;
                     for (int k = 0; k < 64; ++k) h += (int)((xr >> k) & 1u);
                     int L = lmin_of(arms_ref + 4 * (y * W + x));
-                    float pa = alpha[L] * TA[s];
-                    float pc = beta[L] * TC[h];
-                    float qa = rintf(pa * 1048576.0f);
-                    float qc = rintf(pc * 1048576.0f);
+                    double qa = rint((double)alpha[L] * (double)TA[s] * 1048576.0);
+                    double qc = rint((double)beta[L] * (double)TC[h] * 1048576.0);
                     v = (int32_t)qa + (int32_t)qc;
                 }
                 q[((size_t)d * H + y) * W + x] = v;

@@ -476,6 +476,14 @@ __device__ inline void lds_st(uint32_t* base, uint32_t byte_off, uint32_t v) {
     *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 
+// One Q20 term of Eq. 1, rint(a t) rounded once from the exact product of
+// the float factors (a carries the 2^20 scale), for 0 <= a t < 2^22: the
+// fused a t + 2^23 rounds to 2^23 + rint(a t), whose float bits are
+// 0x4B000000 + rint(a t).
+__device__ inline uint32_t q20_term(float a, float t) {
+    return __builtin_bit_cast(uint32_t, __builtin_fmaf(a, t, 0x1p23f)) - 0x4B000000u;
+}
+
 // RN((float)s / N) * 2^-20 given N' = N * 2^20 and y' = RN(1/N) * 2^-20.
 // With y = RN(1/N): q0 = RN(s * y) is within two ulps of s/N, r = s - q0 * N
 // is then exact, and s/N is never a float midpoint for integer N, so
@@ -606,9 +614,7 @@ __device__ inline void process_chunk(const AggArgs& A, int yc, int y0, int y1, c
                     const uint32_t h = (uint32_t)__popcll(x);
                     const float2 ab = *reinterpret_cast<const float2*>(
                         reinterpret_cast<const char*>(S.ab) + in.ref[j].w);
-                    const float qa = __builtin_rintf(ab.x * S.tabA[s]);
-                    const float qc = __builtin_rintf(ab.y * S.tabC[h]);
-                    uint32_t q = (uint32_t)(qa + qc);
+                    uint32_t q = q20_term(ab.x, S.tabA[s]) + q20_term(ab.y, S.tabC[h]);
                     // keep the lookups unconditional (interleaved across
                     // segments); the select is then one lane-mask cndmask
                     asm volatile("" : "+v"(q));
@@ -970,11 +976,7 @@ __device__ inline void ws_row_phase(const AggArgs& A, int ys, int y0, int y1, in
             const uint32_t sad = __builtin_amdgcn_sad_u8(in.ref[j].z, in.par[s][j].z, 0u);
             const uint64_t x = rc ^ ((uint64_t)in.par[s][j].y << 32 | in.par[s][j].x);
             const uint32_t h = (uint32_t)__popcll(x);
-            // RN(x + 2^23) = 2^23 + rint(x) for 0 <= x < 2^22, so the float
-            // bits minus those of 2^23 are rint(x)
-            const float ta = ab.x * S.tabA[sad], tc = ab.y * S.tabC[h];
-            q[s][j] = __builtin_bit_cast(uint32_t, ta + 0x1p23f) +
-                      __builtin_bit_cast(uint32_t, tc + 0x1p23f) - 2u * 0x4B000000u;
+            q[s][j] = q20_term(ab.x, S.tabA[sad]) + q20_term(ab.y, S.tabC[h]);
         }
     }
     // every lookup stays unconditional; the selects are lane-mask cndmasks

@@ -1,14 +1,16 @@
 // k_cost.hip -- raw AD-census cost volume of one reference view (Eq. 1) in
 // fixed point: q = rint(alpha_L * TA[s] * 2^20) + rint(beta_L * TC[h] * 2^20),
-// stored as q * 2^-20.
+// each term rounded once from the exact product of its float factors, stored
+// as q * 2^-20.
 //
 // One workgroup = one image row, 256 consecutive reference pixels and a chunk
 // of kDC disparities.  The partner row segment those pixels can reach (packed
 // RGB and census codes) is staged in LDS together with the two lookup tables,
 // so the inner loop is: one SAD of packed bytes (v_sad_u8), two popcounts,
-// two table reads, two float products, two round-to-nearest-even, one store.
+// two table reads, two fused multiply-adds that round the products to
+// integers, one store.
 // Stores are coalesced along x for each d.
-#include "dco_internal.h"
+#include "dco_device.h"
 
 namespace {
 
@@ -74,9 +76,7 @@ __global__ __launch_bounds__(256) void k_cost(int ref, const uint8_t* __restrict
             const uint32_t s = __builtin_amdgcn_sad_u8(crgb, s_prgb[i], 0u);
             const uint64_t xr = ccen ^ s_pcen[i];
             const int h = __popcll(xr);
-            const float qa = __builtin_rintf(al * s_tabA[s]);
-            const float qc = __builtin_rintf(be * s_tabC[h]);
-            v = (qa + qc) * 0x1p-20f;
+            v = (float)(dco::q20_term(al, s_tabA[s]) + dco::q20_term(be, s_tabC[h])) * 0x1p-20f;
         }
         cost[(size_t)d * slice + pix] = v;
     }
