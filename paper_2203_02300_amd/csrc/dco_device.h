@@ -1355,7 +1355,7 @@ __device__ inline void wta_pairs_quad(const float* __restrict__ vol, int P, int 
                      __builtin_bit_cast(float, w0.z & 0x7fffffffu),
                      __builtin_bit_cast(float, w0.w & 0x7fffffffu)};
     int bd[4] = {(int)(w0.x >> 31), (int)(w0.y >> 31), (int)(w0.z >> 31), (int)(w0.w >> 31)};
-    constexpr int U = 8;
+    constexpr int U = 16;  // 16 loads in flight per thread
     int g = 1;
     for (; g + U <= G; g += U) {
         u32x4 v[U];
