@@ -61,20 +61,28 @@ __device__ inline bool close_rgb(const Centre& c, uint32_t b) {
 // Census code of tile pixel (tx, ty) from the grey levels in LDS: bit k is
 // set when neighbour k (row-major over the window, centre skipped) is darker
 // than the centre.  The fixed-size form unrolls, so its LDS reads pipeline.
+// Grey levels are below 256, so n - c is negative exactly when n < c: each
+// bit enters as the sign of n - c with one funnel shift (alignbit), from the
+// last neighbour back to the first, the upper bits in one word and the lower
+// in another.
 template <int HW, int HH>
 __device__ inline uint64_t census_code(const CensusLds& S, int tx, int ty) {
+    constexpr int kBits = (2 * HW + 1) * (2 * HH + 1) - 1;
+    static_assert(kBits <= 64, "one 64-bit code");
     const uint32_t c = S.grey[ty + kCenHH][tx + kCenHW];
-    uint64_t code = 0;
-    int bit = 0;
+    uint32_t hi = 0, lo = 0;
 #pragma unroll
-    for (int dy = -HH; dy <= HH; ++dy)
-#pragma unroll
-        for (int dx = -HW; dx <= HW; ++dx) {
-            if (dy == 0 && dx == 0) continue;
-            code |= (uint64_t)(S.grey[ty + kCenHH + dy][tx + kCenHW + dx] < c) << bit;
-            ++bit;
-        }
-    return code;
+    for (int k = kBits - 1; k >= 0; --k) {
+        constexpr int kCentre = HH * (2 * HW + 1) + HW;
+        const int n = k < kCentre ? k : k + 1;  // window index, centre skipped
+        const int dy = n / (2 * HW + 1) - HH, dx = n % (2 * HW + 1) - HW;
+        const uint32_t d = S.grey[ty + kCenHH + dy][tx + kCenHW + dx] - c;
+        if (k >= 32)
+            hi = __builtin_amdgcn_alignbit(hi, d, 31);
+        else
+            lo = __builtin_amdgcn_alignbit(lo, d, 31);
+    }
+    return (uint64_t)hi << 32 | lo;
 }
 
 __device__ inline uint64_t census_code_any(const CensusLds& S, int tx, int ty, int hw, int hh) {
