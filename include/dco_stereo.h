@@ -110,8 +110,9 @@ dco_status dco_census(dco_stereo* h, const uint8_t* rgb, uint64_t* census, uint8
  *   q = rint(alpha_L * TA[s] * 2^20) + rint(beta_L * TC[h] * 2^20)
  * with float tables alpha_L = 1 - exp(-gamma_L / (L + eps)), beta_L =
  * exp(-gamma_L / (L + eps)), TA[s] = 1 - exp(-s / (3 lambda_AD)), TC[h] =
- * 1 - exp(-h / lambda_census), each rounded once from double, float products,
- * round-half-even.  A partner outside the image gives q = 2^20.
+ * 1 - exp(-h / lambda_census), each rounded once from double; each term is
+ * rounded once (half to even) from the exact product of its float factors.
+ * A partner outside the image gives q = 2^20.
  * cost[d][y][x] = q * 2^-20 (D x H x W float, out). */
 dco_status dco_cost_volume(dco_stereo* h, int ref, const uint8_t* rgbL, const uint8_t* rgbR,
                            const uint64_t* cenL, const uint64_t* cenR, const uint8_t* arms_ref,
