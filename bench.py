@@ -326,6 +326,9 @@ def main():
     if not args.no_cpu:
         log(f"bench: CPU oracle on {args.cpu_rows} rows")
         cpu = cpu_baseline(L, R, D, args.cpu_rows)
+        if "sizes" in want:
+            log("bench: CPU oracle at 64x48 D=16 and 640x480 D=64 (whole frames, one thread)")
+            extras["sizes_oracle"] = _guarded(sizes_oracle)
         log("bench: CPU oracle on all cores (row bands)")
         res = _guarded(cpu_all_cores, L, R, D)
         if isinstance(res, tuple):
@@ -449,6 +452,33 @@ def sizes_extras(steps):
         ms = _time(lambda: m.match(L, R, disp, valid), steps)
         m.close()
         out[name] = dict(ms_per_frame=round(ms, 4), Mpix_disp_s=round(W * H * D / ms / 1e3, 1))
+    return out
+
+
+def sizes_oracle():
+    """CPU leg at the two smaller workloads: the oracle on one thread over the
+    whole frame (timed), and the one-call match's maps against it, bit for
+    bit."""
+    import torch
+    import oracle
+    from paper_2203_02300_amd import StereoMatcher, synth
+    out = {}
+    for name, pair, D in (("64x48 D=16", synth.config_c1(), 16),
+                          ("640x480 D=64", synth.config_c2(), 64)):
+        H, W = pair["left"].shape[:2]
+        with StereoMatcher(W, H, D) as m:
+            disp, valid = m.match(torch.from_numpy(pair["left"]).cuda(),
+                                  torch.from_numpy(pair["right"]).cuda())
+            torch.cuda.synchronize()
+            gdisp, gvalid = disp.cpu().numpy(), valid.cpu().numpy()
+        t0 = time.perf_counter()
+        odisp, ovalid, _, _ = oracle.match(pair["left"], pair["right"], D)
+        dt = time.perf_counter() - t0
+        gate = accuracy_gate(gdisp, gvalid, ovalid=ovalid, odisp=odisp)
+        out[name] = dict(oracle_ms_1thread=round(dt * 1e3, 1),
+                         oracle_Mpix_disp_s=round(W * H * D / dt / 1e6, 2),
+                         bit_exact=gate["bit_exact"], mismatched_disp=gate["mismatched_disp"],
+                         mismatched_valid=gate["mismatched_valid"])
     return out
 
 
