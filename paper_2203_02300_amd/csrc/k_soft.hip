@@ -468,6 +468,10 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hgrad(SoftGeom g, SoftI
     }
 }
 
+// e^x as 2^(x log2 e) on the hardware base-2 exponential (about 1 ulp); the
+// rounding of the product adds a relative error of about |x| 2^-24.
+__device__ inline float exp_e(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+
 // Backward seed and adjoint row pass.  Per pixel and disparity, with
 // w = softmax weight and g = dLoss/d dhat:
 //   G_A2 / N2 = g w (dhat - d) / (T N2),   dLoss/dT term = g w (d - dhat) A2 / T^2;
@@ -484,7 +488,8 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_seed_adj(
     const float* __restrict__ gdhat, float* __restrict__ out, double* __restrict__ partT,
     size_t lds_wave) {
     extern __shared__ __align__(16) unsigned char dyn[];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, W = g.W;
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63,
+              W = g.W;
     unsigned char* mine = dyn + w * lds_wave;
     long long* Dq = reinterpret_cast<long long*>(mine);  // W + 1 entries
     float* row = reinterpret_cast<float*>(mine + ((size_t)(W + 1) * 8 + 15) / 16 * 16);
@@ -499,6 +504,13 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_seed_adj(
         row_of(rid, g.D, g.H, b, d, y);
         const size_t base = ((size_t)b * g.D + d) * P + (size_t)y * W;
         const size_t pix = b * P + (size_t)y * W;
+        // the row's inputs through row pointers (uniform), indexed by column
+        const float* __restrict__ a2r = A2 + base;
+        const float* __restrict__ gr = gdhat + pix;
+        const float* __restrict__ dr = dhat + pix;
+        const float* __restrict__ lr0 = lse + pix;
+        const float* __restrict__ nr = g.n2 + pix;
+        const uint32_t* __restrict__ ar = g.arms + pix;
         double acc = 0.0;
         float gmax = 0.0f;
         over_row<4>(W, [&](auto nb, int x0) {
@@ -507,20 +519,20 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_seed_adj(
             uint32_t a[NB];
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
-                const size_t xc = (size_t)min(x0 + 64 * j + lane, W - 1);
-                a2[j] = A2[base + xc];
-                gp[j] = gdhat[pix + xc];
-                dh[j] = dhat[pix + xc];
-                l[j] = lse[pix + xc];
-                n2[j] = g.n2[pix + xc];
-                a[j] = g.arms[pix + xc];
+                const int xc = min(x0 + 64 * j + lane, W - 1);
+                a2[j] = a2r[xc];
+                gp[j] = gr[xc];
+                dh[j] = dr[xc];
+                l[j] = lr0[xc];
+                n2[j] = nr[xc];
+                a[j] = ar[xc];
             }
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 const int x = x0 + 64 * j + lane;
                 if (x < W) {
-                    const float wgt = expf(-a2[j] * invT - l[j]);
-                    const float G = gp[j] * wgt * (dh[j] - (float)d) * invT / n2[j];
+                    const float wgt = exp_e(-a2[j] * invT - l[j]);
+                    const float G = gp[j] * wgt * (dh[j] - (float)d) * invT * __builtin_amdgcn_rcpf(n2[j]);
                     acc += (double)(gp[j] * wgt * ((float)d - dh[j]) * a2[j]) *
                            (double)(invT * invT);
                     row[x] = G;
@@ -845,13 +857,13 @@ __global__ __launch_bounds__(256) void k_soft_argmin(SoftGeom g, const float* __
         float mb = m;
 #pragma unroll
         for (int j = 0; j < kArgBatch; ++j) mb = d0 + j < g.D ? fmaxf(mb, v[j]) : mb;
-        const float sc = expf(m - mb);  // 0 on the first batch (m = -inf)
+        const float sc = exp_e(m - mb);  // 0 on the first batch (m = -inf)
         z *= sc;
         zd *= sc;
 #pragma unroll
         for (int j = 0; j < kArgBatch; ++j) {
             if (d0 + j < g.D) {
-                const float e = expf(v[j] - mb);
+                const float e = exp_e(v[j] - mb);
                 z += e;
                 zd += (float)(d0 + j) * e;
             }
