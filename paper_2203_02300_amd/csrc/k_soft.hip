@@ -367,7 +367,8 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hrow(SoftGeom g, SoftIm
                                                               float* __restrict__ out,
                                                               size_t lds_wave) {
     extern __shared__ __align__(16) unsigned char dyn[];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, W = g.W;
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63,
+              W = g.W;
     float* tab = reinterpret_cast<float*>(dyn);
     double* Pf = reinterpret_cast<double*>(dyn + (kCost ? kTabLds : 0) + w * lds_wave);
     float* stage = reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(Pf) + prefix_bytes(W));
@@ -386,6 +387,10 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hrow(SoftGeom g, SoftIm
         const size_t pix = b * P + (size_t)y * W;
         prefix_row<kCost, false>(im.pixL + pix, im.pixR + pix, in + base, W, d, tab, stage, Pf,
                                  nullptr);
+        // the row's arrays through row pointers (uniform), indexed by column
+        const uint32_t* __restrict__ ar = g.arms + pix;
+        const float* __restrict__ nr = g.n2 + pix;
+        float* __restrict__ orow = out + base;
         over_row(W, [&](auto nb, int x0) {
             constexpr int NB = decltype(nb)::value;
             uint32_t a[NB];
@@ -393,15 +398,15 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hrow(SoftGeom g, SoftIm
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 const int xc = min(x0 + 64 * j + lane, W - 1);
-                a[j] = g.arms[pix + xc];
-                n[j] = kCost ? 1.0f : g.n2[pix + xc];
+                a[j] = ar[xc];
+                n[j] = kCost ? 1.0f : nr[xc];
             }
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 const int x = x0 + 64 * j + lane;
                 if (x < W) {
                     const float v = (float)(Pf[x + arm(a[j], 1) + 1] - Pf[x - arm(a[j], 0)]);
-                    out[base + x] = kCost ? v : v / n[j];
+                    orow[x] = kCost ? v : v / n[j];
                 }
             }
         });
@@ -419,7 +424,8 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hgrad(SoftGeom g, SoftI
                                                                double* __restrict__ part,
                                                                size_t lds_wave) {
     extern __shared__ __align__(16) unsigned char dyn[];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, W = g.W;
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63,
+              W = g.W;
     float* tab = reinterpret_cast<float*>(dyn);
     unsigned char* mine = dyn + kTabLds + w * lds_wave;
     double* Pa = reinterpret_cast<double*>(mine);
@@ -436,6 +442,8 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hgrad(SoftGeom g, SoftI
         const size_t pix = b * P + (size_t)y * W;
         prefix_row<true, true>(im.pixL + pix, im.pixR + pix, nullptr, W, d, tab, stage, Pa, Pc);
         double sa = 0.0, sc = 0.0;
+        const uint32_t* __restrict__ ar = g.arms + pix;
+        const float* __restrict__ grow = G + base;
         over_row(W, [&](auto nb, int x0) {
             constexpr int NB = decltype(nb)::value;
             uint32_t a[NB];
@@ -443,8 +451,8 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hgrad(SoftGeom g, SoftI
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 const int xc = min(x0 + 64 * j + lane, W - 1);
-                a[j] = g.arms[pix + xc];
-                gv[j] = G[base + xc];
+                a[j] = ar[xc];
+                gv[j] = grow[xc];
             }
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
