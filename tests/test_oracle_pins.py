@@ -6,6 +6,7 @@ formulation (vectorised shifts, explicit region enumeration) or the
 real-valued (float64) shadow of Eq. 1 and Eq. 2.
 """
 import math
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -194,6 +195,48 @@ def test_cost_partner_outside_is_one():
         assert np.all(qL[d, :, d:] < Q)
         assert np.all(qR[d, :, W - d:] == Q)
         assert np.all(qR[d, :, :W - d] < Q)
+
+
+def _round_half_even(fr):
+    """Nearest integer to a Fraction, ties to even."""
+    n = math.floor(fr)
+    rest = fr - n
+    if rest > Fraction(1, 2) or (rest == Fraction(1, 2) and n % 2 == 1):
+        n += 1
+    return n
+
+
+def test_cost_terms_round_once_from_the_exact_product():
+    """Reading of the Q20 quantisation of Eq. 1: each term is the exact
+    product of its two float factors, times 2^20, rounded once to the nearest
+    integer (ties to even).  Every (L_min, s) pair with equal census codes
+    (h = 0, so the census term TC[0] = 0 vanishes) against exact rational
+    arithmetic; rounding the float product first differs from it on some of
+    these pairs, so the test tells the two readings apart."""
+    L1 = 17
+    alpha, _, TA, _ = oracle.tables(L1=L1)
+    ns = 766
+    H, W = L1 + 1, ns
+    left = np.zeros((H, W, 3), np.uint8)
+    right = np.zeros((H, W, 3), np.uint8)
+    s = np.arange(ns)
+    right[:, :, 0] = np.minimum(s, 255)
+    right[:, :, 1] = np.clip(s - 255, 0, 255)
+    right[:, :, 2] = np.clip(s - 510, 0, 255)
+    arms = np.repeat(np.arange(H, dtype=np.uint8)[:, None, None], W, axis=1)
+    arms = np.repeat(arms, 4, axis=2)                  # L_min = row index
+    cen = np.zeros((H, W), np.uint64)
+    q = oracle.cost_q(0, left, right, cen, cen, arms, 1, L1=L1)[0]
+    twice = 0
+    for Lm in range(H):
+        a = Fraction(float(alpha[Lm]))
+        for si in range(ns):
+            exact = a * Fraction(float(TA[si])) * (1 << 20)
+            want = _round_half_even(exact)
+            assert q[Lm, si] == want, (Lm, si, q[Lm, si], want)
+            f32 = float(np.float32(alpha[Lm]) * np.float32(TA[si]))
+            twice += _round_half_even(Fraction(f32) * (1 << 20)) != want
+    assert twice > 0
 
 
 def test_cost_within_fixed_point_bound_of_real_eq1():
