@@ -388,7 +388,8 @@ extern "C" dco_status dco_aggregate(dco_stereo* h, const float* cost, const uint
         return DCO_ERR_ARG;
     }
     const uint32_t* arms = (const uint32_t*)arms_ref;
-    DCO_HIP_CHECK(launch_geometry(arms, h->W, h->H, h->p.agg_iters, h->s.rec[0], h->stream));
+    DCO_HIP_CHECK(launch_geometry(arms, h->W, h->H, h->p.agg_iters, h->s.rec[0],
+                                  pair_rec_geom(h->p.agg_iters), h->stream));
     DCO_HIP_CHECK(launch_aggregate(cost, h->s.rec[0], h->W, h->H, h->D, h->p.agg_iters, agg,
                                    h->stream));
     return DCO_OK;

@@ -563,6 +563,8 @@ struct AggLane {
 struct AggRes {
     rsrc_t rB, rC, rq, rIr, rIp, rOut;
     uint32_t slice_bytes;  // two-slice kernel: distance between its output slices
+    uint32_t in_slice_bytes;  // staged two-slice kernel: distance between its input
+                              // slices (0 when only one slice is left: it is read twice)
     int nout;              // two-slice kernel: slices that exist (the others are not stored)
     bool paired;           // two-slice kernel: paired layout (AggArgs::paired)
 };
@@ -869,20 +871,30 @@ struct WsColIn {
 };
 
 struct WsRowLane {
-    uint32_t img[kSeg], par[kWsSlices][kSeg], inval[kSeg], cbs[kSeg], vout[kSeg], recw;
+    uint32_t img[kSeg], col4[kSeg], par[kWsSlices][kSeg], inval[kSeg], cbs[kSeg], vout[kSeg], recw;
     bool pok[kWsSlices][kSeg];
 };
 
 // Row wavefront: loads for phase p (step 1 of chunk p, step 3 of chunk p - 2).
+// kFused: the pixels of both views for the raw cost; else the two slices'
+// raw costs of the row from the cost volume (in the x words of in.par).
+template <bool kFused>
 __device__ inline void ws_row_load(const AggArgs& A, int ys, int p, int w, const WsRowLane& ln,
                                    const AggRes& R, WsRowIn& in) {
     const uint32_t W = (uint32_t)A.W, Wp = (uint32_t)A.rec.Wp;
     const uint32_t yq = (uint32_t)min(ys + kAggK * p + w, A.H - 1);
 #pragma unroll
     for (int j = 0; j < kSeg; ++j) {
-        in.ref[j] = ld128(R.rIr, ln.img[j], yq * W * 16);
+        if constexpr (kFused) {
+            in.ref[j] = ld128(R.rIr, ln.img[j], yq * W * 16);
 #pragma unroll
-        for (int s = 0; s < kWsSlices; ++s) in.par[s][j] = ld128(R.rIp, ln.par[s][j], yq * W * 16);
+            for (int s = 0; s < kWsSlices; ++s)
+                in.par[s][j] = ld128(R.rIp, ln.par[s][j], yq * W * 16);
+        } else {
+#pragma unroll
+            for (int s = 0; s < kWsSlices; ++s)
+                in.par[s][j].x = ld32(R.rq, ln.col4[j], yq * W * 4 + s * R.in_slice_bytes);
+        }
     }
     const int y2 = ys + kAggK * (p - 2) + w - 2 * kLMax - 1;
     const uint32_t rc = (uint32_t)(y2 >= 0 && y2 < A.H ? y2 : A.H);
@@ -951,6 +963,7 @@ __device__ inline void ws_scan_row(const uint32_t (&v)[kWsSlices][kSeg], uint2* 
 }
 
 // Row wavefront w, phase p: step 3 of chunk p - 2 and step 1 of chunk p.
+template <bool kFused>
 __device__ inline void ws_row_phase(const AggArgs& A, int ys, int y0, int y1, int p, int w,
                                     const WsRowLane& ln, const AggRes& R, const WsRowIn& in,
                                     AggLdsWs& S) {
@@ -974,6 +987,15 @@ __device__ inline void ws_row_phase(const AggArgs& A, int ys, int y0, int y1, in
     // stored output ends inside the image (arms stop at the border), so those
     // rows only change prefixes past the last row any stored output reads.
     uint32_t q[kWsSlices][kSeg];
+    if constexpr (!kFused) {
+        // the volume holds q 2^-20 exactly (1.0 where the partner is outside
+        // the image); columns outside the image load 0
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j)
+#pragma unroll
+            for (int s = 0; s < kWsSlices; ++s)
+                q[s][j] = (uint32_t)(__builtin_bit_cast(float, in.par[s][j].x) * 0x1p20f);
+    } else {
 #pragma unroll
     for (int j = 0; j < kSeg; ++j) {
         const uint64_t rc = (uint64_t)in.ref[j].y << 32 | in.ref[j].x;
@@ -995,6 +1017,7 @@ __device__ inline void ws_row_phase(const AggArgs& A, int ys, int y0, int y1, in
     for (int j = 0; j < kSeg; ++j)
 #pragma unroll
         for (int s = 0; s < kWsSlices; ++s) q[s][j] = ln.pok[s][j] ? q[s][j] : ln.inval[j];
+    }
     // step 3: row prefixes of E2 in this wavefront's row, then the horizontal
     // range sums and the final division
     ws_scan_row(e2, row);
@@ -1079,8 +1102,10 @@ __device__ inline void ws_col_phase(int q, int nch, int ct, uint32_t cb, const W
 }
 
 // Output rows [y0, y1) of slices d and d + 1 and column strip `strip`
-// (512 threads; two stages, cost fused); slices at or past dend are computed
-// but not stored.  The records must be written with kRecWs.
+// (512 threads; two stages); slices at or past dend are computed but not
+// stored.  kFused: the raw cost computed from the packed pixels; else read
+// from the cost volume A.cost.  The records must be written with kRecWs.
+template <bool kFused = true>
 __device__ inline void agg_stream_ws(const AggArgs& A, int d, int dend, int strip, int y0, int y1,
                                      AggLdsWs& S) {
     const int W = A.W, H = A.H;
@@ -1089,11 +1114,13 @@ __device__ inline void agg_stream_ws(const AggArgs& A, int d, int dend, int stri
     const int x0 = strip * kStripOut;
     const size_t slice = (size_t)W * H;
 
-    for (int i = t; i < 766; i += kWsThreads) S.tabA[i] = A.tabA[i];
-    if (t < 65) S.tabC[t] = A.tabC[t];
-    if (t <= kLMax) {
-        const int L = min(t, A.L1);
-        S.ab[t] = make_float2(A.alpha[L], A.beta[L]);
+    if constexpr (kFused) {
+        for (int i = t; i < 766; i += kWsThreads) S.tabA[i] = A.tabA[i];
+        if (t < 65) S.tabC[t] = A.tabC[t];
+        if (t <= kLMax) {
+            const int L = min(t, A.L1);
+            S.ab[t] = make_float2(A.alpha[L], A.beta[L]);
+        }
     }
     if (t < 2 * kAggK * kWsP0) {  // P(-1) and the entries before it, every row
         const int r = t / kWsP0;
@@ -1109,10 +1136,12 @@ __device__ inline void agg_stream_ws(const AggArgs& A, int d, int dend, int stri
     const uint4* Ipar = A.ref == 0 ? A.pixR : A.pixL;
     R.rB = make_rsrc(A.rec.b, (uint32_t)(A.rec.Wp * (H + kLMax + 1)) * 16);
     R.rC = make_rsrc(A.rec.c, (uint32_t)(A.rec.Wp * (H + 1)) * 16);
-    R.rq = R.rB;
     R.rIr = make_rsrc(Iref, 4 * P4);
     R.rIp = make_rsrc(Ipar, 4 * P4);
     const int nout = min(kWsSlices, min(A.D, dend) - d);  // slices to store
+    // raw costs of slices d and d + 1; past the last slice, slice d again
+    R.rq = kFused ? R.rB : make_rsrc(A.cost + (size_t)d * slice, (uint32_t)min(kWsSlices, A.D - d) * P4);
+    R.in_slice_bytes = A.D - d >= 2 ? P4 : 0u;
     R.rOut = make_rsrc(A.out + (size_t)d * slice, (uint32_t)nout * P4);
     R.slice_bytes = P4;
     R.nout = nout;
@@ -1132,6 +1161,7 @@ __device__ inline void agg_stream_ws(const AggArgs& A, int d, int dend, int stri
             const int c = x0 - 2 * kLMax + i;       // image column
             const bool in_img = c >= 0 && c < W;
             ln.img[j] = in_img ? (uint32_t)c * 16 : kOOB;
+            ln.col4[j] = in_img ? (uint32_t)c * 4 : kOOB;
 #pragma unroll
             for (int s = 0; s < kWsSlices; ++s) {
                 const int cp = A.ref == 0 ? c - d - s : c + d + s;
@@ -1148,14 +1178,14 @@ __device__ inline void agg_stream_ws(const AggArgs& A, int d, int dend, int stri
         }
         ln.recw = (uint32_t)(x0 - 2 * kLMax + lane + A.rec.apron) * 4;
         WsRowIn ia, ib;
-        ws_row_load(A, ys, 0, w, ln, R, ia);
+        ws_row_load<kFused>(A, ys, 0, w, ln, R, ia);
         for (int p = 0;; p += 2) {
-            ws_row_load(A, ys, p + 1, w, ln, R, ib);
-            ws_row_phase(A, ys, y0, y1, p, w, ln, R, ia, S);
+            ws_row_load<kFused>(A, ys, p + 1, w, ln, R, ib);
+            ws_row_phase<kFused>(A, ys, y0, y1, p, w, ln, R, ia, S);
             __syncthreads();
             if (p + 1 > last) break;
-            ws_row_load(A, ys, p + 2, w, ln, R, ia);
-            ws_row_phase(A, ys, y0, y1, p + 1, w, ln, R, ib, S);
+            ws_row_load<kFused>(A, ys, p + 2, w, ln, R, ia);
+            ws_row_phase<kFused>(A, ys, y0, y1, p + 1, w, ln, R, ib, S);
             __syncthreads();
             if (p + 2 > last) break;
         }

@@ -248,8 +248,10 @@ hipError_t launch_front2(const uint8_t* rgbL, const uint8_t* rgbR, int W, int H,
                          uint4* pixL, uint4* pixR, const AggRecords& recL, const AggRecords& recR,
                          const RecGeom& g, hipStream_t st);
 RecGeom pair_rec_geom(int iters);
+// Records for the aggregation kernels; g = pair_rec_geom(iters) for the
+// kernels of dco_aggregate and dco_stereo_match.
 hipError_t launch_geometry(const uint32_t* arms, int W, int H, int iters, const AggRecords& rec,
-                           hipStream_t st);
+                           const RecGeom& g, hipStream_t st);
 hipError_t launch_cost(int ref, const uint8_t* rgbL, const uint8_t* rgbR, const uint64_t* cenL,
                        const uint64_t* cenR, const uint32_t* arms_ref, int W, int H, int D,
                        const float* tabA, const float* tabC, const float* alpha,

@@ -78,13 +78,16 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_agg_pair(dco::AggArgs A0, 
 }
 
 // Two stages: the same items with two adjacent disparities per item, one
-// 512-thread workgroup per CU (dco::agg_stream_ws).
+// 512-thread workgroup per CU (dco::agg_stream_ws).  kFused: both views, the
+// raw cost computed on the fly; else one view (nviews = 1) from its cost
+// volume A0.cost (the staged dco_aggregate).
+template <bool kFused>
 __global__ __launch_bounds__(dco::kWsThreads, 1) void k_agg_pair_ws(dco::AggArgs A0,
                                                                     AggRecords rec1, float* out1,
-                                                                    int s8) {
+                                                                    int s8, int nviews) {
     __shared__ dco::AggLdsWs S;
     const int groups = (A0.D + dco::kWsSlices - 1) / dco::kWsSlices;
-    const int per_view = A0.nstrips * groups, N = 2 * per_view;
+    const int per_view = A0.nstrips * groups, N = nviews * per_view;
     const int x = blockIdx.x % 8, i = blockIdx.x / 8;
     int start, nx, m;
     pair_part(N, x, s8, A0.H, start, nx, m);
@@ -108,7 +111,7 @@ __global__ __launch_bounds__(dco::kWsThreads, 1) void k_agg_pair_ws(dco::AggArgs
         A.rec = rec1;
         A.out = out1;
     }
-    dco::agg_stream_ws(A, g * dco::kWsSlices, A.D, strip, y0, y1, S);
+    dco::agg_stream_ws<kFused>(A, g * dco::kWsSlices, A.D, strip, y0, y1, S);
 }
 
 // Resident workgroups per XCD of a kernel (queried once per device and
@@ -133,21 +136,22 @@ hipError_t xcd_slots(K kernel, int threads, std::atomic<int>* slots, int* s8) {
     return hipSuccess;
 }
 
-hipError_t launch_pair_ws(const dco::AggArgs& a0, const AggRecords& rec1, float* out1,
+template <bool kFused>
+hipError_t launch_pair_ws(const dco::AggArgs& a0, const AggRecords& rec1, float* out1, int nviews,
                           hipStream_t st) {
     static std::atomic<int> slots[64];
     int s8 = 0;
-    hipError_t e = xcd_slots(k_agg_pair_ws, dco::kWsThreads, slots, &s8);
+    hipError_t e = xcd_slots(k_agg_pair_ws<kFused>, dco::kWsThreads, slots, &s8);
     if (e != hipSuccess) return e;
-    const int N = 2 * a0.nstrips * ((a0.D + dco::kWsSlices - 1) / dco::kWsSlices);
+    const int N = nviews * a0.nstrips * ((a0.D + dco::kWsSlices - 1) / dco::kWsSlices);
     int most = 1;
     for (int x = 0; x < 8; ++x) {
         int start, nx, m;
         pair_part(N, x, s8, a0.H, start, nx, m);
         most = nx + m > most ? nx + m : most;
     }
-    hipLaunchKernelGGL(k_agg_pair_ws, dim3(8 * most), dim3(dco::kWsThreads), 0, st, a0, rec1,
-                       out1, s8);
+    hipLaunchKernelGGL(k_agg_pair_ws<kFused>, dim3(8 * most), dim3(dco::kWsThreads), 0, st, a0,
+                       rec1, out1, s8, nviews);
     return hipGetLastError();
 }
 
@@ -204,7 +208,10 @@ hipError_t launch_aggregate(const float* cost, const AggRecords& rec, int W, int
     a.H = H;
     a.D = D;
     a.nstrips = (W + kStripOut - 1) / kStripOut;
-    return iters == 1 ? launch_stream<1, false>(a, st) : launch_stream<2, false>(a, st);
+    // two stages: the two-slice kernel on the volume (records written with
+    // kRecWs, plain slice order)
+    return iters == 1 ? launch_stream<1, false>(a, st)
+                      : launch_pair_ws<false>(a, rec, out, 1, st);
 }
 
 hipError_t launch_cost_aggregate2(const uint4* pixL, const uint4* pixR, const AggRecords& recL,
@@ -228,7 +235,8 @@ hipError_t launch_cost_aggregate2(const uint4* pixL, const uint4* pixR, const Ag
     a.rec = recL;
     a.out = outL;
     a.paired = paired && iters == 2;
-    return iters == 1 ? launch_pair<1>(a, recR, outR, st) : launch_pair_ws(a, recR, outR, st);
+    return iters == 1 ? launch_pair<1>(a, recR, outR, st)
+                      : launch_pair_ws<true>(a, recR, outR, 2, st);
 }
 
 RecGeom pair_rec_geom(int iters) { return iters == 2 ? dco::kRecWs : dco::kRecPlain; }

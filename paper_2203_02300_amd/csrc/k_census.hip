@@ -17,10 +17,10 @@ __global__ __launch_bounds__(256) void k_census_arms(const uint8_t* __restrict__
 }
 
 __global__ __launch_bounds__(256) void k_geometry(const uint32_t* __restrict__ arms, int W, int H,
-                                                  int iters, AggRecords rec) {
+                                                  int iters, AggRecords rec, RecGeom g) {
     __shared__ dco::GeomLds S;
     dco::geometry_tile(arms, W, H, iters, rec, blockIdx.x * dco::kGeoTW, blockIdx.y * dco::kGeoTH,
-                       S);
+                       S, g);
 }
 
 // Both views of the one-call path in one launch each (blockIdx.z = view);
@@ -105,8 +105,8 @@ hipError_t launch_census_arms(const uint8_t* rgb, int W, int H, int cw, int ch, 
 }
 
 hipError_t launch_geometry(const uint32_t* arms, int W, int H, int iters, const AggRecords& rec,
-                           hipStream_t st) {
+                           const RecGeom& g, hipStream_t st) {
     dim3 grid((W + dco::kGeoTW - 1) / dco::kGeoTW, (H + dco::kGeoTH - 1) / dco::kGeoTH);
-    hipLaunchKernelGGL(k_geometry, grid, dim3(256), 0, st, arms, W, H, iters, rec);
+    hipLaunchKernelGGL(k_geometry, grid, dim3(256), 0, st, arms, W, H, iters, rec, g);
     return hipGetLastError();
 }
