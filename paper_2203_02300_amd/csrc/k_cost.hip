@@ -14,7 +14,7 @@
 
 namespace {
 
-constexpr int kDC = 16;
+constexpr int kDC = 32;
 
 __global__ __launch_bounds__(256) void k_cost(int ref, const uint8_t* __restrict__ rgbL,
                                               const uint8_t* __restrict__ rgbR,
