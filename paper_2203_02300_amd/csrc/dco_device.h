@@ -106,7 +106,7 @@ __device__ inline uint64_t census_code_any(const CensusLds& S, int tx, int ty, i
 //   census: bit k = Y(q_k) < Y(p), neighbours row-major without the centre
 //   arms:   steps j = 1.. while inside, j <= L1 and max channel |diff| < tau1
 template <int NT = 256>
-__device__ inline void census_tile(const uint8_t* __restrict__ rgb, int W, int H, int cw, int ch,
+__device__ inline __attribute__((always_inline)) void census_tile(const uint8_t* __restrict__ rgb, int W, int H, int cw, int ch,
                                    int L1, int tau1, uint64_t* __restrict__ census,
                                    uint32_t* __restrict__ arms, uint32_t* __restrict__ rgb_packed,
                                    uint4* __restrict__ pix, int x0, int y0, CensusLds& S) {
@@ -436,9 +436,6 @@ __device__ inline rsrc_t make_rsrc(const void* p, uint32_t bytes) {
 }
 __device__ inline uint32_t ld32(rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
-}
-__device__ inline uint2 ld64(rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
 __device__ inline uint4 ld128(rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));

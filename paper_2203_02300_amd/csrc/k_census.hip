@@ -5,15 +5,17 @@
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_census_arms(const uint8_t* __restrict__ rgb, int W,
+// One thread per pixel of a tile (1024 threads, at most 64 VGPRs so that two
+// workgroups share a CU).
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_census_arms(const uint8_t* __restrict__ rgb, int W,
                                                      int H, int cw, int ch, int L1, int tau1,
                                                      uint64_t* __restrict__ census,
                                                      uint32_t* __restrict__ arms,
                                                      uint32_t* __restrict__ rgb_packed,
                                                      uint4* __restrict__ pix) {
     __shared__ dco::CensusLds S;
-    dco::census_tile(rgb, W, H, cw, ch, L1, tau1, census, arms, rgb_packed, pix,
-                     blockIdx.x * dco::kCenTW, blockIdx.y * dco::kCenTH, S);
+    dco::census_tile<1024>(rgb, W, H, cw, ch, L1, tau1, census, arms, rgb_packed, pix,
+                           blockIdx.x * dco::kCenTW, blockIdx.y * dco::kCenTH, S);
 }
 
 __global__ __launch_bounds__(256) void k_geometry(const uint32_t* __restrict__ arms, int W, int H,
@@ -49,8 +51,8 @@ __global__ __launch_bounds__(1024) void k_geometry2(const uint32_t* __restrict__
 }
 
 // Every view of a batch of pairs in one launch (blockIdx.z = 2 * pair + view),
-// for the soft path: arms and packed pixels.
-__global__ __launch_bounds__(256) void k_census_pairs(const uint8_t* __restrict__ rgbL,
+// for the soft path: arms and packed pixels; one thread per pixel of a tile.
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_census_pairs(const uint8_t* __restrict__ rgbL,
                                                      const uint8_t* __restrict__ rgbR, int W,
                                                      int H, int cw, int ch, int L1, int tau1,
                                                      uint32_t* __restrict__ armsL,
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(256) void k_census_pairs(const uint8_t* __restrict_
     __shared__ dco::CensusLds S;
     const bool r = (blockIdx.z & 1) != 0;
     const size_t P = (size_t)W * H, o = P * (blockIdx.z >> 1);
-    dco::census_tile((r ? rgbR : rgbL) + 3 * o, W, H, cw, ch, L1, tau1, nullptr,
+    dco::census_tile<1024>((r ? rgbR : rgbL) + 3 * o, W, H, cw, ch, L1, tau1, nullptr,
                      (r ? armsR : armsL) + o, nullptr, (r ? pixR : pixL) + o,
                      blockIdx.x * dco::kCenTW, blockIdx.y * dco::kCenTH, S);
 }
@@ -76,7 +78,7 @@ hipError_t launch_census_pairs(const uint8_t* rgbL, const uint8_t* rgbR, int B, 
         const int nb = B - b0 < kMaxPairs ? B - b0 : kMaxPairs;
         const size_t o = P * b0;
         dim3 g((W + dco::kCenTW - 1) / dco::kCenTW, (H + dco::kCenTH - 1) / dco::kCenTH, 2 * nb);
-        hipLaunchKernelGGL(k_census_pairs, g, dim3(256), 0, st, rgbL + 3 * o, rgbR + 3 * o, W, H,
+        hipLaunchKernelGGL(k_census_pairs, g, dim3(1024), 0, st, rgbL + 3 * o, rgbR + 3 * o, W, H,
                            cw, ch, L1, tau1, armsL + o, armsR + o, pixL + o, pixR + o);
     }
     return hipGetLastError();
@@ -99,7 +101,7 @@ hipError_t launch_census_arms(const uint8_t* rgb, int W, int H, int cw, int ch, 
                               uint64_t* census, uint32_t* arms, uint32_t* rgb_packed, uint4* pix,
                               hipStream_t st) {
     dim3 grid((W + dco::kCenTW - 1) / dco::kCenTW, (H + dco::kCenTH - 1) / dco::kCenTH);
-    hipLaunchKernelGGL(k_census_arms, grid, dim3(256), 0, st, rgb, W, H, cw, ch, L1, tau1, census,
+    hipLaunchKernelGGL(k_census_arms, grid, dim3(1024), 0, st, rgb, W, H, cw, ch, L1, tau1, census,
                        arms, rgb_packed, pix);
     return hipGetLastError();
 }
