@@ -78,9 +78,10 @@ dco_status dco_default_params(dco_params* out);
 
 /* Create a matcher for W x H images and disparities d = 0 .. D-1.
  * Requires 1 <= D < W, W >= census_w, H >= census_h, W, H <= 16384,
- * W * H <= 2^27 and W * H * D < 2^31 (else DCO_ERR_SHAPE).  Copies *p (NULL = defaults), builds the Eq. 1 tables on
- * the host in double precision and uploads them, and allocates the scratch
- * that dco_stereo_match needs.  Synchronous.  On failure *out is NULL. */
+ * W * H <= 2^27 and W * H * D < 2^31 (else DCO_ERR_SHAPE).  Copies *p
+ * (NULL = defaults), builds the Eq. 1 tables on the host in double precision
+ * and uploads them, and allocates the scratch that dco_stereo_match needs.
+ * Synchronous.  On failure *out is NULL. */
 dco_status dco_stereo_create(dco_stereo** out, int W, int H, int D, const dco_params* p,
                              void* stream);
 

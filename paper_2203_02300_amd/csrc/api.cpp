@@ -595,7 +595,8 @@ static dco_status soft_front(dco_stereo* h, int B, const uint8_t* L, const uint8
                                       h->stream));
     DCO_HIP_CHECK(soft_prepare(theta, f.tab, f.arms, B, h->W, h->H, h->D, f.n1, f.n2, h->stream));
     *sb = SoftBuffers{f.arms, f.n1, f.n2, f.pix[0], f.pix[1], h->alpha, f.tab};
-    DCO_HIP_CHECK(soft_aggregate(*sb, B, h->W, h->H, h->D, f.vol[0], f.vol[1], f.vol[2], h->stream));
+    DCO_HIP_CHECK(
+        soft_aggregate(*sb, B, h->W, h->H, h->D, f.vol[0], f.vol[1], f.vol[2], h->stream));
     f.held = true;
     f.held_B = B;
     f.held_L = L;

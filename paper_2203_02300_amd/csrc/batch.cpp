@@ -353,7 +353,8 @@ dco_status tune_class(const dco_params& p, int W, int H, int D, hipStream_t st, 
     for (int y = 0; y < H; ++y)
         for (int c = 0; c < W; ++c)
             for (int k = 0; k < 3; ++k)
-                img2[((size_t)y * W + c) * 3 + k] = img[((size_t)y * W + std::min(W - 1, c + D / 2)) * 3 + k];
+                img2[((size_t)y * W + c) * 3 + k] =
+                    img[((size_t)y * W + std::min(W - 1, c + D / 2)) * 3 + k];
     hipError_t e = hipMemcpy(L, img.data(), img.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(R, img2.data(), img2.size(), hipMemcpyHostToDevice);
     // every copy reads the same pair and writes the same maps (identical values)

@@ -17,7 +17,7 @@ namespace dco {
 
 constexpr int kCenTW = 64, kCenTH = 16;                                  // pixel tile
 constexpr int kCenRW = kCenTW + 2 * kLMax, kCenRH = kCenTH + 2 * kLMax;  // staged RGB region
-constexpr int kCenHW = 4, kCenHH = 4;                                     // census half-window limits
+constexpr int kCenHW = 4, kCenHH = 4;  // census half-window limits
 constexpr int kCenGW = kCenTW + 2 * kCenHW, kCenGH = kCenTH + 2 * kCenHH;
 
 struct CensusLds {
@@ -106,10 +106,10 @@ __device__ inline uint64_t census_code_any(const CensusLds& S, int tx, int ty, i
 //   census: bit k = Y(q_k) < Y(p), neighbours row-major without the centre
 //   arms:   steps j = 1.. while inside, j <= L1 and max channel |diff| < tau1
 template <int NT = 256>
-__device__ inline __attribute__((always_inline)) void census_tile(const uint8_t* __restrict__ rgb, int W, int H, int cw, int ch,
-                                   int L1, int tau1, uint64_t* __restrict__ census,
-                                   uint32_t* __restrict__ arms, uint32_t* __restrict__ rgb_packed,
-                                   uint4* __restrict__ pix, int x0, int y0, CensusLds& S) {
+__device__ inline __attribute__((always_inline)) void census_tile(
+    const uint8_t* __restrict__ rgb, int W, int H, int cw, int ch, int L1, int tau1,
+    uint64_t* __restrict__ census, uint32_t* __restrict__ arms, uint32_t* __restrict__ rgb_packed,
+    uint4* __restrict__ pix, int x0, int y0, CensusLds& S) {
     static_assert(NT % 64 == 0 && (kCenTW * kCenTH) % NT == 0, "whole rows per pass");
     const int t = threadIdx.x;
     {   // stage the region: every load issued before any is stored
@@ -119,7 +119,8 @@ __device__ inline __attribute__((always_inline)) void census_tile(const uint8_t*
         for (int k = 0; k < kN; ++k) {
             const int i = min(t + NT * k, kCenRW * kCenRH - 1);
             const int ry = i / kCenRW, rx = i - ry * kCenRW;
-            const int gx = clampi(x0 - kLMax + rx, 0, W - 1), gy = clampi(y0 - kLMax + ry, 0, H - 1);
+            const int gx = clampi(x0 - kLMax + rx, 0, W - 1);
+            const int gy = clampi(y0 - kLMax + ry, 0, H - 1);
             const uint8_t* p = rgb + 3 * ((size_t)gy * W + gx);
             v[k] = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
         }
@@ -269,9 +270,9 @@ struct GeomLds {
 // NT = 1024 threads use DPP scans (16 lanes per column, one wavefront per
 // row) and take one pixel each.
 template <int NT = 256>
-__device__ inline void geometry_tile(const uint32_t* __restrict__ arms, int W, int H, int iters,
-                                     const AggRecords& rec, int x0, int y0, GeomLds& S,
-                                     const RecGeom& g = kRecPlain) {
+__device__ inline __attribute__((always_inline)) void geometry_tile(
+    const uint32_t* __restrict__ arms, int W, int H, int iters, const AggRecords& rec, int x0,
+    int y0, GeomLds& S, const RecGeom& g = kRecPlain) {
     static_assert(NT == 256 || NT == 1024, "256 or 1024 threads");
     const int t = threadIdx.x;
     {   // stage the arms: every load issued before any is used (clamped addresses)
@@ -1137,7 +1138,8 @@ __device__ inline void agg_stream_ws(const AggArgs& A, int d, int dend, int stri
     R.rIp = make_rsrc(Ipar, 4 * P4);
     const int nout = min(kWsSlices, min(A.D, dend) - d);  // slices to store
     // raw costs of slices d and d + 1; past the last slice, slice d again
-    R.rq = kFused ? R.rB : make_rsrc(A.cost + (size_t)d * slice, (uint32_t)min(kWsSlices, A.D - d) * P4);
+    R.rq = kFused ? R.rB
+                  : make_rsrc(A.cost + (size_t)d * slice, (uint32_t)min(kWsSlices, A.D - d) * P4);
     R.in_slice_bytes = A.D - d >= 2 ? P4 : 0u;
     R.rOut = make_rsrc(A.out + (size_t)d * slice, (uint32_t)nout * P4);
     R.slice_bytes = P4;

@@ -65,7 +65,8 @@ __global__ __launch_bounds__(dco::kWsThreads, 1) void k_batch_agg_ws(BatchArgs B
 // same tiles as the one-call front end: census + arms + packed pixels, then
 // region counts and records, of 64 x 64 blocks; persistent over the items.
 template <int ITERS, int STAGE>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_batch_front(BatchArgs B, int first, int count) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_batch_front(
+    BatchArgs B, int first, int count) {
     __shared__ typename std::conditional<STAGE == 0, dco::CensusLds, dco::GeomLds>::type S;
     for (int k = blockIdx.x; k < count; k += gridDim.x) {
         const BatchItem I = B.items[first + k];

@@ -7,37 +7,33 @@ namespace {
 
 // One thread per pixel of a tile (1024 threads, at most 64 VGPRs so that two
 // workgroups share a CU).
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_census_arms(const uint8_t* __restrict__ rgb, int W,
-                                                     int H, int cw, int ch, int L1, int tau1,
-                                                     uint64_t* __restrict__ census,
-                                                     uint32_t* __restrict__ arms,
-                                                     uint32_t* __restrict__ rgb_packed,
-                                                     uint4* __restrict__ pix) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_census_arms(
+    const uint8_t* __restrict__ rgb, int W, int H, int cw, int ch, int L1, int tau1,
+    uint64_t* __restrict__ census, uint32_t* __restrict__ arms, uint32_t* __restrict__ rgb_packed,
+    uint4* __restrict__ pix) {
     __shared__ dco::CensusLds S;
     dco::census_tile<1024>(rgb, W, H, cw, ch, L1, tau1, census, arms, rgb_packed, pix,
                            blockIdx.x * dco::kCenTW, blockIdx.y * dco::kCenTH, S);
 }
 
-__global__ __launch_bounds__(256) void k_geometry(const uint32_t* __restrict__ arms, int W, int H,
-                                                  int iters, AggRecords rec, RecGeom g) {
+__global__ __launch_bounds__(1024) void k_geometry(const uint32_t* __restrict__ arms, int W, int H,
+                                                   int iters, AggRecords rec, RecGeom g) {
     __shared__ dco::GeomLds S;
-    dco::geometry_tile(arms, W, H, iters, rec, blockIdx.x * dco::kGeoTW, blockIdx.y * dco::kGeoTH,
-                       S, g);
+    dco::geometry_tile<1024>(arms, W, H, iters, rec, blockIdx.x * dco::kGeoTW,
+                             blockIdx.y * dco::kGeoTH, S, g);
 }
 
 // Both views of the one-call path in one launch each (blockIdx.z = view);
 // one thread per pixel of a tile.
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_census_arms2(const uint8_t* __restrict__ rgbL,
-                                                      const uint8_t* __restrict__ rgbR, int W,
-                                                      int H, int cw, int ch, int L1, int tau1,
-                                                      uint32_t* __restrict__ armsL,
-                                                      uint32_t* __restrict__ armsR,
-                                                      uint4* __restrict__ pixL,
-                                                      uint4* __restrict__ pixR) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_census_arms2(
+    const uint8_t* __restrict__ rgbL, const uint8_t* __restrict__ rgbR, int W, int H, int cw,
+    int ch, int L1, int tau1, uint32_t* __restrict__ armsL, uint32_t* __restrict__ armsR,
+    uint4* __restrict__ pixL, uint4* __restrict__ pixR) {
     __shared__ dco::CensusLds S;
     const bool r = blockIdx.z != 0;
-    dco::census_tile<1024>(r ? rgbR : rgbL, W, H, cw, ch, L1, tau1, nullptr, r ? armsR : armsL, nullptr,
-                     r ? pixR : pixL, blockIdx.x * dco::kCenTW, blockIdx.y * dco::kCenTH, S);
+    dco::census_tile<1024>(r ? rgbR : rgbL, W, H, cw, ch, L1, tau1, nullptr, r ? armsR : armsL,
+                           nullptr, r ? pixR : pixL, blockIdx.x * dco::kCenTW,
+                           blockIdx.y * dco::kCenTH, S);
 }
 
 __global__ __launch_bounds__(1024) void k_geometry2(const uint32_t* __restrict__ armsL,
@@ -52,19 +48,16 @@ __global__ __launch_bounds__(1024) void k_geometry2(const uint32_t* __restrict__
 
 // Every view of a batch of pairs in one launch (blockIdx.z = 2 * pair + view),
 // for the soft path: arms and packed pixels; one thread per pixel of a tile.
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_census_pairs(const uint8_t* __restrict__ rgbL,
-                                                     const uint8_t* __restrict__ rgbR, int W,
-                                                     int H, int cw, int ch, int L1, int tau1,
-                                                     uint32_t* __restrict__ armsL,
-                                                     uint32_t* __restrict__ armsR,
-                                                     uint4* __restrict__ pixL,
-                                                     uint4* __restrict__ pixR) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_census_pairs(
+    const uint8_t* __restrict__ rgbL, const uint8_t* __restrict__ rgbR, int W, int H, int cw,
+    int ch, int L1, int tau1, uint32_t* __restrict__ armsL, uint32_t* __restrict__ armsR,
+    uint4* __restrict__ pixL, uint4* __restrict__ pixR) {
     __shared__ dco::CensusLds S;
     const bool r = (blockIdx.z & 1) != 0;
     const size_t P = (size_t)W * H, o = P * (blockIdx.z >> 1);
     dco::census_tile<1024>((r ? rgbR : rgbL) + 3 * o, W, H, cw, ch, L1, tau1, nullptr,
-                     (r ? armsR : armsL) + o, nullptr, (r ? pixR : pixL) + o,
-                     blockIdx.x * dco::kCenTW, blockIdx.y * dco::kCenTH, S);
+                           (r ? armsR : armsL) + o, nullptr, (r ? pixR : pixL) + o,
+                           blockIdx.x * dco::kCenTW, blockIdx.y * dco::kCenTH, S);
 }
 
 }  // namespace
@@ -109,6 +102,6 @@ hipError_t launch_census_arms(const uint8_t* rgb, int W, int H, int cw, int ch, 
 hipError_t launch_geometry(const uint32_t* arms, int W, int H, int iters, const AggRecords& rec,
                            const RecGeom& g, hipStream_t st) {
     dim3 grid((W + dco::kGeoTW - 1) / dco::kGeoTW, (H + dco::kGeoTH - 1) / dco::kGeoTH);
-    hipLaunchKernelGGL(k_geometry, grid, dim3(256), 0, st, arms, W, H, iters, rec, g);
+    hipLaunchKernelGGL(k_geometry, grid, dim3(1024), 0, st, arms, W, H, iters, rec, g);
     return hipGetLastError();
 }

@@ -252,8 +252,9 @@ __global__ __launch_bounds__(256) void k_hyst(const uint8_t* __restrict__ in, in
         for (int k = threadIdx.x; k < kHTH * kHTW; k += 256) {
             const int ty = k / kHTW + 1, tx = k % kHTW + 1;
             if (T[ty][tx] != 1) continue;
-            const bool hit = T[ty - 1][tx - 1] == 2 || T[ty - 1][tx] == 2 || T[ty - 1][tx + 1] == 2 ||
-                             T[ty][tx - 1] == 2 || T[ty][tx + 1] == 2 || T[ty + 1][tx - 1] == 2 ||
+            const bool hit = T[ty - 1][tx - 1] == 2 || T[ty - 1][tx] == 2 ||
+                             T[ty - 1][tx + 1] == 2 || T[ty][tx - 1] == 2 ||
+                             T[ty][tx + 1] == 2 || T[ty + 1][tx - 1] == 2 ||
                              T[ty + 1][tx] == 2 || T[ty + 1][tx + 1] == 2;
             if (hit) {
                 T[ty][tx] = 2;

@@ -147,8 +147,9 @@ __device__ inline void cost_px(uint4 a, uint4 b, bool inside, const float* tab, 
 // workgroup, each with its own LDS slice (no workgroup barriers after the
 // table load) and kRowsPerWave rows in turn.  Row ids run over (b, y, d)
 // with d fastest, so the rows that run together share one image row (its
-// pixels, arms and counts stay in cache across the disparities).  Outside the prefix phase (which has its own layout, see
-// prefix_row) lane `lane` handles columns lane + 64 k; loads are issued
+// pixels, arms and counts stay in cache across the disparities).  Outside
+// the prefix phase (which has its own layout, see prefix_row) lane `lane`
+// handles columns lane + 64 k; loads are issued
 // kRowBatch columns at a time with clamped (always valid) addresses.
 constexpr int kRowWaves = 4;
 constexpr int kRowsPerWave = 4;
@@ -340,7 +341,9 @@ __device__ inline void prefix_row(const uint4* pl, const uint4* pr, const float*
 // stage when it computes raw costs), gradient (two and the stage) and
 // adjoint (64-bit difference array, the row, its arms).
 __host__ __device__ inline size_t row_bytes(int W) { return ((size_t)W * 4 + 15) / 16 * 16; }
-__host__ __device__ inline size_t prefix_bytes(int W) { return ((size_t)(W + 1) * 8 + 15) / 16 * 16; }
+__host__ __device__ inline size_t prefix_bytes(int W) {
+    return ((size_t)(W + 1) * 8 + 15) / 16 * 16;
+}
 constexpr size_t kStageBytes = kPreChunk * sizeof(float);
 inline size_t row_lds_fwd(int W) { return prefix_bytes(W); }
 inline size_t row_lds_cost(int W) { return prefix_bytes(W) + kStageBytes; }
@@ -540,7 +543,8 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_seed_adj(
                 const int x = x0 + 64 * j + lane;
                 if (x < W) {
                     const float wgt = exp_e(-a2[j] * invT - l[j]);
-                    const float G = gp[j] * wgt * (dh[j] - (float)d) * invT * __builtin_amdgcn_rcpf(n2[j]);
+                    const float G =
+                        gp[j] * wgt * (dh[j] - (float)d) * invT * __builtin_amdgcn_rcpf(n2[j]);
                     acc += (double)(gp[j] * wgt * ((float)d - dh[j]) * a2[j]) *
                            (double)(invT * invT);
                     row[x] = G;
@@ -598,7 +602,8 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_seed_adj(
             for (int k = 0; k < 4; ++k) o[k] = (float)((double)(before + sk[k]) * down);
             if (vec) {
                 if (x < W)
-                    *reinterpret_cast<float4*>(out + base + x) = make_float4(o[0], o[1], o[2], o[3]);
+                    *reinterpret_cast<float4*>(out + base + x) =
+                        make_float4(o[0], o[1], o[2], o[3]);
             } else {
 #pragma unroll
                 for (int k = 0; k < 4; ++k)

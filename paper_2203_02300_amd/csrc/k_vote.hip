@@ -164,7 +164,8 @@ __global__ __launch_bounds__(kVThreads) void k_vote(const int16_t* __restrict__ 
     for (int base = vlo; base <= vhi; base += kVBins) {  // uniform
         const int nb = min(kVBins, vhi - base + 1);      // bins past vhi get no votes
         // 1. each segment's counts (one thread per segment; row 0 is zero)
-        for (int i = tid; i < kVT * kVWords; i += kVThreads) S.cnt[0][i / kVWords][i % kVWords] = 0u;
+        for (int i = tid; i < kVT * kVWords; i += kVThreads)
+            S.cnt[0][i / kVWords][i % kVWords] = 0u;
         for (int sg = tid; sg < kVSegs; sg += kVThreads) {
             const int ry = sg / kVT, cx = sg - ry * kVT;
             uint32_t* c = S.cnt[ry + 1][cx];
