@@ -6,20 +6,21 @@
 // disparity.  Invalid pixels (-1) neither vote nor change.  Passes read only
 // the previous pass's map.
 //
-// Layout: one workgroup of four wavefronts per 16 x 16 pixel tile, one
-// thread per pixel.  The tile's votes plus a kLMax apron on every side
-// (50 x 50 int16) and the horizontal arms of the tile columns over the apron
-// rows go to LDS, and each staged row is run-length coded once (runs of equal
-// votes: start column, value, and the run of each column).  A pixel's region
-// is the union of the horizontal segments of the rows on its vertical arm,
-// and the segment of (column, row) is the same for every pixel whose arm
-// covers that row; so the votes are counted once per segment: for a window
-// of kVBins disparities at a time, each of the 50 x 16 segments adds, for
-// every run it meets, the overlap length to its own counters; the counters
-// are then prefix-summed down each tile column, and a pixel reads its counts
-// as the difference of two prefix rows (the ends of its vertical arm).
-// Counters are 16-bit, two per 32-bit word (a count is at most 51 rows x 35
-// columns, so packed sums and differences never carry between the halves).
+// Layout: one workgroup of eight wavefronts per 16 x 32 pixel tile (16
+// columns, 32 rows), one thread per pixel.  The tile's votes plus a kLMax
+// apron on every side (66 rows x 50 columns of int16) and the horizontal arms
+// of the tile columns over the apron rows go to LDS, and each staged row is
+// run-length coded once (runs of equal votes: start column, value, and the
+// run of each column).  A pixel's region is the union of the horizontal
+// segments of the rows on its vertical arm, and the segment of (column, row)
+// is the same for every pixel whose arm covers that row; so the votes are
+// counted once per segment: for a window of kVBins disparities at a time,
+// each of the 66 x 16 segments adds, for every run it meets, the overlap
+// length to its own counters; the counters are then prefix-summed down each
+// tile column, and a pixel reads its counts as the difference of two prefix
+// rows (the ends of its vertical arm).  Counters are 16-bit, two per 32-bit
+// word (a count is at most 67 rows x 35 columns, so packed sums and
+// differences never carry between the halves).
 // The windows step from the smallest to the largest vote staged for the
 // tile; a strict running maximum keeps the smallest disparity among equal
 // counts.  All counts are integers, so the result does not depend on the
@@ -28,29 +29,31 @@
 
 namespace {
 
-constexpr int kVT = 16;                     // tile side
-constexpr int kVThreads = kVT * kVT;        // one thread per tile pixel
+constexpr int kVTW = 16, kVTH = 32;         // tile width and height
+constexpr int kVThreads = kVTW * kVTH;      // one thread per tile pixel
 constexpr int kVWaves = kVThreads / 64;
-constexpr int kVR = kVT + 2 * kLMax;        // staged side
-constexpr int kVStride = kVR + 2;
+constexpr int kVRW = kVTW + 2 * kLMax;      // staged width
+constexpr int kVRH = kVTH + 2 * kLMax;      // staged height
+constexpr int kVStride = kVRW + 2;
 
 constexpr int kVBins = 16;               // disparities per counter window
 constexpr int kVWords = kVBins / 2;      // two 16-bit counters per word
 constexpr int kVWordStride = kVWords + 1;  // per tile column (odd: no bank conflicts)
-constexpr int kVSegs = kVR * kVT;        // segments: staged rows x tile columns
-constexpr int kVStage = (kVR * kVR + kVThreads - 1) / kVThreads;
-constexpr int kVArms = (kVR * kVT + kVThreads - 1) / kVThreads;
-static_assert(kVBins % 2 == 0 && kVR * 35 < 65536, "packed 16-bit counters");
+constexpr int kVSegs = kVRH * kVTW;      // segments: staged rows x tile columns
+constexpr int kVStage = (kVRW * kVRH + kVThreads - 1) / kVThreads;
+constexpr int kVArms = (kVRH * kVTW + kVThreads - 1) / kVThreads;
+static_assert(kVBins % 2 == 0 && (kVRH + 1) * 35 < 65536, "packed 16-bit counters");
+static_assert((kVTW & (kVTW - 1)) == 0, "tile width a power of two");
 
 struct VoteLds {
     // cnt[r][c][k]: for tile column c and the window's bins 2k, 2k + 1, the
     // votes over the segments of staged rows 0 .. r - 1 (row 0: none)
-    uint32_t cnt[kVR + 1][kVT][kVWordStride];
-    int16_t d[kVR][kVStride];   // votes of the staged region (-1: none)
-    int16_t rv[kVR][kVR];       // value of run k of each staged row
-    uint8_t rs[kVR][kVR + 2];   // run of each column
-    uint8_t st[kVR][kVR + 2];   // start column of run k; st[nruns] = kVR
-    uint8_t l[kVR][kVT], r[kVR][kVT];  // horizontal arms of the tile columns
+    uint32_t cnt[kVRH + 1][kVTW][kVWordStride];
+    int16_t d[kVRH][kVStride];    // votes of the staged region (-1: none)
+    int16_t rv[kVRH][kVRW];       // value of run k of each staged row
+    uint8_t rs[kVRH][kVRW + 2];   // run of each column
+    uint8_t st[kVRH][kVRW + 2];   // start column of run k; st[nruns] = kVRW
+    uint8_t l[kVRH][kVTW], r[kVRH][kVTW];  // horizontal arms of the tile columns
     int lo[kVWaves], hi[kVWaves];      // vote range seen by each wavefront
 };
 
@@ -71,15 +74,15 @@ __global__ __launch_bounds__(kVThreads) void k_vote(const int16_t* __restrict__ 
                                                     int H, int D, int16_t* __restrict__ dout) {
     __shared__ __align__(16) VoteLds S;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int tx = tid & (kVT - 1), ty = tid / kVT;
-    const int x0 = blockIdx.x * kVT, y0 = blockIdx.y * kVT;
+    const int tx = tid & (kVTW - 1), ty = tid / kVTW;
+    const int x0 = blockIdx.x * kVTW, y0 = blockIdx.y * kVTH;
     {   // stage the votes: every load issued before any is used (clamped addresses)
         int dv[kVStage];
         bool ok[kVStage];
 #pragma unroll
         for (int t = 0; t < kVStage; ++t) {
-            const int i = min(tid + kVThreads * t, kVR * kVR - 1);
-            const int ry = i / kVR, rx = i - ry * kVR;
+            const int i = min(tid + kVThreads * t, kVRW * kVRH - 1);
+            const int ry = i / kVRW, rx = i - ry * kVRW;
             const int x = x0 - kLMax + rx, y = y0 - kLMax + ry;
             ok[t] = x >= 0 && x < W && y >= 0 && y < H;
             const size_t q = (size_t)min(max(y, 0), H - 1) * W + min(max(x, 0), W - 1);
@@ -91,9 +94,9 @@ __global__ __launch_bounds__(kVThreads) void k_vote(const int16_t* __restrict__ 
         for (int t = 0; t < kVStage; ++t) {
             const int i = tid + kVThreads * t;
             const int v = ok[t] && dv[t] >= 0 && dv[t] < D ? dv[t] : -1;
-            if (i < kVR * kVR) {
-                const int ry = i / kVR;
-                S.d[ry][i - ry * kVR] = (int16_t)v;
+            if (i < kVRW * kVRH) {
+                const int ry = i / kVRW;
+                S.d[ry][i - ry * kVRW] = (int16_t)v;
                 if (v >= 0) {
                     lo = min(lo, v);
                     hi = max(hi, v);
@@ -111,18 +114,18 @@ __global__ __launch_bounds__(kVThreads) void k_vote(const int16_t* __restrict__ 
         uint32_t av[kVArms];
 #pragma unroll
         for (int t = 0; t < kVArms; ++t) {
-            const int i = min(tid + kVThreads * t, kVR * kVT - 1);
-            const int ry = i / kVT, cx = i - ry * kVT;
+            const int i = min(tid + kVThreads * t, kVRH * kVTW - 1);
+            const int ry = i / kVTW, cx = i - ry * kVTW;
             const int x = min(x0 + cx, W - 1), y = min(max(y0 - kLMax + ry, 0), H - 1);
             av[t] = arms[(size_t)y * W + x];
         }
 #pragma unroll
         for (int t = 0; t < kVArms; ++t) {
             const int i = tid + kVThreads * t;
-            const int ry = i / kVT, cx = i - ry * kVT;
+            const int ry = i / kVTW, cx = i - ry * kVTW;
             const int x = x0 + cx, y = y0 - kLMax + ry;
             const uint32_t a = x < W && y >= 0 && y < H ? av[t] : 0u;
-            if (i < kVR * kVT) {
+            if (i < kVRH * kVTW) {
                 S.l[ry][cx] = (uint8_t)min(a & 0xff, (uint32_t)kLMax);
                 S.r[ry][cx] = (uint8_t)min((a >> 8) & 0xff, (uint32_t)kLMax);
             }
@@ -135,10 +138,10 @@ __global__ __launch_bounds__(kVThreads) void k_vote(const int16_t* __restrict__ 
         vlo = min(vlo, S.lo[k]);
         vhi = max(vhi, S.hi[k]);
     }
-    if (tid < kVR) {  // run-length code staged row `tid`
+    if (tid < kVRH) {  // run-length code staged row `tid`
         int n = 0, prev = 0;
 #pragma unroll 5
-        for (int c = 0; c < kVR; ++c) {
+        for (int c = 0; c < kVRW; ++c) {
             const int v = S.d[tid][c];
             if (c == 0 || v != prev) {
                 S.st[tid][n] = (uint8_t)c;
@@ -148,7 +151,7 @@ __global__ __launch_bounds__(kVThreads) void k_vote(const int16_t* __restrict__ 
             }
             S.rs[tid][c] = (uint8_t)(n - 1);
         }
-        S.st[tid][n] = (uint8_t)kVR;
+        S.st[tid][n] = (uint8_t)kVRW;
     }
     __syncthreads();
 
@@ -164,10 +167,10 @@ __global__ __launch_bounds__(kVThreads) void k_vote(const int16_t* __restrict__ 
     for (int base = vlo; base <= vhi; base += kVBins) {  // uniform
         const int nb = min(kVBins, vhi - base + 1);      // bins past vhi get no votes
         // 1. each segment's counts (one thread per segment; row 0 is zero)
-        for (int i = tid; i < kVT * kVWords; i += kVThreads)
+        for (int i = tid; i < kVTW * kVWords; i += kVThreads)
             S.cnt[0][i / kVWords][i % kVWords] = 0u;
         for (int sg = tid; sg < kVSegs; sg += kVThreads) {
-            const int ry = sg / kVT, cx = sg - ry * kVT;
+            const int ry = sg / kVTW, cx = sg - ry * kVTW;
             uint32_t* c = S.cnt[ry + 1][cx];
 #pragma unroll
             for (int k = 0; k < kVWords; ++k) c[k] = 0u;
@@ -185,11 +188,11 @@ __global__ __launch_bounds__(kVThreads) void k_vote(const int16_t* __restrict__ 
         }
         __syncthreads();
         // 2. prefix sums down each tile column, a (column, word) per thread
-        for (int i = tid; i < kVT * kVWords; i += kVThreads) {
+        for (int i = tid; i < kVTW * kVWords; i += kVThreads) {
             const int cx = i / kVWords, k = i % kVWords;
             uint32_t run = 0u;
-#pragma unroll 10
-            for (int ry = 1; ry <= kVR; ++ry) {
+#pragma unroll 11
+            for (int ry = 1; ry <= kVRH; ++ry) {
                 run += S.cnt[ry][cx][k];
                 S.cnt[ry][cx][k] = run;
             }
@@ -252,7 +255,7 @@ __global__ __launch_bounds__(256) void k_vote_finish(const int16_t* dv, const ui
 hipError_t launch_vote(const int16_t* dL, const uint8_t* valid, const uint32_t* arms, int W, int H,
                        int D, int iters, int16_t* buf0, int16_t* buf1, const int16_t** result,
                        hipStream_t st) {
-    const dim3 grid((W + kVT - 1) / kVT, (H + kVT - 1) / kVT);
+    const dim3 grid((W + kVTW - 1) / kVTW, (H + kVTH - 1) / kVTH);
     const int16_t* src = dL;
     const uint8_t* mask = valid;
     int16_t* bufs[2] = {buf0, buf1};
