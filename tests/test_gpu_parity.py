@@ -72,6 +72,24 @@ def test_aggregate_bit_exact(torch_mod, name):
             assert bad.size == 0, (tag, bad[:5], agg[tuple(bad[0])], want[tuple(bad[0])])
 
 
+@pytest.mark.parametrize("D", [1, 2, 37])
+def test_aggregate_odd_and_small_ranges_bit_exact(torch_mod, D):
+    """The staged two-stage aggregation takes two slices per workgroup: with
+    an odd range the last workgroup has one slice (it reads that slice twice
+    and stores one), and D = 1 has only that workgroup."""
+    from paper_2203_02300_amd import StereoMatcher
+    L, R, _ = case("ragged")
+    H, W = L.shape[:2]
+    print(f"staged aggregation, ragged {W}x{H} D={D}", flush=True)
+    st = oracle.stages(L, R, D)
+    with StereoMatcher(W, H, D) as m:
+        for tag in ("L", "R"):
+            cost = dev((st["q" + tag].astype(np.float64) * 2.0 ** -20).astype(np.float32))
+            agg = host(m.aggregate(cost, dev(st["arms" + tag])))
+            bad = np.argwhere(agg != st["agg" + tag])
+            assert bad.size == 0, (D, tag, bad[:5])
+
+
 @pytest.mark.parametrize("name", CASES)
 def test_wta_lrcheck_bit_exact(torch_mod, name):
     st = oracle_stages(name)
