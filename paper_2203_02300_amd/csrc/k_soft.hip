@@ -409,7 +409,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_soft_hrow(SoftGeom g, SoftIm
                 const int x = x0 + 64 * j + lane;
                 if (x < W) {
                     const float v = (float)(Pf[x + arm(a[j], 1) + 1] - Pf[x - arm(a[j], 0)]);
-                    orow[x] = kCost ? v : v / n[j];
+                    orow[x] = kCost ? v : v * __builtin_amdgcn_rcpf(n[j]);
                 }
             }
         });
