@@ -238,8 +238,11 @@ __device__ inline void write_records(const AggRecords& rec, int x, int y, int it
     if (iters == 2) {
         const uint32_t lg = n1 <= 1 ? 0u : 32u - (uint32_t)__clz((int)(n1 - 1));
         const uint32_t sh = 31u + lg;
-        const uint64_t num = (uint64_t)1 << sh;
-        bv[0] = (uint32_t)((num + n1 - 1) / n1);
+        // m = ceil(2^sh / N1) from the correctly rounded double quotient:
+        // the quotient is below 2^32, so its rounding error is at most 2^-22,
+        // while a quotient that is not an integer is at least 1 / N1 > 2^-11
+        // away from one, so the ceiling is exact
+        bv[0] = (uint32_t)__builtin_ceil(__builtin_ldexp(1.0, (int)sh) / (double)n1);
         reinterpret_cast<uint16_t*>(bv + 2)[1] = (uint16_t)((n1 >> 1) | sh << 10);
         uint32_t* c = rec.c + 4 * ((size_t)y * rec.Wp + col);
         c[0] = ring_slot((int)hi, g.ring2) * g.step2 | ring_slot((int)lo, g.ring2) * g.step2 << 16;
@@ -1153,6 +1156,9 @@ __device__ inline void agg_stream_ws(const AggArgs& A, int d, int dend, int stri
     __syncthreads();
 
     if (w < kAggK) {  // row wavefronts
+        // the row wavefronts carry the longer chain of each phase; issuing
+        // their instructions first when both kinds are ready helps slightly
+        __builtin_amdgcn_s_setprio(1);
         WsRowLane ln;
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) {
