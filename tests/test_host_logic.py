@@ -46,6 +46,17 @@ def test_magic_division_exact():
                 assert (n * m) >> sh == n // N, (N, n)
 
 
+def test_magic_multiplier_from_double_quotient():
+    """The record kernel computes m as the ceiling of the correctly rounded
+    double quotient 2^sh / N (Python floats are IEEE doubles with correctly
+    rounded division); it equals the exact integer ceiling for every N up to
+    2^11."""
+    import math
+    for N in range(1, 2049):
+        m, sh = magic(N)
+        assert math.ceil(math.ldexp(1.0, sh) / N) == m, N
+
+
 def rn32(x: Fraction) -> Fraction:
     """Round a rational to the nearest float32 (ties to even), normal range."""
     if x == 0:
