@@ -1382,10 +1382,54 @@ __device__ inline void wta_pairs_pixel(const float* __restrict__ vol, int P, int
     if (delta_out) *delta_out = subpixel ? wta_pair_delta(vol, P, D, i, best, bd) : 0.f;
 }
 
-// Four consecutive pixels (P % 4 == 0): one 16-byte load per even slice,
-// eight slices in flight.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Pair step that also keeps, for the left view's parabola, the word of the
+// pair before the best one (prevw) and of the pair after it (nextw): the
+// neighbour of the winner in an adjacent pair is then often that pair's
+// minimum, already loaded.
+__device__ inline void wta_pair_step_tr(uint32_t s, int g, float& best, int& bd, uint32_t& lastw,
+                                        uint32_t& prevw, uint32_t& nextw, bool& pend) {
+    const float v = __builtin_bit_cast(float, s & 0x7fffffffu);
+    if (pend) {
+        nextw = s;
+        pend = false;
+    }
+    if (v < best) {
+        best = v;
+        bd = 2 * g + (int)(s >> 31);
+        prevw = lastw;
+        pend = true;
+    }
+    lastw = s;
+}
+
+// wta_pair_delta with the adjacent pairs' words from the scan: the winner's
+// pair partner is that pair's maximum (the odd slice), and the neighbour in
+// the adjacent pair is read only when it is not that pair's minimum.  The
+// values are the same ones paired_at decodes.
+__device__ inline float wta_pair_delta_tr(const float* __restrict__ vol, int P, int D, int i,
+                                          float best, int bd, uint32_t prevw, uint32_t nextw) {
+    if (bd <= 0 || bd >= D - 1) return 0.f;
+    const int g = bd >> 1;
+    const float partner = vol[(size_t)(2 * g + 1) * P + i];
+    float m, pl;
+    if ((bd & 1) == 0) {
+        m = (prevw >> 31) ? __builtin_bit_cast(float, prevw & 0x7fffffffu)
+                          : vol[(size_t)(2 * g - 1) * P + i];
+        pl = partner;
+    } else {
+        m = partner;
+        pl = (nextw >> 31) == 0u || 2 * g + 3 >= D ? __builtin_bit_cast(float, nextw & 0x7fffffffu)
+                                                   : vol[(size_t)(2 * g + 3) * P + i];
+    }
+    return subpixel_delta(m, best, pl, bd, D);
+}
+
+// Four consecutive pixels (P % 4 == 0): one 16-byte load per even slice,
+// sixteen slices in flight.  kSub: the left view, with the parabola's offset
+// into delta_out; else delta_out is null.
+template <bool kSub>
 __device__ inline void wta_pairs_quad(const float* __restrict__ vol, int P, int D, int i4,
                                       int subpixel, int16_t* __restrict__ dout,
                                       float* __restrict__ delta_out) {
@@ -1393,11 +1437,27 @@ __device__ inline void wta_pairs_quad(const float* __restrict__ vol, int P, int 
     const u32x4* __restrict__ s4 = reinterpret_cast<const u32x4*>(vol + i4);
     const size_t st = (size_t)P / 2;  // two slices, in 16-byte words
     const u32x4 w0 = __builtin_nontemporal_load(s4);
-    float best[4] = {__builtin_bit_cast(float, w0.x & 0x7fffffffu),
-                     __builtin_bit_cast(float, w0.y & 0x7fffffffu),
-                     __builtin_bit_cast(float, w0.z & 0x7fffffffu),
-                     __builtin_bit_cast(float, w0.w & 0x7fffffffu)};
-    int bd[4] = {(int)(w0.x >> 31), (int)(w0.y >> 31), (int)(w0.z >> 31), (int)(w0.w >> 31)};
+    const uint32_t w0s[4] = {w0.x, w0.y, w0.z, w0.w};
+    float best[4];
+    int bd[4];
+    uint32_t lastw[4], prevw[4] = {0u, 0u, 0u, 0u}, nextw[4] = {0u, 0u, 0u, 0u};
+    bool pend[4] = {true, true, true, true};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        best[q] = __builtin_bit_cast(float, w0s[q] & 0x7fffffffu);
+        bd[q] = (int)(w0s[q] >> 31);
+        lastw[q] = w0s[q];
+    }
+    const auto step = [&](const u32x4& v, int g) {
+        const uint32_t vs[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if constexpr (kSub)
+                wta_pair_step_tr(vs[q], g, best[q], bd[q], lastw[q], prevw[q], nextw[q], pend[q]);
+            else
+                wta_pair_step(vs[q], g, best[q], bd[q]);
+        }
+    };
     constexpr int U = 16;  // 16 loads in flight per thread
     int g = 1;
     for (; g + U <= G; g += U) {
@@ -1405,32 +1465,20 @@ __device__ inline void wta_pairs_quad(const float* __restrict__ vol, int P, int 
 #pragma unroll
         for (int k = 0; k < U; ++k) v[k] = __builtin_nontemporal_load(s4 + (size_t)(g + k) * st);
 #pragma unroll
-        for (int k = 0; k < U; ++k) {
-            wta_pair_step(v[k].x, g + k, best[0], bd[0]);
-            wta_pair_step(v[k].y, g + k, best[1], bd[1]);
-            wta_pair_step(v[k].z, g + k, best[2], bd[2]);
-            wta_pair_step(v[k].w, g + k, best[3], bd[3]);
-        }
+        for (int k = 0; k < U; ++k) step(v[k], g + k);
     }
-    for (; g < G; ++g) {
-        const u32x4 v = __builtin_nontemporal_load(s4 + (size_t)g * st);
-        wta_pair_step(v.x, g, best[0], bd[0]);
-        wta_pair_step(v.y, g, best[1], bd[1]);
-        wta_pair_step(v.z, g, best[2], bd[2]);
-        wta_pair_step(v.w, g, best[3], bd[3]);
-    }
+    for (; g < G; ++g) step(__builtin_nontemporal_load(s4 + (size_t)g * st), g);
     const uint32_t lo = (uint32_t)(uint16_t)bd[0] | (uint32_t)(uint16_t)bd[1] << 16;
     const uint32_t hi = (uint32_t)(uint16_t)bd[2] | (uint32_t)(uint16_t)bd[3] << 16;
     *reinterpret_cast<uint2*>(dout + i4) = make_uint2(lo, hi);
-    if (delta_out) {
-        float4 del = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (kSub) {
+        float del[4] = {0.f, 0.f, 0.f, 0.f};
         if (subpixel) {
-            del.x = wta_pair_delta(vol, P, D, i4, best[0], bd[0]);
-            del.y = wta_pair_delta(vol, P, D, i4 + 1, best[1], bd[1]);
-            del.z = wta_pair_delta(vol, P, D, i4 + 2, best[2], bd[2]);
-            del.w = wta_pair_delta(vol, P, D, i4 + 3, best[3], bd[3]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                del[q] = wta_pair_delta_tr(vol, P, D, i4 + q, best[q], bd[q], prevw[q], nextw[q]);
         }
-        *reinterpret_cast<float4*>(delta_out + i4) = del;
+        *reinterpret_cast<float4*>(delta_out + i4) = make_float4(del[0], del[1], del[2], del[3]);
     }
 }
 

@@ -152,10 +152,10 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BatchArgs B, int first, 
                     const int i4 = I.a + (r * 256 + t) * 4;
                     if (i4 >= P) break;
                     if (paired) {
-                        dco::wta_pairs_quad(pr.agg[0], P, pr.D, i4, B.subpixel, pr.dint[0],
-                                            pr.delta);
-                        dco::wta_pairs_quad(pr.agg[1], P, pr.D, i4, B.subpixel, pr.dint[1],
-                                            nullptr);
+                        dco::wta_pairs_quad<true>(pr.agg[0], P, pr.D, i4, B.subpixel,
+                                                  pr.dint[0], pr.delta);
+                        dco::wta_pairs_quad<false>(pr.agg[1], P, pr.D, i4, B.subpixel,
+                                                   pr.dint[1], nullptr);
                     } else {
                         dco::wta_quad(pr.agg[0], P, pr.D, i4, B.subpixel, pr.dint[0], pr.delta);
                         dco::wta_quad(pr.agg[1], P, pr.D, i4, B.subpixel, pr.dint[1], nullptr);

@@ -58,9 +58,9 @@ __global__ __launch_bounds__(256) void k_wta_pairs4(const float* __restrict__ ag
     const int i4 = (blockIdx.x * 256 + threadIdx.x) * 4;
     if (i4 >= P) return;
     if (blockIdx.y == 0)
-        dco::wta_pairs_quad(aggL, P, D, i4, subpixel, dL, deltaL);
+        dco::wta_pairs_quad<true>(aggL, P, D, i4, subpixel, dL, deltaL);
     else
-        dco::wta_pairs_quad(aggR, P, D, i4, subpixel, dR, nullptr);
+        dco::wta_pairs_quad<false>(aggR, P, D, i4, subpixel, dR, nullptr);
 }
 
 // Slices d0 .. d0 + n - 1 of a paired-layout volume, decoded to n x P.
