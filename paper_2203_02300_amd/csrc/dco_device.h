@@ -1,10 +1,9 @@
 // dco_device.h -- device-side bodies of every stage of the plain matcher.
 //
 // The one-call kernels (k_census.hip, k_aggregate.hip, k_wta.hip) and the
-// persistent batched kernel (k_batch.hip) run exactly these functions, so a
+// batched work-list kernels (k_batch.hip) run exactly these functions, so a
 // pair matched alone and the same pair matched in a batch give the same bits.
-// Each function takes its LDS as an explicit struct so the persistent kernel
-// can overlay the stages' LDS in one union.
+// Each function takes its LDS as an explicit struct.
 #pragma once
 
 #include "dco_internal.h"

@@ -1,10 +1,12 @@
-// k_aggregate.hip -- aggregation over the adaptive cross region (Eq. 2),
-// applied as two stages, in exact integer arithmetic: one workgroup per
-// (disparity slice, column strip) streaming down the rows.  With kFused the
-// raw cost of Eq. 1 is computed on the fly from the images and census codes
-// (the one-call matcher) instead of being read from a cost volume (the
-// staged dco_aggregate).  The stage body (dco::agg_stream) lives in
-// dco_device.h.
+// k_aggregate.hip -- aggregation over the adaptive cross region (Eq. 2), in
+// exact integer arithmetic, each workgroup streaming a column strip down the
+// rows.  Two stages (the path's reading of Eq. 2): k_agg_pair_ws, two
+// adjacent disparity slices per workgroup (dco::agg_stream_ws), with the raw
+// cost of Eq. 1 computed on the fly for both views in one launch (the
+// one-call matcher) or read from one view's cost volume (the staged
+// dco_aggregate).  One stage: one slice per workgroup (dco::agg_stream,
+// k_agg_stream for the staged call, k_agg_pair for the one-call matcher).
+// The stage bodies live in dco_device.h.
 #include <atomic>
 
 #include "dco_device.h"

@@ -1,8 +1,9 @@
 // k_wta.hip -- winner-take-all over the aggregated volumes (Eq. 3) with
 // parabola sub-pixel refinement, and the left-right consistency check.
 // k_wta_pairs* take the same decision on volumes in the paired layout
-// (dco::paired_at): they read only the even slices and gather d - 1 and d + 1
-// for the sub-pixel step.
+// (dco::paired_at): they read only the even slices; for the sub-pixel step
+// they gather the winner's pair partner and, when it is not the adjacent
+// pair's minimum kept from the scan, its other neighbour.
 // One thread per pixel (or per four pixels, with 16-byte loads, when W * H is
 // a multiple of four) walks d = 0 .. D-1; loads of one slice are coalesced
 // across the block, so each volume is read exactly once.  The stage bodies
