@@ -1426,7 +1426,7 @@ __device__ inline float wta_pair_delta_tr(const float* __restrict__ vol, int P, 
 }
 
 // Four consecutive pixels (P % 4 == 0): one 16-byte load per even slice,
-// sixteen slices in flight.  kSub: the left view, with the parabola's offset
+// 21 slices in flight.  kSub: the left view, with the parabola's offset
 // into delta_out; else delta_out is null.
 template <bool kSub>
 __device__ inline void wta_pairs_quad(const float* __restrict__ vol, int P, int D, int i4,
@@ -1457,7 +1457,7 @@ __device__ inline void wta_pairs_quad(const float* __restrict__ vol, int P, int 
                 wta_pair_step(vs[q], g, best[q], bd[q]);
         }
     };
-    constexpr int U = 16;  // 16 loads in flight per thread
+    constexpr int U = 21;  // 21 loads in flight per thread (three batches for D = 128)
     int g = 1;
     for (; g + U <= G; g += U) {
         u32x4 v[U];
@@ -1466,7 +1466,15 @@ __device__ inline void wta_pairs_quad(const float* __restrict__ vol, int P, int 
 #pragma unroll
         for (int k = 0; k < U; ++k) step(v[k], g + k);
     }
-    for (; g < G; ++g) step(__builtin_nontemporal_load(s4 + (size_t)g * st), g);
+    if (g < G) {  // the last groups as one batch (loads clamped to the last group)
+        u32x4 v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            v[k] = __builtin_nontemporal_load(s4 + (size_t)min(g + k, G - 1) * st);
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (g + k < G) step(v[k], g + k);
+    }
     const uint32_t lo = (uint32_t)(uint16_t)bd[0] | (uint32_t)(uint16_t)bd[1] << 16;
     const uint32_t hi = (uint32_t)(uint16_t)bd[2] | (uint32_t)(uint16_t)bd[3] << 16;
     *reinterpret_cast<uint2*>(dout + i4) = make_uint2(lo, hi);
